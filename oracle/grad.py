@@ -1,0 +1,172 @@
+"""Gradients of the oracle's L1 loss, by two independent routes (FP64).
+
+Test infrastructure only (see the package docstring).
+
+Route 1 re-implements the renderer of oracle.render in torch.float64 on the
+CPU and differentiates it with autograd.  It is written separately from the
+numpy renderer: the chord integral uses the antiderivative literally,
+S(t_out) - S(t_in) (Eq. 7-8), instead of the midpoint form, so agreement of
+the two renderers also checks both integral forms.  Discrete decisions
+(culling, rectangles, depth order, termination) are taken from the numpy key
+path and carry no gradient.
+
+Route 2 is central finite differences of the numpy renderer's loss.
+
+The paper's renderer is differentiable (Sec. 5: a differentiable
+splatting-based renderer) but its adjoint is not described; these routes
+define the reference gradient of the loss with respect to centres, scales,
+raw quaternions, W1, b1, W2, b2 and colours (or colour-MLP weights).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .keys import project_all
+from .render import RenderOptions, depth_order, l1_loss, render_views
+
+PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi")
+
+
+def _rotmat_t(q):
+    q = q / torch.linalg.norm(q, dim=-1, keepdim=True)
+    w, x, y, z = q.unbind(-1)
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
+    ], -2)
+
+
+def _colors_t(params, meta, o):
+    if meta["color_mode"] == 0:
+        return params["colors"]
+    dirv = params["centers"] - o
+    dirv = dirv / torch.linalg.norm(dirv, dim=1, keepdim=True)
+    h = torch.cat([dirv, params["xi"]], 1)
+    vec = params["cmlp"]
+    width, depth = meta["cmlp_width"], meta["cmlp_depth"]
+    dims = [h.shape[1]] + [width] * depth + [3]
+    pos = 0
+    for li, (a, b) in enumerate(zip(dims[:-1], dims[1:])):
+        Wm = vec[:, pos:pos + a * b].reshape(-1, b, a)
+        pos += a * b
+        bb = vec[:, pos:pos + b]
+        pos += b
+        h = torch.einsum("poi,pi->po", Wm, h) + bb
+        if li + 1 < len(dims) - 1:
+            h = torch.relu(h)
+    return torch.sigmoid(h)
+
+
+def render_view_torch(params, meta, cam, opts: RenderOptions = RenderOptions(), proj=None):
+    """Differentiable float64 render of one view (route 1)."""
+    if proj is None:
+        np_scene = {k: (params[k].detach().numpy() if params.get(k) is not None else None)
+                    for k in PARAM_KEYS}
+        proj = project_all(np_scene, cam, 16, 16, opts.z_near)
+    H, W = cam.height, cam.width
+    Rinv = torch.linalg.inv(torch.tensor(np.asarray(cam.R, dtype=np.float64)))
+    tc = torch.tensor(np.asarray(cam.t, dtype=np.float64))
+    o = -Rinv @ tc
+    fx, fy, cx, cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    Rp = _rotmat_t(params["quats"])
+    colors = _colors_t(params, meta, o)
+    om = float(meta["omega0"])
+    img = torch.zeros(H, W, 3, dtype=torch.float64)
+    T = torch.ones(H, W, dtype=torch.float64)
+    done = torch.zeros(H, W, dtype=torch.bool)
+    for p in depth_order(proj):
+        x0, x1, y0, y1 = (int(v) for v in proj["rect"][p])
+        jj, ii = torch.meshgrid(torch.arange(y0, y1 + 1, dtype=torch.float64),
+                                torch.arange(x0, x1 + 1, dtype=torch.float64), indexing="ij")
+        dc = torch.stack([(ii + 0.5 - cx) / fx, (jj + 0.5 - cy) / fy, torch.ones_like(ii)], -1)
+        d = dc @ Rinv.T
+        d = d / torch.linalg.norm(d, dim=-1, keepdim=True)
+        xb, s, R = params["centers"][p], params["scales"][p], Rp[p]
+        op = ((o - xb) @ R) / s
+        dp = (d @ R) / s
+        A = (dp * dp).sum(-1)
+        B = dp @ op
+        Cq = op @ op - 1.0
+        disc = B * B - A * Cq
+        live = ~done[y0:y1 + 1, x0:x1 + 1]
+        hit = (disc > 0) & live
+        if not bool(hit.any()):
+            continue
+        sq = torch.sqrt(torch.where(disc > 0, disc, torch.ones_like(disc)))
+        t_in = (-B - sq) / A
+        t_out = (-B + sq) / A
+        m = torch.max(s)
+        a = (d @ params["w1"][p].T) / m                      # (..., N)
+        c = ((o - xb) @ params["w1"][p].T) / m + params["b1"][p]
+        w2 = params["w2"][p]
+        tiny = a.abs() < 1e-9
+        a_safe = torch.where(tiny, torch.ones_like(a), a)
+
+        def S(t):
+            return (w2 * torch.sin(om * (a_safe * t[..., None] + c)) / (om * a_safe))
+
+        lit = S(t_out) - S(t_in)
+        lim = w2 * torch.cos(om * (a * (0.5 * (t_in + t_out))[..., None] + c)) * (t_out - t_in)[..., None]
+        integral = torch.where(tiny, lim, lit).sum(-1) + params["b2"][p] * (t_out - t_in)
+        alpha = 1.0 - torch.exp(-torch.clamp(integral, min=0.0))
+        alpha = torch.clamp(alpha, max=opts.alpha_max)
+        use = hit
+        if opts.alpha_min > 0:
+            use = use & (alpha.detach() >= opts.alpha_min)
+        alpha = torch.where(use, alpha, torch.zeros_like(alpha))
+        Tb = T[y0:y1 + 1, x0:x1 + 1]
+        img = img.clone()
+        img[y0:y1 + 1, x0:x1 + 1] = img[y0:y1 + 1, x0:x1 + 1] + (alpha * Tb)[..., None] * colors[p]
+        Tn = Tb * (1.0 - alpha)
+        T = T.clone()
+        T[y0:y1 + 1, x0:x1 + 1] = Tn
+        if opts.t_eps > 0:
+            done[y0:y1 + 1, x0:x1 + 1] |= use & (Tn.detach() < opts.t_eps)
+    img = img + T[..., None] * torch.tensor(opts.bg, dtype=torch.float64)
+    return img, T
+
+
+def autograd_loss_and_grads(scene, cams, targets, opts: RenderOptions = RenderOptions()):
+    """Route 1: loss and d loss / d params (numpy float64 arrays)."""
+    meta = dict(color_mode=scene["color_mode"], omega0=scene["omega0"],
+                cmlp_width=scene.get("cmlp_width", 0), cmlp_depth=scene.get("cmlp_depth", 0))
+    params = {}
+    for k in PARAM_KEYS:
+        if scene.get(k) is not None:
+            params[k] = torch.tensor(np.asarray(scene[k], dtype=np.float64), requires_grad=True)
+    total = torch.zeros((), dtype=torch.float64)
+    n = 0
+    images = []
+    for cam, tgt in zip(cams, targets):
+        img, _ = render_view_torch(params, meta, cam, opts)
+        images.append(img.detach().numpy())
+        total = total + (img - torch.tensor(np.asarray(tgt, dtype=np.float64))).abs().sum()
+        n += int(np.asarray(tgt).size)
+    loss = total / n
+    loss.backward()
+    grads = {k: (v.grad.numpy().copy() if v.grad is not None else np.zeros(v.shape))
+             for k, v in params.items()}
+    return float(loss.detach()), grads, images
+
+
+def numpy_loss(scene, cams, targets, opts: RenderOptions = RenderOptions()):
+    """L1 loss of the numpy renderer."""
+    imgs = [r["image"] for r in render_views(scene, cams, opts)]
+    return l1_loss(imgs, targets)[0]
+
+
+def fd_gradient(scene, cams, targets, key, index, rel_step=1e-6, opts: RenderOptions = RenderOptions()):
+    """Route 2: central difference of the numpy loss in one parameter element,
+    step h = rel_step * max(1, |theta|)."""
+    base = np.asarray(scene[key], dtype=np.float64)
+    h = rel_step * max(1.0, abs(float(base[index])))
+    vals = []
+    for sgn in (+1.0, -1.0):
+        arr = base.copy()
+        arr[index] += sgn * h
+        sc = dict(scene)
+        sc[key] = arr
+        vals.append(numpy_loss(sc, cams, targets, opts))
+    return (vals[0] - vals[1]) / (2.0 * h)

@@ -1,0 +1,154 @@
+"""Splatting renderer of the oracle (FP64): images, hit-pair counts and loss.
+
+Test infrastructure only (see the package docstring).
+
+Per view and pixel, the primitives whose bounds cover the pixel are taken in
+ascending (depth bits, index) order (the tiling/sorting readings in
+oracle.keys).  For each one, the ray-ellipsoid intersection gives the chord
+[t_in, t_out]; the exact integral of the primitive's density over the chord
+(Eq. 7-8) gives alpha = 1 - exp(-max(0, integral)) (Eq. 9); the colours are
+blended front to back, C = sum_i c_i alpha_i prod_{j<i} (1 - alpha_j) (Eq. 4).
+
+Readings of what the paper leaves open (3DGS conventions, all switchable):
+  * alpha_max (default 0.99): alpha is clamped to at most alpha_max;
+  * alpha_min (default 0): primitives with alpha < alpha_min are skipped;
+  * early termination: after blending a primitive, a pixel whose
+    transmittance T fell below t_eps (default 1e-4) takes no further
+    primitives (t_eps = 0 disables it);
+  * background: C += T_final * bg, bg = 0 by default;
+  * a (pixel, primitive) pair is a "hit pair" when the ray meets the
+    ellipsoid (disc > 0) and the pixel has not terminated yet; clamped pairs
+    (integral <= 0) count as hits.
+
+The image is computed by looping over primitives in depth order and updating
+the pixels of each primitive's bounding rectangle at once (every hit pixel lies
+in that rectangle).  The loss is the mean absolute error over all pixels,
+channels and views.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from .color import primitive_colors
+from .density import chord_integral
+from .geometry import intersect_ellipsoid, pixel_rays, quat_to_rotmat
+from .keys import project_all
+
+
+@dataclasses.dataclass
+class RenderOptions:
+    z_near: float = 0.2
+    t_eps: float = 1e-4
+    alpha_min: float = 0.0
+    alpha_max: float = 0.99
+    bg: tuple = (0.0, 0.0, 0.0)
+
+
+def primitive(scene, p, R=None):
+    """Primitive p of a scene as the dict the density functions take."""
+    return dict(center=scene["centers"][p], scale=scene["scales"][p],
+                w1=scene["w1"][p], b1=scene["b1"][p], w2=scene["w2"][p],
+                b2=scene["b2"][p], omega0=scene["omega0"],
+                R=quat_to_rotmat(scene["quats"][p]) if R is None else R)
+
+
+def splat_alpha(o, d, prim):
+    """disc and alpha (Eq. 9) of one primitive for rays (o, d); alpha is 0
+    where the ray misses.  Returns (disc, alpha_unclamped_integral, alpha)."""
+    disc, t_in, t_out = intersect_ellipsoid(o, d, prim["center"], prim["scale"], prim["R"])
+    hit = disc > 0
+    integral = np.zeros(disc.shape)
+    if np.any(hit):
+        integral[hit] = chord_integral(o, d[hit], t_in[hit], t_out[hit], prim)
+    alpha = np.where(hit, 1.0 - np.exp(-np.maximum(integral, 0.0)), 0.0)
+    return disc, integral, alpha
+
+
+def depth_order(proj):
+    """Indices of the primitives with a non-empty rectangle, ascending in
+    (depth bits, index)."""
+    ids = np.nonzero(proj["nonempty"])[0]
+    order = np.lexsort((ids, proj["depth_bits"][ids]))
+    return ids[order]
+
+
+def render_view(scene, cam, opts: RenderOptions = RenderOptions(), return_trace=False):
+    """Render one view.  Returns dict(image (H,W,3), T (H,W), hit_pairs int)."""
+    H, W = cam.height, cam.width
+    proj = project_all(scene, cam, 16, 16, opts.z_near)
+    colors = primitive_colors(scene, cam)
+    Rs = quat_to_rotmat(scene["quats"])
+    img = np.zeros((H, W, 3))
+    T = np.ones((H, W))
+    done = np.zeros((H, W), dtype=bool)
+    hit_pairs = 0
+    for p in depth_order(proj):
+        x0, x1, y0, y1 = proj["rect"][p]
+        rows, cols = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+        o, d = pixel_rays(cam, cols, rows)
+        disc, _, alpha = splat_alpha(o, d, primitive(scene, p, Rs[p]))
+        live = ~done[y0:y1 + 1, x0:x1 + 1]
+        hit = (disc > 0) & live
+        hit_pairs += int(hit.sum())
+        alpha = np.minimum(alpha, opts.alpha_max)
+        use = hit & (alpha >= opts.alpha_min) if opts.alpha_min > 0 else hit
+        a = np.where(use, alpha, 0.0)
+        Tb = T[y0:y1 + 1, x0:x1 + 1]
+        img[y0:y1 + 1, x0:x1 + 1] += (a * Tb)[..., None] * colors[p]
+        Tn = Tb * (1.0 - a)
+        T[y0:y1 + 1, x0:x1 + 1] = Tn
+        if opts.t_eps > 0:
+            done[y0:y1 + 1, x0:x1 + 1] |= use & (Tn < opts.t_eps)
+    img += T[..., None] * np.asarray(opts.bg, dtype=np.float64)
+    return dict(image=img, T=T, hit_pairs=hit_pairs)
+
+
+def render_views(scene, cams, opts: RenderOptions = RenderOptions()):
+    return [render_view(scene, c, opts) for c in cams]
+
+
+def render_pixels(scene, cam, cols, rows, opts: RenderOptions = RenderOptions(), proj=None):
+    """Colour and transmittance of individual pixels, each computed on its
+    own from all primitives whose rectangle contains it (for spot checks of
+    images too large to render whole).  Returns (colors (n,3), T (n,), hits (n,))."""
+    if proj is None:
+        proj = project_all(scene, cam, 16, 16, opts.z_near)
+    colors = primitive_colors(scene, cam)
+    order = depth_order(proj)
+    rect = proj["rect"][order]
+    out_c = np.zeros((len(cols), 3))
+    out_t = np.ones(len(cols))
+    out_h = np.zeros(len(cols), dtype=np.int64)
+    for n, (i, j) in enumerate(zip(cols, rows)):
+        sel = order[(rect[:, 0] <= i) & (i <= rect[:, 1]) & (rect[:, 2] <= j) & (j <= rect[:, 3])]
+        o, d = pixel_rays(cam, np.array([i]), np.array([j]))
+        C = np.zeros(3)
+        T = 1.0
+        for p in sel:
+            disc, _, alpha = splat_alpha(o, d, primitive(scene, p))
+            if disc[0] <= 0:
+                continue
+            out_h[n] += 1
+            a = min(alpha[0], opts.alpha_max)
+            if opts.alpha_min > 0 and a < opts.alpha_min:
+                continue
+            C += colors[p] * a * T
+            T *= 1.0 - a
+            if opts.t_eps > 0 and T < opts.t_eps:
+                break
+        out_c[n] = C + T * np.asarray(opts.bg, dtype=np.float64)
+        out_t[n] = T
+    return out_c, out_t, out_h
+
+
+def l1_loss(images, targets):
+    """Mean absolute error over all views, pixels and channels, and its
+    gradient with respect to each image (sign(C - target) / count)."""
+    n = sum(int(np.asarray(t).size) for t in targets)
+    L = sum(float(np.abs(np.asarray(i, dtype=np.float64) - np.asarray(t, dtype=np.float64)).sum())
+            for i, t in zip(images, targets)) / n
+    grads = [np.sign(np.asarray(i, dtype=np.float64) - np.asarray(t, dtype=np.float64)) / n
+             for i, t in zip(images, targets)]
+    return L, grads
