@@ -1,0 +1,223 @@
+/*
+ * snp.h -- C ABI of the splattable-neural-primitive rasterizer for MI355X
+ * (gfx950).
+ *
+ * The library renders primitives made of an ellipsoid bound and a shallow
+ * cosine density MLP (Splat the Net, ICLR 2026, Sec. 3.1, Eq. 5-6): for every
+ * pixel ray and every primitive whose screen bounds cover the pixel it
+ * intersects the ray with the ellipsoid, integrates the density exactly over
+ * the chord (Eq. 7-8), turns the integral into alpha = 1 - exp(-max(0, .))
+ * (Eq. 9) and blends front to back in depth order (Eq. 3-4).  The backward
+ * pass is the exact adjoint of that forward pass for an L1 image loss.
+ *
+ * Conventions shared by every entry point
+ *  - All arrays passed as `const float*` / `float*` are DEVICE pointers,
+ *    owned by the caller, float32, C-contiguous.  `cams` and `cfg` are HOST
+ *    pointers read during the call only.
+ *  - Every call only enqueues work on `stream` (a hipStream_t; 0 = null
+ *    stream).  No call allocates memory, synchronises, or keeps a pointer
+ *    after it returns -- except snp_read_status (synchronises the stream) and
+ *    the snp_graph_* calls (documented there).
+ *  - Arguments are validated on the host before anything is enqueued; an
+ *    invalid call returns SNP_ERR_INVALID and enqueues nothing.
+ *  - Sizes that are only known on the device (the number of tile instances)
+ *    are checked on the device against the workspace capacity; an overflow
+ *    sets a flag that snp_read_status reports (SNP_ERR_CAPACITY); the results
+ *    of that step are then incomplete and must be discarded.
+ *  - Images: the V views are packed one after another, view v as a row-major
+ *    H_v x W_v x 3 block (RGB); transmittances likewise as H_v x W_v.
+ *  - Primitive arrays (P primitives, N hidden units): centers P x 3,
+ *    scales P x 3 (semi-axis lengths, > 0), quats P x 4 (w, x, y, z; need not
+ *    be normalised), w1 P x N x 3, b1 P x N, w2 P x N, b2 P, and either
+ *    colors P x 3 (color_mode 0) or cmlp P x K with xi P x 8 (color_mode 1).
+ */
+#ifndef SNP_H_
+#define SNP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SNP_OK = 0,
+  SNP_ERR_INVALID = 1,     /* bad argument; nothing was enqueued */
+  SNP_ERR_CAPACITY = 2,    /* tile instances exceeded the workspace capacity */
+  SNP_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
+  SNP_ERR_UNSUPPORTED = 4, /* valid but not built (e.g. N outside {4,8,16,32}) */
+  SNP_ERR_RANGE = 5        /* density-MLP phase outside the hardware sine range */
+} snp_status;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point X
+ * has camera coordinates R X + t (R row-major); pixel (i, j) -- column i,
+ * row j -- has its centre at (i + 0.5, j + 0.5) and views the direction
+ * R^-1 ((i + 0.5 - cx)/fx, (j + 0.5 - cy)/fy, 1) from the camera centre
+ * -R^-1 t (Sec. 2.1: rays r(t) = o + t d, t in world length). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+} snp_camera;
+
+/* Rendering options.  Readings of what the paper leaves open:
+ *  n_hidden   N, width of the density MLP (Eq. 6); 4, 8, 16 or 32.
+ *  omega0     frequency boost omega0 of Eq. 6 (multiplies W1 x + b1).
+ *  color_mode 0 = constant RGB per primitive; 1 = per-(primitive, view)
+ *             colour MLP: input [normalize(x_B - o_v), xi_p], cmlp_depth
+ *             ReLU layers of cmlp_width units, sigmoid RGB output; weights
+ *             per primitive layer after layer, each W (out x in) then b.
+ *  tile_w, tile_h, px_per_lane: rasterizer tile shape and pixels per thread;
+ *             supported shapes are listed by snp_supported_tiles().
+ *  z_near     a primitive is culled for a view unless its whole ellipsoid
+ *             lies in front of camera-space z = z_near.
+ *  t_eps      a pixel takes no more primitives once its transmittance fell
+ *             below t_eps (0 disables early termination).
+ *  alpha_min  primitives with alpha < alpha_min are skipped (0 disables).
+ *  alpha_max  alpha is clamped to at most alpha_max (< 1).
+ *  bg         background colour added as T_final * bg.
+ *  persistent 1 = one persistent launch over all (view, tile) work items
+ *             with a device work queue; 0 = one workgroup per tile. */
+typedef struct {
+  int32_t n_hidden;
+  float omega0;
+  int32_t color_mode;
+  int32_t cmlp_width, cmlp_depth;
+  int32_t tile_w, tile_h, px_per_lane;
+  float z_near, t_eps, alpha_min, alpha_max;
+  float bg[3];
+  int32_t persistent;
+} snp_config;
+
+typedef struct {
+  int64_t P;
+  const float *centers, *scales, *quats, *w1, *b1, *w2, *b2;
+  const float *colors; /* color_mode 0, else NULL */
+  const float *cmlp;   /* color_mode 1, else NULL */
+  const float *xi;     /* color_mode 1, else NULL */
+} snp_prims;
+
+/* Gradient outputs, same shapes as the parameters.  The backward ADDS into
+ * them (the caller zeroes them first); NULL skips a tensor (gradients of xi
+ * are only produced when non-NULL). */
+typedef struct {
+  float *centers, *scales, *quats, *w1, *b1, *w2, *b2, *colors, *cmlp, *xi;
+} snp_grads;
+
+/* Byte offsets of the internal arrays inside a workspace (for inspection by
+ * tests and tools).  All offsets are from the workspace base pointer. */
+typedef struct {
+  size_t bytes;           /* total workspace size */
+  size_t cams;            /* per-view device constants */
+  size_t table;           /* per-primitive density table, P x table_stride floats */
+  size_t records;         /* per-(view, primitive) records, V*P x 24 floats */
+  size_t rects;           /* per-(view, primitive) pixel rectangles, int32 x0,x1,y0,y1 */
+  size_t depth_bits;      /* per-(view, primitive) uint32 depth key (0 = culled) */
+  size_t tile_counts;     /* per-(view, primitive) uint32 number of tiles */
+  size_t offsets;         /* per-(view, primitive) uint32 exclusive scan of tile_counts */
+  size_t keys;            /* uint64 sorted keys (tile << 31 | depth bits), capacity entries */
+  size_t values;          /* uint32 sorted primitive ids, capacity entries */
+  size_t ranges;          /* per global tile uint32 [start, end) */
+  size_t counters;        /* uint64: [0] instances, [1] overflow flag, [2] hit pairs, [3] range flag */
+  size_t gview;           /* backward: per-(view, primitive) gradient records */
+  size_t gtable;          /* backward: per-primitive table gradients */
+  size_t loss;            /* loss partial sums (float64) */
+  int64_t capacity;       /* tile-instance capacity */
+  int32_t table_stride;   /* floats per table row */
+  int32_t total_tiles;    /* tiles over all views */
+} snp_layout;
+
+/* Size and layout of the workspace for P primitives seen by V cameras with
+ * room for `max_instances` (tile, primitive) instances.  The workspace must
+ * be 256-byte aligned, at least layout.bytes long, and is reused by every
+ * later call of the same step.  Every call that takes a workspace also takes
+ * this layout; it is recomputed from the call's arguments and must match
+ * (else SNP_ERR_INVALID). */
+snp_status snp_workspace_layout(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams,
+                                int64_t max_instances, snp_layout* out);
+
+/* Per-(primitive, view) preprocessing (Sec. 3.1-3.2 quantities that do not
+ * depend on the pixel): near culling, exact screen bounds of the projected
+ * ellipsoid, depth key, tile counts, the ray-frame coefficients the
+ * rasterizer evaluates per pixel, the per-primitive phase table of the
+ * density MLP, and the colour of every (primitive, view).  The culling,
+ * bounds and depth are computed in float64 in a fixed operation order. */
+snp_status snp_preprocess(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                          void* ws, const snp_layout* layout, hipStream_t stream);
+
+/* Tile binning: exclusive scan of the tile counts and one (key, value)
+ * instance per covered tile, key = (global tile id << 31) | depth bits,
+ * value = primitive id; instance count and overflow flag on the device. */
+snp_status snp_bin(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
+                   const snp_layout* layout, hipStream_t stream);
+
+/* Stable device radix sort of the instances by key (so equal keys keep
+ * primitive order) and the [start, end) range of every global tile. */
+snp_status snp_sort(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
+                    const snp_layout* layout, hipStream_t stream);
+
+/* Forward rasterizer (Eq. 3-4, 7-9).  images: sum_v H_v W_v 3 floats;
+ * final_T: sum_v H_v W_v floats.  count_pairs != 0 also counts the hit pairs
+ * (pixel, primitive with the ray meeting the ellipsoid, pixel not yet
+ * terminated) into the workspace counter [2]. */
+snp_status snp_render_forward(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                              void* ws, const snp_layout* layout, float* images, float* final_T, int32_t count_pairs,
+                              hipStream_t stream);
+
+/* L1 loss: loss_out[0] (device double) = sum |images - targets| / n_norm and
+ * dL_dimages = sign(images - targets) / n_norm.  n_norm is the element count
+ * the mean is taken over (all views of the step). */
+snp_status snp_loss_l1(const snp_config* cfg, int32_t V, const snp_camera* cams, const float* images,
+                       const float* targets, double n_norm, void* ws, const snp_layout* layout, double* loss_out,
+                       float* dL_dimages, hipStream_t stream);
+
+/* Backward: gradients of the loss with respect to every primitive parameter
+ * given dL/dimages, the forward's images and the workspace the forward left.
+ * The traversal recomputes transmittance in forward order; nothing per pixel
+ * or per pair is stored between the passes.  Adds into `grads`. */
+snp_status snp_render_backward(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                               void* ws, const snp_layout* layout, const float* images, const float* dL_dimages,
+                               const snp_grads* grads, hipStream_t stream);
+
+/* One whole training step: zero `grads`, preprocess, bin, sort, forward,
+ * L1 loss against `targets` (mean over n_norm elements), backward. */
+snp_status snp_step(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams, void* ws,
+                    const snp_layout* layout, float* images, float* final_T, const float* targets, double n_norm,
+                    double* loss_out, float* dL_dimages, const snp_grads* grads, hipStream_t stream);
+
+/* Captures snp_step with these exact arguments into a HIP graph (the
+ * pointers must stay valid while the graph lives) and returns an opaque
+ * handle.  This call synchronises `stream`.  snp_graph_launch replays it on
+ * `stream`; snp_graph_destroy frees it. */
+snp_status snp_graph_create(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                            void* ws, const snp_layout* layout, float* images, float* final_T, const float* targets,
+                            double n_norm, double* loss_out, float* dL_dimages, const snp_grads* grads,
+                            hipStream_t stream, void** graph_out);
+snp_status snp_graph_launch(void* graph, hipStream_t stream);
+snp_status snp_graph_destroy(void* graph);
+
+/* Synchronises `stream`, then reads the instance count and the flags.
+ * Returns SNP_ERR_CAPACITY if the last binning overflowed and SNP_ERR_RANGE if
+ * a density-MLP phase exceeded the supported range. */
+snp_status snp_read_status(void* ws, const snp_layout* layout, int64_t* instances_out, int64_t* hit_pairs_out,
+                           hipStream_t stream);
+
+/* Tile shapes the rasterizer is built for: writes up to `max` triples
+ * (tile_w, tile_h, px_per_lane) and returns how many exist. */
+int32_t snp_supported_tiles(int32_t* triples, int32_t max);
+
+const char* snp_status_string(snp_status s);
+
+/* Device self-test of the wave-wide reduction the backward uses: `in` and
+ * `out` are device arrays of 64 * waves floats; out[i] = sum of in over the
+ * wave of i.  Enqueues on `stream`. */
+snp_status snp_selftest_wave_sum(const float* in, float* out, int32_t waves, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNP_H_ */

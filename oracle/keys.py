@@ -25,7 +25,8 @@ The readings used here:
   * Tiles.  Row-major tiles of tile_w x tile_h pixels; a primitive is listed
     in every tile its pixel rectangle touches.  The global tile id of view v
     is the number of tiles of views 0..v-1 plus the local id, and the sort key
-    of an instance is (global tile id << 32) | depth bits.
+    of an instance is (global tile id << 31) | depth bits (the depth is
+    positive, so its sign bit is zero and is dropped).
 
 The key path is evaluated in float64 with one fixed order of correctly
 rounded operations (no fused multiply-add; each numpy elementwise operation
@@ -172,7 +173,7 @@ def sorted_instances(lists):
     keys, vals = [], []
     for gid, lst in enumerate(lists):
         for bits, p in lst:
-            keys.append((gid << 32) | bits)
+            keys.append((gid << 31) | bits)
             vals.append(p)
     return np.array(keys, dtype=np.uint64), np.array(vals, dtype=np.uint32)
 

@@ -1,0 +1,99 @@
+"""ctypes binding of libsnp.so (include/snp.h): struct mirrors and function
+prototypes.  Argument marshalling only; every computation runs in the HIP
+library.  Loading fails loudly if the library has not been built."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsnp.so")
+
+SNP_OK, SNP_ERR_INVALID, SNP_ERR_CAPACITY, SNP_ERR_HIP, SNP_ERR_UNSUPPORTED, SNP_ERR_RANGE = range(6)
+
+
+class SnpCamera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3)]
+
+
+class SnpConfig(C.Structure):
+    _fields_ = [("n_hidden", C.c_int32), ("omega0", C.c_float), ("color_mode", C.c_int32),
+                ("cmlp_width", C.c_int32), ("cmlp_depth", C.c_int32), ("tile_w", C.c_int32),
+                ("tile_h", C.c_int32), ("px_per_lane", C.c_int32), ("z_near", C.c_float),
+                ("t_eps", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
+                ("bg", C.c_float * 3), ("persistent", C.c_int32)]
+
+
+class SnpPrims(C.Structure):
+    _fields_ = [("P", C.c_int64)] + [(k, C.c_void_p) for k in
+                                     ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi")]
+
+
+class SnpGrads(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in
+                ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi")]
+
+
+class SnpLayout(C.Structure):
+    _fields_ = [(k, C.c_size_t) for k in
+                ("bytes", "cams", "table", "records", "rects", "depth_bits", "tile_counts", "offsets", "keys",
+                 "values", "ranges", "counters", "gview", "gtable", "loss")] + \
+               [("capacity", C.c_int64), ("table_stride", C.c_int32), ("total_tiles", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_08491_amd.build` "
+                           "(there is no fallback path)")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D, VP = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    cfg, cams, prims, grads, lay = P(SnpConfig), P(SnpCamera), P(SnpPrims), P(SnpGrads), P(SnpLayout)
+    protos = {
+        "snp_workspace_layout": [cfg, I64, I32, cams, I64, lay],
+        "snp_preprocess": [cfg, prims, I32, cams, VP, lay, VP],
+        "snp_bin": [cfg, I64, I32, cams, VP, lay, VP],
+        "snp_sort": [cfg, I64, I32, cams, VP, lay, VP],
+        "snp_render_forward": [cfg, prims, I32, cams, VP, lay, VP, VP, I32, VP],
+        "snp_loss_l1": [cfg, I32, cams, VP, VP, D, VP, lay, VP, VP, VP],
+        "snp_render_backward": [cfg, prims, I32, cams, VP, lay, VP, VP, grads, VP],
+        "snp_step": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, D, VP, VP, grads, VP],
+        "snp_graph_create": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, D, VP, VP, grads, VP, P(VP)],
+        "snp_graph_launch": [VP, VP],
+        "snp_graph_destroy": [VP],
+        "snp_read_status": [VP, lay, P(I64), P(I64), VP],
+        "snp_supported_tiles": [P(I32), I32],
+        "snp_selftest_wave_sum": [VP, VP, I32, VP],
+    }
+    for name, args in protos.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+    L.snp_status_string.argtypes = [C.c_int32]
+    L.snp_status_string.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+EXPORTED = ["snp_workspace_layout", "snp_preprocess", "snp_bin", "snp_sort", "snp_render_forward", "snp_loss_l1",
+            "snp_render_backward", "snp_step", "snp_graph_create", "snp_graph_launch", "snp_graph_destroy",
+            "snp_read_status", "snp_supported_tiles", "snp_status_string", "snp_selftest_wave_sum"]
+
+
+class SnpError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().snp_status_string(code).decode()
+        super().__init__(f"{where}: {msg} (status {code})")
+
+
+def check(code, where):
+    if code != SNP_OK:
+        raise SnpError(code, where)

@@ -1,0 +1,556 @@
+// C ABI of libsnp: argument validation, workspace layout and the sequence of
+// kernel launches of each stage.  No entry point allocates device memory;
+// everything lives in the caller's workspace.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "snp_internal.h"
+
+namespace snp {
+
+static inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Plan {
+  snp_layout L;
+  size_t scan_scratch, sort_scratch, loss_partials, cams_bytes;
+  size_t keys_alt, values_alt;
+  std::vector<int32_t> tile_base;
+  std::vector<int64_t> pix_base;
+  int64_t total_pixels;
+  int key_bits;
+};
+
+static bool valid_n(int n) { return n == 4 || n == 8 || n == 16 || n == 32; }
+
+static snp_status check_cfg(const snp_config* cfg) {
+  if (!cfg) return SNP_ERR_INVALID;
+  if (!valid_n(cfg->n_hidden)) return SNP_ERR_UNSUPPORTED;
+  if (!(cfg->omega0 > 0.f) || !std::isfinite(cfg->omega0)) return SNP_ERR_INVALID;
+  if (cfg->color_mode != 0 && cfg->color_mode != 1) return SNP_ERR_INVALID;
+  if (cfg->color_mode == 1 && !cmlp_supported(cfg->cmlp_width, cfg->cmlp_depth)) return SNP_ERR_UNSUPPORTED;
+  if (!tile_supported(cfg->tile_w, cfg->tile_h, cfg->px_per_lane)) return SNP_ERR_UNSUPPORTED;
+  if (!(cfg->z_near > 0.f)) return SNP_ERR_INVALID;
+  if (!(cfg->t_eps >= 0.f && cfg->t_eps < 1.f)) return SNP_ERR_INVALID;
+  if (!(cfg->alpha_min >= 0.f && cfg->alpha_max > 0.f && cfg->alpha_max < 1.f)) return SNP_ERR_INVALID;
+  if (cfg->persistent != 0 && cfg->persistent != 1) return SNP_ERR_INVALID;
+  return SNP_OK;
+}
+
+static snp_status check_cams(int32_t V, const snp_camera* cams) {
+  if (V <= 0 || V > 4096 || !cams) return SNP_ERR_INVALID;
+  for (int v = 0; v < V; ++v) {
+    const snp_camera& c = cams[v];
+    if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384) return SNP_ERR_INVALID;
+    if (!(c.fx > 0.f) || !(c.fy > 0.f)) return SNP_ERR_INVALID;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(c.R[k])) return SNP_ERR_INVALID;
+    const double det = (double)c.R[0] * ((double)c.R[4] * c.R[8] - (double)c.R[5] * c.R[7]) -
+                       (double)c.R[1] * ((double)c.R[3] * c.R[8] - (double)c.R[5] * c.R[6]) +
+                       (double)c.R[2] * ((double)c.R[3] * c.R[7] - (double)c.R[4] * c.R[6]);
+    if (!(std::fabs(det) > 1e-6)) return SNP_ERR_INVALID;
+  }
+  return SNP_OK;
+}
+
+static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, int64_t cap,
+                            Plan* pl) {
+  snp_status s = check_cfg(cfg);
+  if (s != SNP_OK) return s;
+  s = check_cams(V, cams);
+  if (s != SNP_OK) return s;
+  if (P <= 0 || P > ((int64_t)1 << 31) - 1) return SNP_ERR_INVALID;
+  if ((int64_t)V * P > ((int64_t)1 << 33)) return SNP_ERR_INVALID;
+  if (cap <= 0 || cap > ((int64_t)1 << 31) - 1) return SNP_ERR_INVALID;
+  pl->tile_base.resize(V);
+  pl->pix_base.resize(V);
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < V; ++v) {
+    pl->tile_base[v] = (int32_t)tiles;
+    pl->pix_base[v] = pix;
+    tiles += (int64_t)((cams[v].width + cfg->tile_w - 1) / cfg->tile_w) * ((cams[v].height + cfg->tile_h - 1) / cfg->tile_h);
+    pix += (int64_t)cams[v].width * cams[v].height;
+  }
+  if (tiles >= ((int64_t)1 << 30)) return SNP_ERR_INVALID;
+  pl->total_pixels = pix;
+  int tb = 1;
+  while (((int64_t)1 << tb) < tiles) ++tb;
+  pl->key_bits = 31 + tb;
+  const int N = cfg->n_hidden;
+  const int TS = table_stride(N);
+  const int64_t VP = (int64_t)V * P;
+  snp_layout& L = pl->L;
+  std::memset(&L, 0, sizeof(L));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.counters = take(sizeof(unsigned long long) * CNT_COUNT);
+  L.loss = take(loss_scratch_bytes());
+  pl->loss_partials = L.loss;
+  L.cams = take(sizeof(CamDev) * (size_t)V);
+  L.table = take(sizeof(float) * (size_t)P * TS);
+  L.records = take(sizeof(float) * (size_t)VP * kRecFloats);
+  L.rects = take(sizeof(int32_t) * 4 * (size_t)VP);
+  L.depth_bits = take(sizeof(uint32_t) * (size_t)VP);
+  L.tile_counts = take(sizeof(uint32_t) * (size_t)VP);
+  L.offsets = take(sizeof(uint32_t) * (size_t)VP);
+  pl->scan_scratch = take(scan_scratch_bytes(VP));
+  L.keys = take(sizeof(unsigned long long) * (size_t)cap);
+  pl->keys_alt = take(sizeof(unsigned long long) * (size_t)cap);
+  L.values = take(sizeof(uint32_t) * (size_t)cap);
+  pl->values_alt = take(sizeof(uint32_t) * (size_t)cap);
+  pl->sort_scratch = take(sort_scratch_bytes(cap));
+  L.ranges = take(sizeof(uint32_t) * 2 * (size_t)tiles);
+  L.gview = take(sizeof(float) * (size_t)VP * kGViewFloats);
+  L.gtable = take(sizeof(float) * (size_t)P * TS);
+  L.bytes = off;
+  L.capacity = cap;
+  L.table_stride = TS;
+  L.total_tiles = (int32_t)tiles;
+  return SNP_OK;
+}
+
+static snp_status check_ws(const Plan& pl, void* ws, size_t ws_bytes) {
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0) return SNP_ERR_INVALID;
+  if (ws_bytes < pl.L.bytes) return SNP_ERR_INVALID;
+  return SNP_OK;
+}
+
+static snp_status check_prims(const snp_config* cfg, const snp_prims* pr) {
+  if (!pr || pr->P <= 0) return SNP_ERR_INVALID;
+  if (!pr->centers || !pr->scales || !pr->quats || !pr->w1 || !pr->b1 || !pr->w2 || !pr->b2) return SNP_ERR_INVALID;
+  if (cfg->color_mode == 0 && !pr->colors) return SNP_ERR_INVALID;
+  if (cfg->color_mode == 1 && (!pr->cmlp || !pr->xi)) return SNP_ERR_INVALID;
+  return SNP_OK;
+}
+
+#define SNP_HIP(x)                          \
+  do {                                      \
+    if ((x) != hipSuccess) return SNP_ERR_HIP; \
+  } while (0)
+
+template <typename T>
+static T* wsp(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int32_t V, const snp_camera* cams,
+                                const Plan& pl, void* ws, hipStream_t st) {
+  const snp_layout& L = pl.L;
+  unsigned long long* counters = wsp<unsigned long long>(ws, L.counters);
+  CamDev* cd = wsp<CamDev>(ws, L.cams);
+  SNP_HIP(zero_counters(counters, CNT_COUNT, st));
+  for (int v0 = 0; v0 < V; v0 += kMaxCamsPerChunk) {
+    CamChunk ch;
+    std::memset(&ch, 0, sizeof(ch));
+    ch.first = v0;
+    ch.count = std::min(kMaxCamsPerChunk, V - v0);
+    ch.tile_w = cfg->tile_w;
+    ch.tile_h = cfg->tile_h;
+    for (int i = 0; i < ch.count; ++i) {
+      ch.cam[i] = cams[v0 + i];
+      ch.tile_base[i] = pl.tile_base[v0 + i];
+      ch.pix_base[i] = pl.pix_base[v0 + i];
+    }
+    SNP_HIP(launch_setup_cams(ch, cd, st));
+  }
+  SNP_HIP(launch_prim_table(cfg->n_hidden, pr->P, cfg->omega0, *pr, wsp<float>(ws, L.table), counters, st));
+  ViewArgs va;
+  va.P = pr->P;
+  va.V = V;
+  va.z_near = cfg->z_near;
+  va.color_mode = cfg->color_mode;
+  va.centers = pr->centers;
+  va.scales = pr->scales;
+  va.quats = pr->quats;
+  va.colors = pr->colors;
+  va.cams = cd;
+  va.records = wsp<float>(ws, L.records);
+  va.rects = wsp<int32_t>(ws, L.rects);
+  va.depth_bits = wsp<uint32_t>(ws, L.depth_bits);
+  va.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
+  SNP_HIP(launch_preprocess_views(va, st));
+  if (cfg->color_mode == 1) {
+    CmlpArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.P = pr->P;
+    ca.V = V;
+    ca.centers = pr->centers;
+    ca.xi = pr->xi;
+    ca.cmlp = pr->cmlp;
+    ca.cams = cd;
+    ca.tile_counts = va.tile_counts;
+    ca.records = va.records;
+    SNP_HIP(launch_cmlp_fwd(cfg->cmlp_width, cfg->cmlp_depth, ca, st));
+  }
+  return SNP_OK;
+}
+
+static snp_status do_bin(const snp_config* cfg, int64_t P, int32_t V, const Plan& pl, void* ws, hipStream_t st) {
+  const snp_layout& L = pl.L;
+  unsigned long long* counters = wsp<unsigned long long>(ws, L.counters);
+  const int64_t VP = (int64_t)V * P;
+  SNP_HIP(scan_exclusive_u32(wsp<uint32_t>(ws, L.tile_counts), wsp<uint32_t>(ws, L.offsets), VP,
+                             wsp<void>(ws, pl.scan_scratch), reinterpret_cast<uint64_t*>(counters + CNT_INSTANCES), st));
+  const bool odd = radix_passes(pl.key_bits) % 2 == 1;
+  EmitArgs ea;
+  ea.P = P;
+  ea.V = V;
+  ea.capacity = L.capacity;
+  ea.cams = wsp<CamDev>(ws, L.cams);
+  ea.rects = wsp<int32_t>(ws, L.rects);
+  ea.depth_bits = wsp<uint32_t>(ws, L.depth_bits);
+  ea.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
+  ea.offsets = wsp<uint32_t>(ws, L.offsets);
+  ea.keys = wsp<unsigned long long>(ws, odd ? pl.keys_alt : L.keys);
+  ea.values = wsp<uint32_t>(ws, odd ? pl.values_alt : L.values);
+  SNP_HIP(launch_emit(ea, counters, st));
+  (void)cfg;
+  return SNP_OK;
+}
+
+static snp_status do_sort(const Plan& pl, void* ws, hipStream_t st) {
+  const snp_layout& L = pl.L;
+  unsigned long long* counters = wsp<unsigned long long>(ws, L.counters);
+  const bool odd = radix_passes(pl.key_bits) % 2 == 1;
+  unsigned long long* k_main = wsp<unsigned long long>(ws, L.keys);
+  unsigned long long* k_alt = wsp<unsigned long long>(ws, pl.keys_alt);
+  uint32_t* v_main = wsp<uint32_t>(ws, L.values);
+  uint32_t* v_alt = wsp<uint32_t>(ws, pl.values_alt);
+  if (odd)
+    SNP_HIP(radix_sort(k_alt, v_alt, k_main, v_main, L.capacity, counters, pl.key_bits, wsp<void>(ws, pl.sort_scratch), st));
+  else
+    SNP_HIP(radix_sort(k_main, v_main, k_alt, v_alt, L.capacity, counters, pl.key_bits, wsp<void>(ws, pl.sort_scratch), st));
+  SNP_HIP(launch_ranges(k_main, counters, L.capacity, wsp<uint32_t>(ws, L.ranges), L.total_tiles, st));
+  return SNP_OK;
+}
+
+static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const Plan& pl, void* ws) {
+  const snp_layout& L = pl.L;
+  RasterArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.cams = wsp<CamDev>(ws, L.cams);
+  a.V = V;
+  a.P = P;
+  a.total_tiles = L.total_tiles;
+  a.table = wsp<float>(ws, L.table);
+  a.records = wsp<float>(ws, L.records);
+  a.values = wsp<uint32_t>(ws, L.values);
+  a.ranges = wsp<uint32_t>(ws, L.ranges);
+  a.gview = wsp<float>(ws, L.gview);
+  a.gtable = wsp<float>(ws, L.gtable);
+  a.counters = wsp<unsigned long long>(ws, L.counters);
+  a.t_eps = cfg->t_eps;
+  a.alpha_min = cfg->alpha_min;
+  a.alpha_max = cfg->alpha_max;
+  a.bg0 = cfg->bg[0];
+  a.bg1 = cfg->bg[1];
+  a.bg2 = cfg->bg[2];
+  return a;
+}
+
+static snp_status do_forward(const snp_config* cfg, int64_t P, int32_t V, const Plan& pl, void* ws, float* images,
+                             float* final_T, int count, hipStream_t st) {
+  RasterArgs a = raster_args(cfg, P, V, pl, ws);
+  a.images = images;
+  a.final_T = final_T;
+  if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_FWD, st));
+  SNP_HIP(launch_render_fwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0,
+                            count != 0, a, st));
+  return SNP_OK;
+}
+
+static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_t V, const Plan& pl, void* ws,
+                              const float* images, const float* dL, const snp_grads* g, hipStream_t st) {
+  const snp_layout& L = pl.L;
+  const int64_t P = pr->P;
+  RasterArgs a = raster_args(cfg, P, V, pl, ws);
+  a.images_in = images;
+  a.dL = dL;
+  SNP_HIP(zero_f32(a.gview, (int64_t)V * P * kGViewFloats, st));
+  SNP_HIP(zero_f32(a.gtable, P * (int64_t)L.table_stride, st));
+  if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_BWD, st));
+  SNP_HIP(launch_render_bwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0, a, st));
+  if (cfg->color_mode == 1) {
+    CmlpArgs ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.P = P;
+    ca.V = V;
+    ca.centers = pr->centers;
+    ca.xi = pr->xi;
+    ca.cmlp = pr->cmlp;
+    ca.cams = a.cams;
+    ca.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
+    ca.records = wsp<float>(ws, L.records);
+    ca.gview = a.gview;
+    ca.g_cmlp = g->cmlp;
+    ca.g_xi = g->xi;
+    if (g->cmlp) SNP_HIP(launch_cmlp_bwd(cfg->cmlp_width, cfg->cmlp_depth, ca, st));
+  }
+  PreBwdArgs pa;
+  pa.P = P;
+  pa.V = V;
+  pa.N = cfg->n_hidden;
+  pa.color_mode = cfg->color_mode;
+  pa.omega0 = cfg->omega0;
+  pa.centers = pr->centers;
+  pa.scales = pr->scales;
+  pa.quats = pr->quats;
+  pa.w1 = pr->w1;
+  pa.cams = a.cams;
+  pa.records = wsp<float>(ws, L.records);
+  pa.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
+  pa.gview = a.gview;
+  pa.gtable = a.gtable;
+  pa.g = *g;
+  SNP_HIP(launch_preprocess_bwd(pa, st));
+  return SNP_OK;
+}
+
+static snp_status zero_grads(const snp_config* cfg, int64_t P, const snp_grads* g, hipStream_t st) {
+  const int64_t N = cfg->n_hidden;
+  SNP_HIP(zero_f32(g->centers, 3 * P, st));
+  SNP_HIP(zero_f32(g->scales, 3 * P, st));
+  SNP_HIP(zero_f32(g->quats, 4 * P, st));
+  SNP_HIP(zero_f32(g->w1, 3 * N * P, st));
+  SNP_HIP(zero_f32(g->b1, N * P, st));
+  SNP_HIP(zero_f32(g->w2, N * P, st));
+  SNP_HIP(zero_f32(g->b2, P, st));
+  if (cfg->color_mode == 0) SNP_HIP(zero_f32(g->colors, 3 * P, st));
+  if (cfg->color_mode == 1) {
+    SNP_HIP(zero_f32(g->cmlp, (int64_t)cmlp_param_count(cfg->cmlp_width, cfg->cmlp_depth) * P, st));
+    SNP_HIP(zero_f32(g->xi, (int64_t)kXiDim * P, st));
+  }
+  return SNP_OK;
+}
+
+struct GraphHandle {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+}  // namespace snp
+
+using namespace snp;
+
+#define SNP_TRY(x)                  \
+  do {                              \
+    snp_status s_ = (x);            \
+    if (s_ != SNP_OK) return s_;    \
+  } while (0)
+
+extern "C" {
+
+snp_status snp_workspace_layout(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams,
+                                int64_t max_instances, snp_layout* out) {
+  if (!out) return SNP_ERR_INVALID;
+  Plan pl;
+  SNP_TRY(make_plan(cfg, P, V, cams, max_instances, &pl));
+  *out = pl.L;
+  return SNP_OK;
+}
+
+static bool same_layout(const snp_layout& a, const snp_layout& b) {
+  return a.bytes == b.bytes && a.cams == b.cams && a.table == b.table && a.records == b.records &&
+         a.rects == b.rects && a.depth_bits == b.depth_bits && a.tile_counts == b.tile_counts &&
+         a.offsets == b.offsets && a.keys == b.keys && a.values == b.values && a.ranges == b.ranges &&
+         a.counters == b.counters && a.gview == b.gview && a.gtable == b.gtable && a.loss == b.loss &&
+         a.capacity == b.capacity && a.table_stride == b.table_stride && a.total_tiles == b.total_tiles;
+}
+
+// Rebuilds the plan of a call from its arguments and checks it against the
+// caller's layout and workspace.
+static snp_status plan_for(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
+                           const snp_layout* layout, Plan* pl) {
+  if (!layout) return SNP_ERR_INVALID;
+  SNP_TRY(make_plan(cfg, P, V, cams, layout->capacity, pl));
+  if (!same_layout(pl->L, *layout)) return SNP_ERR_INVALID;
+  return check_ws(*pl, ws, layout->bytes);
+}
+
+snp_status snp_preprocess(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams, void* ws,
+                          const snp_layout* layout, hipStream_t stream) {
+  if (!cfg || !prims) return SNP_ERR_INVALID;
+  Plan pl;
+  SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
+  SNP_TRY(check_prims(cfg, prims));
+  return do_preprocess(cfg, prims, V, cams, pl, ws, stream);
+}
+
+snp_status snp_bin(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
+                   const snp_layout* layout, hipStream_t stream) {
+  Plan pl;
+  SNP_TRY(plan_for(cfg, P, V, cams, ws, layout, &pl));
+  return do_bin(cfg, P, V, pl, ws, stream);
+}
+
+snp_status snp_sort(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
+                    const snp_layout* layout, hipStream_t stream) {
+  Plan pl;
+  SNP_TRY(plan_for(cfg, P, V, cams, ws, layout, &pl));
+  return do_sort(pl, ws, stream);
+}
+
+snp_status snp_render_forward(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                              void* ws, const snp_layout* layout, float* images, float* final_T, int32_t count_pairs,
+                              hipStream_t stream) {
+  if (!cfg || !prims || !images || !final_T) return SNP_ERR_INVALID;
+  Plan pl;
+  SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
+  SNP_TRY(check_prims(cfg, prims));
+  return do_forward(cfg, prims->P, V, pl, ws, images, final_T, count_pairs, stream);
+}
+
+static snp_status do_loss(const Plan& pl, const float* images, const float* targets, double n_norm, void* ws,
+                          double* loss_out, float* dL, hipStream_t st) {
+  SNP_HIP(launch_l1(images, targets, 3 * pl.total_pixels, n_norm, dL, wsp<double>(ws, pl.L.loss), loss_out, st));
+  return SNP_OK;
+}
+
+snp_status snp_loss_l1(const snp_config* cfg, int32_t V, const snp_camera* cams, const float* images,
+                       const float* targets, double n_norm, void* ws, const snp_layout* layout, double* loss_out,
+                       float* dL_dimages, hipStream_t stream) {
+  if (!images || !targets || !loss_out || !dL_dimages || !(n_norm > 0.0) || !layout) return SNP_ERR_INVALID;
+  SNP_TRY(check_cfg(cfg));
+  SNP_TRY(check_cams(V, cams));
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 || layout->loss + loss_scratch_bytes() > layout->bytes)
+    return SNP_ERR_INVALID;
+  Plan pl;
+  pl.L = *layout;
+  pl.total_pixels = 0;
+  for (int v = 0; v < V; ++v) pl.total_pixels += (int64_t)cams[v].width * cams[v].height;
+  return do_loss(pl, images, targets, n_norm, ws, loss_out, dL_dimages, stream);
+}
+
+snp_status snp_render_backward(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                               void* ws, const snp_layout* layout, const float* images, const float* dL_dimages,
+                               const snp_grads* grads, hipStream_t stream) {
+  if (!cfg || !prims || !images || !dL_dimages || !grads) return SNP_ERR_INVALID;
+  Plan pl;
+  SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
+  SNP_TRY(check_prims(cfg, prims));
+  return do_backward(cfg, prims, V, pl, ws, images, dL_dimages, grads, stream);
+}
+
+static snp_status do_step(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                          const Plan& pl, void* ws, float* images, float* final_T, const float* targets,
+                          double n_norm, double* loss_out, float* dL, const snp_grads* grads, hipStream_t st) {
+  SNP_TRY(zero_grads(cfg, prims->P, grads, st));
+  SNP_TRY(do_preprocess(cfg, prims, V, cams, pl, ws, st));
+  SNP_TRY(do_bin(cfg, prims->P, V, pl, ws, st));
+  SNP_TRY(do_sort(pl, ws, st));
+  SNP_TRY(do_forward(cfg, prims->P, V, pl, ws, images, final_T, 0, st));
+  SNP_TRY(do_loss(pl, images, targets, n_norm, ws, loss_out, dL, st));
+  SNP_TRY(do_backward(cfg, prims, V, pl, ws, images, dL, grads, st));
+  return SNP_OK;
+}
+
+static snp_status check_step_args(const snp_config* cfg, const snp_prims* prims, float* images, float* final_T,
+                                  const float* targets, double n_norm, double* loss_out, float* dL,
+                                  const snp_grads* grads) {
+  if (!cfg || !prims || !images || !final_T || !targets || !loss_out || !dL || !grads || !(n_norm > 0.0))
+    return SNP_ERR_INVALID;
+  return check_prims(cfg, prims);
+}
+
+snp_status snp_step(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams, void* ws,
+                    const snp_layout* layout, float* images, float* final_T, const float* targets, double n_norm,
+                    double* loss_out, float* dL_dimages, const snp_grads* grads, hipStream_t stream) {
+  SNP_TRY(check_step_args(cfg, prims, images, final_T, targets, n_norm, loss_out, dL_dimages, grads));
+  Plan pl;
+  SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
+  return do_step(cfg, prims, V, cams, pl, ws, images, final_T, targets, n_norm, loss_out, dL_dimages, grads, stream);
+}
+
+snp_status snp_graph_create(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                            void* ws, const snp_layout* layout, float* images, float* final_T, const float* targets,
+                            double n_norm, double* loss_out, float* dL_dimages, const snp_grads* grads,
+                            hipStream_t stream, void** graph_out) {
+  if (!graph_out) return SNP_ERR_INVALID;
+  SNP_TRY(check_step_args(cfg, prims, images, final_T, targets, n_norm, loss_out, dL_dimages, grads));
+  Plan pl;
+  SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
+  SNP_HIP(hipStreamSynchronize(stream));
+  hipStream_t cs;
+  SNP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  GraphHandle* h = new GraphHandle();
+  snp_status s = SNP_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    s = SNP_ERR_HIP;
+  } else {
+    s = do_step(cfg, prims, V, cams, pl, ws, images, final_T, targets, n_norm, loss_out, dL_dimages, grads, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (s == SNP_OK && e != hipSuccess) s = SNP_ERR_HIP;
+    if (s == SNP_OK) {
+      h->graph = g;
+      if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) s = SNP_ERR_HIP;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (s != SNP_OK) {
+    delete h;
+    return s;
+  }
+  *graph_out = h;
+  return SNP_OK;
+}
+
+snp_status snp_graph_launch(void* graph, hipStream_t stream) {
+  if (!graph) return SNP_ERR_INVALID;
+  GraphHandle* h = reinterpret_cast<GraphHandle*>(graph);
+  SNP_HIP(hipGraphLaunch(h->exec, stream));
+  return SNP_OK;
+}
+
+snp_status snp_graph_destroy(void* graph) {
+  if (!graph) return SNP_ERR_INVALID;
+  GraphHandle* h = reinterpret_cast<GraphHandle*>(graph);
+  (void)hipGraphExecDestroy(h->exec);
+  (void)hipGraphDestroy(h->graph);
+  delete h;
+  return SNP_OK;
+}
+
+snp_status snp_read_status(void* ws, const snp_layout* layout, int64_t* instances_out, int64_t* hit_pairs_out,
+                           hipStream_t stream) {
+  if (!ws || !layout) return SNP_ERR_INVALID;
+  SNP_HIP(hipStreamSynchronize(stream));
+  unsigned long long c[CNT_COUNT];
+  SNP_HIP(hipMemcpy(c, reinterpret_cast<char*>(ws) + layout->counters, sizeof(c), hipMemcpyDeviceToHost));
+  if (instances_out) *instances_out = (int64_t)c[CNT_INSTANCES];
+  if (hit_pairs_out) *hit_pairs_out = (int64_t)c[CNT_HIT_PAIRS];
+  if (c[CNT_OVERFLOW]) return SNP_ERR_CAPACITY;
+  if (c[CNT_RANGE]) return SNP_ERR_RANGE;
+  return SNP_OK;
+}
+
+int32_t snp_supported_tiles(int32_t* triples, int32_t max) {
+  if (!triples) max = 0;
+  return supported_tiles(triples, max);
+}
+
+const char* snp_status_string(snp_status s) {
+  switch (s) {
+    case SNP_OK: return "ok";
+    case SNP_ERR_INVALID: return "invalid argument";
+    case SNP_ERR_CAPACITY: return "tile instances exceeded the workspace capacity";
+    case SNP_ERR_HIP: return "HIP runtime error";
+    case SNP_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SNP_ERR_RANGE: return "density-MLP phase outside the supported range";
+  }
+  return "unknown status";
+}
+
+snp_status snp_selftest_wave_sum(const float* in, float* out, int32_t waves, hipStream_t stream) {
+  if (!in || !out || waves <= 0) return SNP_ERR_INVALID;
+  SNP_HIP(launch_wave_sum_selftest(in, out, waves, stream));
+  return SNP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+// Tile binning and depth sorting (the tiling / sorting stages the paper's
+// App. A lists beside preprocessing; the blending of Eq. 4 needs the
+// primitives of every pixel in depth order).
+//
+//   scan   : exclusive prefix sum of the per-(view, primitive) tile counts
+//   emit   : one (key, value) instance per covered tile,
+//            key = (global tile id << 31) | float32 depth bits, value = primitive id
+//   sort   : stable LSD radix sort of the instances by key, 8-bit digits,
+//            3 kernels per pass (digit histogram per block, scan, stable scatter)
+//   ranges : [start, end) of every global tile in the sorted array
+//
+// Sizes only known on the device (the instance count) are read from device
+// memory; launches are sized by the workspace capacity, so the sequence can
+// be captured in a graph.  Writes past the capacity are dropped and flagged.
+#include "snp_internal.h"
+
+namespace snp {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int64_t kScanChunk = (int64_t)kScanThreads * kScanItems;  // 4096
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int64_t kSortChunk = (int64_t)kSortThreads * kSortRounds;  // 4096
+constexpr int kRadix = 256;
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan: uint32 values -> uint32 offsets, uint64 block totals
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t block_exclusive_scan_u64(uint64_t x, uint64_t* total, uint64_t* s_warp) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_warp[w] = inc;
+  __syncthreads();
+  uint64_t base = 0, tot = 0;
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    if (k < w) base += s_warp[k];
+    tot += s_warp[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
+template <typename TI>
+__global__ void __launch_bounds__(kScanThreads) scan_block_kernel(const TI* in, uint64_t* out64,
+                                                                  uint32_t* out32, int64_t n,
+                                                                  uint64_t* block_sums) {
+  __shared__ uint64_t s_warp[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint64_t v[kScanItems];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    v[k] = i < n ? (uint64_t)in[i] : 0;
+    sum += v[k];
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive_scan_u64(sum, &total, s_warp);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k;
+    if (i < n) {
+      if (out64) out64[i] = run;
+      if (out32) out32[i] = (uint32_t)run;
+    }
+    run += v[k];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_add_kernel(uint64_t* out64, uint32_t* out32, int64_t n,
+                                                                const uint64_t* __restrict__ block_off) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const uint64_t off = block_off[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanChunk; k += kScanThreads) {
+    const int64_t i = base + k;
+    if (i < n) {
+      if (out64) out64[i] += off;
+      if (out32) out32[i] = (uint32_t)(out32[i] + off);
+    }
+  }
+}
+
+__global__ void store_total_kernel(const uint64_t* sums, uint64_t* total_out) { *total_out = sums[0]; }
+
+// Scratch needed by scan_exclusive for n elements (bytes).
+size_t scan_scratch_bytes(int64_t n) {
+  size_t bytes = 0;
+  while (true) {
+    const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    bytes += ((size_t)nb * 8 + 255) / 256 * 256;
+    if (nb <= 1) break;
+    n = nb;
+  }
+  return bytes + 256;
+}
+
+// Exclusive scan of n uint32 values into out32 (wrapping) and the exact
+// total into *total_out (uint64, device) if non-null.
+template <typename TI>
+static hipError_t scan_level(const TI* in, uint64_t* out64, uint32_t* out32, int64_t n, char* scratch,
+                             uint64_t* total_out, hipStream_t st) {
+  const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  uint64_t* sums = reinterpret_cast<uint64_t*>(scratch);
+  char* next = scratch + ((size_t)nb * 8 + 255) / 256 * 256;
+  hipLaunchKernelGGL(scan_block_kernel<TI>, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, out64, out32, n, sums);
+  if (nb > 1) {
+    // sums -> exclusive offsets in place (through a uint64 copy level)
+    hipError_t e = scan_level<uint64_t>(sums, sums, nullptr, nb, next, total_out, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, out64, out32, n, sums);
+  } else if (total_out) {
+    hipLaunchKernelGGL(store_total_kernel, dim3(1), dim3(1), 0, st, sums, total_out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch, uint64_t* total_out,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  return scan_level<uint32_t>(in, nullptr, out, n, reinterpret_cast<char*>(scratch), total_out, st);
+}
+
+// ---------------------------------------------------------------------------
+// emit instances
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) emit_kernel(EmitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.P * a.V) return;
+  const uint32_t cnt = a.tile_counts[i];
+  if (cnt == 0) return;
+  const int v = (int)(i / a.P);
+  const uint32_t p = (uint32_t)(i - (int64_t)v * a.P);
+  const CamDev& cam = a.cams[v];
+  const int tx0 = a.rects[4 * i] / cam.tile_w, tx1 = a.rects[4 * i + 1] / cam.tile_w;
+  const int ty0 = a.rects[4 * i + 2] / cam.tile_h, ty1 = a.rects[4 * i + 3] / cam.tile_h;
+  const unsigned long long dbits = a.depth_bits[i];
+  int64_t pos = a.offsets[i];
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
+      if (pos >= a.capacity) return;
+      const unsigned long long tile = (unsigned long long)(cam.tile_base + ty * cam.ntx + tx);
+      a.keys[pos] = (tile << 31) | dbits;
+      a.values[pos] = p;
+    }
+}
+
+__global__ void check_capacity_kernel(unsigned long long* counters, int64_t capacity) {
+  if (counters[CNT_INSTANCES] > (unsigned long long)capacity) counters[CNT_OVERFLOW] = 1ull;
+}
+
+hipError_t launch_emit(const EmitArgs& a, unsigned long long* counters, hipStream_t st) {
+  const int64_t n = a.P * a.V;
+  hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(check_capacity_kernel, dim3(1), dim3(1), 0, st, counters, a.capacity);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t sort_count(const unsigned long long* counters, int64_t capacity) {
+  const unsigned long long n = counters[CNT_INSTANCES];
+  return n > (unsigned long long)capacity ? capacity : (int64_t)n;
+}
+
+__global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const unsigned long long* __restrict__ keys,
+                                                                  const unsigned long long* counters,
+                                                                  int64_t capacity, int shift,
+                                                                  uint32_t* __restrict__ hist, int64_t nblocks) {
+  __shared__ uint32_t s_h[kRadix];
+  s_h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = sort_count(counters, capacity);
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & 0xFF], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
+    const unsigned long long* __restrict__ kin, const uint32_t* __restrict__ vin,
+    unsigned long long* __restrict__ kout, uint32_t* __restrict__ vout, const unsigned long long* counters,
+    int64_t capacity, int shift, const uint32_t* __restrict__ offs, int64_t nblocks) {
+  constexpr int NW = kSortThreads / 64;
+  __shared__ uint32_t s_off[kRadix];        // global offset of each digit for this block (running)
+  __shared__ uint32_t s_wcnt[NW][kRadix];   // per-wave digit counts in the current round
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  s_off[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  const int64_t n = sort_count(counters, capacity);
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk;
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t rbase = base + (int64_t)r * kSortThreads;
+    if (rbase >= n) break;  // uniform over the block
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s_wcnt[k][t] = 0;
+    __syncthreads();
+    const int64_t i = rbase + t;
+    const bool valid = i < n;
+    unsigned long long key = 0;
+    uint32_t val = 0, d = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+      d = (uint32_t)((key >> shift) & 0xFF);
+    }
+    // lanes of this wave holding the same digit
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long bal = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    const uint32_t rank_w = (uint32_t)__popcll(peers & lt_mask);
+    if (valid && rank_w == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    // per digit: prefix over the waves, advance the running offset
+    {
+      uint32_t run = s_off[t];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const uint32_t c = s_wcnt[k][t];
+        s_wcnt[k][t] = run;
+        run += c;
+      }
+      s_off[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = s_wcnt[w][d] + rank_w;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+size_t sort_scratch_bytes(int64_t capacity) {
+  const int64_t nblocks = (capacity + kSortChunk - 1) / kSortChunk;
+  const int64_t nh = nblocks * kRadix;
+  return ((size_t)nh * 4 + 255) / 256 * 256 * 2 + scan_scratch_bytes(nh);
+}
+
+// Sorts keys/values by bits [0, key_bits).  Buffers ping-pong between (k0,v0)
+// and (k1,v1); the input is in (k0,v0) and the result ends in (k0,v0) if the
+// number of passes is even, else in (k1,v1).
+hipError_t radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1, int64_t capacity,
+                      const unsigned long long* counters, int key_bits, void* scratch, hipStream_t st) {
+  const int64_t nblocks = (capacity + kSortChunk - 1) / kSortChunk;
+  if (nblocks <= 0) return hipSuccess;
+  const int64_t nh = nblocks * kRadix;
+  char* sp = reinterpret_cast<char*>(scratch);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(sp);
+  uint32_t* offs = reinterpret_cast<uint32_t*>(sp + ((size_t)nh * 4 + 255) / 256 * 256);
+  char* scan_scr = sp + ((size_t)nh * 4 + 255) / 256 * 256 * 2;
+  const int passes = (key_bits + 7) / 8;
+  unsigned long long *ki = k0, *ko = k1;
+  uint32_t *vi = v0, *vo = v1;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = 8 * ps;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nblocks), dim3(kSortThreads), 0, st, ki, counters, capacity,
+                       shift, hist, nblocks);
+    hipError_t e = scan_exclusive_u32(hist, offs, nh, scan_scr, nullptr, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nblocks), dim3(kSortThreads), 0, st, ki, vi, ko, vo,
+                       counters, capacity, shift, offs, nblocks);
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  return hipGetLastError();
+}
+
+int radix_passes(int key_bits) { return (key_bits + 7) / 8; }
+
+// ---------------------------------------------------------------------------
+// tile ranges
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) ranges_kernel(const unsigned long long* __restrict__ keys,
+                                                     const unsigned long long* counters, int64_t capacity,
+                                                     uint32_t* __restrict__ ranges) {
+  const int64_t n = sort_count(counters, capacity);
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const unsigned long long tile = keys[i] >> 31;
+    if (i == 0 || (keys[i - 1] >> 31) != tile) ranges[2 * tile] = (uint32_t)i;
+    if (i == n - 1 || (keys[i + 1] >> 31) != tile) ranges[2 * tile + 1] = (uint32_t)(i + 1);
+  }
+}
+
+hipError_t launch_ranges(const unsigned long long* keys, const unsigned long long* counters, int64_t capacity,
+                         uint32_t* ranges, int64_t n_tiles, hipStream_t st) {
+  hipError_t e = fill_u32(ranges, 2 * n_tiles, 0u, st);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (capacity + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, keys, counters, capacity, ranges);
+  return hipGetLastError();
+}
+
+}  // namespace snp

@@ -1,0 +1,726 @@
+// Per-(primitive, view) preprocessing, colour MLP, and their adjoints.
+//
+// Sec. 3.1 (ellipsoid bound B = {x_B, s_B, q_B}, density field Eq. 5-6) and
+// Sec. 3.2 (line-ellipsoid intersection) define everything here.  The
+// quantities that do not depend on the pixel are computed once per
+// (primitive, view) in float64 and rounded to float32 records that the
+// rasterizer evaluates per pixel:
+//
+//   U  = diag(1/s) R(q)^T               world -> unit-sphere frame of B
+//   o' = U (o - x_B)                    camera centre in that frame
+//   d'(px,py) = U R_cam^-1 ((px-cx)/fx, (py-cy)/fy, 1)   (affine in the pixel)
+//   m'(px,py) = o' x d'(px,py)          moment of the ray (affine in the pixel)
+//
+// With A = |d'|^2 and M = |m'|^2 the ray meets B iff disc = A - M > 0; the
+// chord midpoint in the frame is p' = d' x m' / A and the chord half-length
+// (per unit of the un-normalised direction) is sqrt(disc) / A.
+//
+// The density MLP's phase along the chord is linear in p' (Eq. 5-6 with the
+// normalisation of Eq. 5 made explicit); per primitive the table stores
+//   Wt_k = omega0 / (2 pi m) W1_k R diag(s)   (m = max s)
+//   bt_k = omega0 b1_k / (2 pi)  reduced to [-1/2, 1/2]
+// so that phase_k / (2 pi) = Wt_k . p' + bt_k (revolutions).
+//
+// Culling, screen bounds and depth keys follow one fixed order of float64
+// operations with contraction disabled, so that any float64 implementation
+// that follows the same order produces bit-identical integers.
+#include "snp_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace snp {
+
+// ---------------------------------------------------------------------------
+// per-view constants
+// ---------------------------------------------------------------------------
+__global__ void setup_cams_kernel(CamChunk ch, CamDev* out) {
+  const int i = threadIdx.x;
+  if (i >= ch.count) return;
+  const snp_camera& c = ch.cam[i];
+  CamDev d;
+  d.width = c.width;
+  d.height = c.height;
+  d.tile_w = ch.tile_w;
+  d.tile_h = ch.tile_h;
+  d.ntx = (c.width + ch.tile_w - 1) / ch.tile_w;
+  d.nty = (c.height + ch.tile_h - 1) / ch.tile_h;
+  d.tile_base = ch.tile_base[i];
+  d.pad0 = 0;
+  d.pix_base = ch.pix_base[i];
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+  for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+  // exact inverse of the stored (float32, nearly orthogonal) matrix
+  const double a = c.R[0], b = c.R[1], e = c.R[2];
+  const double f = c.R[3], g = c.R[4], h = c.R[5];
+  const double p = c.R[6], q = c.R[7], r = c.R[8];
+  const double A0 = g * r - h * q, A1 = -(b * r - e * q), A2 = b * h - e * g;
+  const double B0 = -(f * r - h * p), B1 = a * r - e * p, B2 = -(a * h - e * f);
+  const double C0 = f * q - g * p, C1 = -(a * q - b * p), C2 = a * g - b * f;
+  const double det = a * A0 + b * B0 + e * C0;
+  const double inv = 1.0 / det;
+  const double Ri[9] = {A0 * inv, A1 * inv, A2 * inv, B0 * inv, B1 * inv, B2 * inv, C0 * inv, C1 * inv, C2 * inv};
+  for (int k = 0; k < 9; ++k) {
+    d.Rinv[k] = Ri[k];
+    d.Rinv_f[k] = (float)Ri[k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    d.o[k] = -(Ri[3 * k] * (double)c.t[0] + Ri[3 * k + 1] * (double)c.t[1] + Ri[3 * k + 2] * (double)c.t[2]);
+    d.o_f[k] = (float)d.o[k];
+  }
+  out[ch.first + i] = d;
+}
+
+// Rotation of a quaternion (w, x, y, z), normalised first; fixed op order.
+__device__ __forceinline__ void quat_rot_f64(const float* qf, double Rp[3][3], double qn_out[4], double* qnorm) {
+  const double q0 = qf[0], q1 = qf[1], q2 = qf[2], q3 = qf[3];
+  const double qn = sqrt(((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3);
+  const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double xy = x * y, xz = x * z, yz = y * z;
+  const double wx = w * x, wy = w * y, wz = w * z;
+  Rp[0][0] = 1.0 - 2.0 * (yy + zz);
+  Rp[0][1] = 2.0 * (xy - wz);
+  Rp[0][2] = 2.0 * (xz + wy);
+  Rp[1][0] = 2.0 * (xy + wz);
+  Rp[1][1] = 1.0 - 2.0 * (xx + zz);
+  Rp[1][2] = 2.0 * (yz - wx);
+  Rp[2][0] = 2.0 * (xz - wy);
+  Rp[2][1] = 2.0 * (yz + wx);
+  Rp[2][2] = 1.0 - 2.0 * (xx + yy);
+  if (qn_out) {
+    qn_out[0] = w;
+    qn_out[1] = x;
+    qn_out[2] = y;
+    qn_out[3] = z;
+  }
+  if (qnorm) *qnorm = qn;
+}
+
+// ---------------------------------------------------------------------------
+// per-primitive density table (view independent)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(256) prim_table_kernel(int64_t P, float omega0, const float* __restrict__ scales,
+                                                         const float* __restrict__ quats,
+                                                         const float* __restrict__ w1, const float* __restrict__ b1,
+                                                         const float* __restrict__ w2, const float* __restrict__ b2,
+                                                         float* __restrict__ table, unsigned long long* counters) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  constexpr int TS = 5 * N + 4;
+  double Rp[3][3];
+  quat_rot_f64(quats + 4 * p, Rp, nullptr, nullptr);
+  const double s0 = scales[3 * p], s1 = scales[3 * p + 1], s2 = scales[3 * p + 2];
+  const double m = fmax(s0, fmax(s1, s2));
+  const double K = (double)omega0 / (6.283185307179586476925 * m);
+  const double s[3] = {s0, s1, s2};
+  float* row = table + p * TS;
+  bool bad = false;
+  for (int k = 0; k < N; ++k) {
+    const float* wk = w1 + (p * N + k) * 3;
+    double wt[3];
+    double l1 = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      wt[j] = K * ((wk[0] * Rp[0][j] + wk[1] * Rp[1][j] + wk[2] * Rp[2][j]) * s[j]);
+      l1 += fabs(wt[j]);
+    }
+    double bt = (double)omega0 * (double)b1[p * N + k] / 6.283185307179586476925;
+    bt -= rint(bt);
+    if (!(l1 < 255.0)) bad = true;
+    row[4 * k + 0] = (float)wt[0];
+    row[4 * k + 1] = (float)wt[1];
+    row[4 * k + 2] = (float)wt[2];
+    row[4 * k + 3] = (float)bt;
+    row[4 * N + k] = (float)((double)w2[p * N + k] / 6.283185307179586476925);
+  }
+  row[5 * N] = b2[p];
+  row[5 * N + 1] = 0.f;
+  row[5 * N + 2] = 0.f;
+  row[5 * N + 3] = 0.f;
+  if (bad) atomicOr(&counters[CNT_RANGE], 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// per-(view, primitive): key path + record
+// ---------------------------------------------------------------------------
+
+// one tangent-line pair of the projected outline -> inclusive pixel range
+__device__ __forceinline__ void outline_extent(double Ma, double Mb, double M22, double f, double cc, double size,
+                                               double* lo, double* hi, double* p_lo, double* p_hi) {
+  double disc = Mb * Mb - Ma * M22;
+  disc = disc > 0.0 ? disc : 0.0;
+  const double sq = sqrt(disc);
+  const double u_lo = (Mb + sq) / M22;
+  const double u_hi = (Mb - sq) / M22;
+  *p_lo = f * u_lo + cc;
+  *p_hi = f * u_hi + cc;
+  double l = ceil((*p_lo - 0.5) - kEpsPx);
+  double h = floor((*p_hi - 0.5) + kEpsPx);
+  l = l > 0.0 ? l : 0.0;
+  h = h < size - 1.0 ? h : size - 1.0;
+  *lo = l;
+  *hi = h;
+}
+
+__global__ void __launch_bounds__(256) preprocess_views_kernel(ViewArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.P * a.V) return;
+  const int v = (int)(i / a.P);
+  const int64_t p = i - (int64_t)v * a.P;
+  const CamDev& cam = a.cams[v];
+
+  double Rp[3][3];
+  quat_rot_f64(a.quats + 4 * p, Rp, nullptr, nullptr);
+  const double xb[3] = {a.centers[3 * p], a.centers[3 * p + 1], a.centers[3 * p + 2]};
+  const double s[3] = {a.scales[3 * p], a.scales[3 * p + 1], a.scales[3 * p + 2]};
+  double C[3][3], t[3];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) C[r][c] = cam.R[3 * r + c];
+    t[r] = cam.t[r];
+  }
+  // camera-frame rotation, centre and shape matrix
+  double Rc[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Rc[r][c] = (C[r][0] * Rp[0][c] + C[r][1] * Rp[1][c]) + C[r][2] * Rp[2][c];
+  double mu[3];
+  for (int r = 0; r < 3; ++r) mu[r] = ((C[r][0] * xb[0] + C[r][1] * xb[1]) + C[r][2] * xb[2]) + t[r];
+  const double ss[3] = {s[0] * s[0], s[1] * s[1], s[2] * s[2]};
+  auto sig = [&](int r, int c) {
+    return (((Rc[r][0] * ss[0]) * Rc[c][0] + (Rc[r][1] * ss[1]) * Rc[c][1]) + (Rc[r][2] * ss[2]) * Rc[c][2]);
+  };
+  const double S00 = sig(0, 0), S02 = sig(0, 2), S11 = sig(1, 1), S12 = sig(1, 2), S22 = sig(2, 2);
+  const bool keep = (mu[2] - sqrt(S22)) > (double)a.z_near;
+
+  uint32_t count = 0;
+  int32_t rect[4] = {0, 0, 0, 0};
+  uint32_t dbits = 0;
+  float* rec = a.records + i * kRecFloats;
+  if (keep) {
+    const double M00 = S00 - mu[0] * mu[0];
+    const double M02 = S02 - mu[0] * mu[2];
+    const double M11 = S11 - mu[1] * mu[1];
+    const double M12 = S12 - mu[1] * mu[2];
+    const double M22 = S22 - mu[2] * mu[2];
+    double x0, x1, y0, y1, pxl, pxh, pyl, pyh;
+    outline_extent(M00, M02, M22, (double)cam.fx, (double)cam.cx, (double)cam.width, &x0, &x1, &pxl, &pxh);
+    outline_extent(M11, M12, M22, (double)cam.fy, (double)cam.cy, (double)cam.height, &y0, &y1, &pyl, &pyh);
+    if (x0 <= x1 && y0 <= y1) {
+      rect[0] = (int32_t)x0;
+      rect[1] = (int32_t)x1;
+      rect[2] = (int32_t)y0;
+      rect[3] = (int32_t)y1;
+      const int tx0 = rect[0] / cam.tile_w, tx1 = rect[1] / cam.tile_w;
+      const int ty0 = rect[2] / cam.tile_h, ty1 = rect[3] / cam.tile_h;
+      count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+      dbits = __float_as_uint((float)mu[2]);
+
+      // ---- record (float64 -> float32) ----
+      const float rxf = (float)(0.5 * (pxl + pxh));
+      const float ryf = (float)(0.5 * (pyl + pyh));
+      double U[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) U[r][c] = Rp[c][r] / s[r];
+      double om[3] = {cam.o[0] - xb[0], cam.o[1] - xb[1], cam.o[2] - xb[2]};
+      double op[3], G[3][3];
+      for (int r = 0; r < 3; ++r) {
+        op[r] = U[r][0] * om[0] + U[r][1] * om[1] + U[r][2] * om[2];
+        for (int c = 0; c < 3; ++c)
+          G[r][c] = U[r][0] * cam.Rinv[c] + U[r][1] * cam.Rinv[3 + c] + U[r][2] * cam.Rinv[6 + c];
+      }
+      const double vr[3] = {((double)rxf - cam.cx) / cam.fx, ((double)ryf - cam.cy) / cam.fy, 1.0};
+      double dc[3], gx[3], gy[3];
+      for (int r = 0; r < 3; ++r) {
+        dc[r] = G[r][0] * vr[0] + G[r][1] * vr[1] + G[r][2] * vr[2];
+        gx[r] = G[r][0] / cam.fx;
+        gy[r] = G[r][1] / cam.fy;
+      }
+      auto cross = [](const double* u, const double* w, double* out) {
+        out[0] = u[1] * w[2] - u[2] * w[1];
+        out[1] = u[2] * w[0] - u[0] * w[2];
+        out[2] = u[0] * w[1] - u[1] * w[0];
+      };
+      double mc[3], hx[3], hy[3];
+      cross(op, dc, mc);
+      cross(op, gx, hx);
+      cross(op, gy, hy);
+      float4* r4 = reinterpret_cast<float4*>(rec);
+      r4[0] = make_float4((float)dc[0], (float)dc[1], (float)dc[2], rxf);
+      r4[1] = make_float4((float)gx[0], (float)gx[1], (float)gx[2], ryf);
+      float cr = 0.f, cg = 0.f, cb = 0.f;
+      if (a.color_mode == 0) {
+        cr = a.colors[3 * p];
+        cg = a.colors[3 * p + 1];
+        cb = a.colors[3 * p + 2];
+      }
+      r4[2] = make_float4((float)gy[0], (float)gy[1], (float)gy[2], cr);
+      r4[3] = make_float4((float)mc[0], (float)mc[1], (float)mc[2], cg);
+      r4[4] = make_float4((float)hx[0], (float)hx[1], (float)hx[2], cb);
+      r4[5] = make_float4((float)hy[0], (float)hy[1], (float)hy[2], 0.f);
+    }
+  }
+  a.rects[4 * i + 0] = rect[0];
+  a.rects[4 * i + 1] = rect[1];
+  a.rects[4 * i + 2] = rect[2];
+  a.rects[4 * i + 3] = rect[3];
+  a.depth_bits[i] = dbits;
+  a.tile_counts[i] = count;
+}
+
+// ---------------------------------------------------------------------------
+// colour MLP: input [normalize(x_B - o_v), xi_p], DEPTH ReLU layers of WIDTH
+// units, sigmoid RGB.  Lanes of one primitive's views are adjacent (group of
+// GS lanes, views v = lane, lane + GS, ...), so the weight loads of a group
+// hit the same addresses.
+// ---------------------------------------------------------------------------
+
+template <int WIDTH, int DEPTH>
+struct CmlpShape {
+  static constexpr int K = kCmlpIn * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH) + WIDTH * 3 + 3;
+};
+
+__device__ __forceinline__ void cmlp_input(const CmlpArgs& a, int64_t p, int v, float* x, float* rawdir,
+                                           float* inv_len) {
+  const CamDev& cam = a.cams[v];
+  const float dx = a.centers[3 * p] - cam.o_f[0];
+  const float dy = a.centers[3 * p + 1] - cam.o_f[1];
+  const float dz = a.centers[3 * p + 2] - cam.o_f[2];
+  const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  rawdir[0] = dx * il;
+  rawdir[1] = dy * il;
+  rawdir[2] = dz * il;
+  *inv_len = il;
+  x[0] = rawdir[0];
+  x[1] = rawdir[1];
+  x[2] = rawdir[2];
+#pragma unroll
+  for (int k = 0; k < kXiDim; ++k) x[3 + k] = a.xi[p * kXiDim + k];
+}
+
+template <int WIDTH, int DEPTH>
+__global__ void __launch_bounds__(256) cmlp_fwd_kernel(CmlpArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = gid / a.GS;
+  const int lane_v = (int)(gid - p * a.GS);
+  if (p >= a.P) return;
+  constexpr int K = CmlpShape<WIDTH, DEPTH>::K;
+  const float* Wp = a.cmlp + p * K;
+  for (int v = lane_v; v < a.V; v += a.GS) {
+    const int64_t i = (int64_t)v * a.P + p;
+    if (a.tile_counts[i] == 0) continue;
+    float x[kCmlpIn], dir[3], il;
+    cmlp_input(a, p, v, x, dir, &il);
+    float h[WIDTH], g[WIDTH];
+    int off = 0;
+    // layer 0
+#pragma unroll
+    for (int o = 0; o < WIDTH; ++o) {
+      float acc = Wp[off + kCmlpIn * WIDTH + o];
+#pragma unroll
+      for (int k = 0; k < kCmlpIn; ++k) acc = __builtin_fmaf(Wp[off + o * kCmlpIn + k], x[k], acc);
+      h[o] = fmaxf(acc, 0.f);
+    }
+    off += kCmlpIn * WIDTH + WIDTH;
+#pragma unroll
+    for (int l = 1; l < DEPTH; ++l) {
+#pragma unroll
+      for (int o = 0; o < WIDTH; ++o) {
+        float acc = Wp[off + WIDTH * WIDTH + o];
+#pragma unroll
+        for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], h[k], acc);
+        g[o] = fmaxf(acc, 0.f);
+      }
+#pragma unroll
+      for (int o = 0; o < WIDTH; ++o) h[o] = g[o];
+      off += WIDTH * WIDTH + WIDTH;
+    }
+    float out[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+      float acc = Wp[off + 3 * WIDTH + o];
+#pragma unroll
+      for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], h[k], acc);
+      out[o] = 1.0f / (1.0f + expf(-acc));
+    }
+    float* rec = a.records + i * kRecFloats;
+    rec[11] = out[0];
+    rec[15] = out[1];
+    rec[19] = out[2];
+  }
+}
+
+// Sum over the GS lanes of a group (GS a power of two <= 64); all lanes get it.
+__device__ __forceinline__ float group_sum(float v, int GS) {
+  for (int off = 1; off < GS; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Backward of one hidden layer L (input activations hs[L-1], output deltas
+// in s_delta), then recursion to layer L-1.  The loop over output units is
+// a runtime loop reading the delta from LDS, so that no register array is
+// indexed dynamically.
+template <int WIDTH, int DEPTH, int Lyr>
+__device__ __forceinline__ void cmlp_bwd_hidden(const CmlpArgs& a, const float* Wp, float* gW, bool writer,
+                                                float (&hs)[DEPTH][WIDTH], float* s_delta) {
+  if constexpr (Lyr >= 1) {
+    const int off = kCmlpIn * WIDTH + WIDTH + (Lyr - 1) * (WIDTH * WIDTH + WIDTH);
+    float dprev[WIDTH];
+#pragma unroll
+    for (int k = 0; k < WIDTH; ++k) dprev[k] = 0.f;
+    for (int o = 0; o < WIDTH; ++o) {
+      const float dl = s_delta[o];
+#pragma unroll
+      for (int k = 0; k < WIDTH; ++k) {
+        const float gw = group_sum(dl * hs[Lyr - 1][k], a.GS);
+        if (writer) gW[off + o * WIDTH + k] += gw;
+        dprev[k] = __builtin_fmaf(Wp[off + o * WIDTH + k], dl, dprev[k]);
+      }
+      const float gb = group_sum(dl, a.GS);
+      if (writer) gW[off + WIDTH * WIDTH + o] += gb;
+    }
+#pragma unroll
+    for (int k = 0; k < WIDTH; ++k) s_delta[k] = hs[Lyr - 1][k] > 0.f ? dprev[k] : 0.f;
+    cmlp_bwd_hidden<WIDTH, DEPTH, Lyr - 1>(a, Wp, gW, writer, hs, s_delta);
+  }
+}
+
+template <int WIDTH, int DEPTH>
+__global__ void __launch_bounds__(256) cmlp_bwd_kernel(CmlpArgs a) {
+  __shared__ float s_delta_all[256 * (WIDTH + 1)];
+  float* s_delta = s_delta_all + threadIdx.x * (WIDTH + 1);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // every lane of a group must reach the shuffles: no early return
+  const int64_t p = gid / a.GS;
+  const int lane_v = (int)(gid - p * a.GS);
+  const bool valid_p = p < a.P;
+  constexpr int K = CmlpShape<WIDTH, DEPTH>::K;
+  const float* Wp = a.cmlp + (valid_p ? p : 0) * K;
+  float* gW = a.g_cmlp + (valid_p ? p : 0) * K;
+  const bool writer = valid_p && lane_v == 0;
+  const int rounds = (a.V + a.GS - 1) / a.GS;
+  for (int r = 0; r < rounds; ++r) {
+    const int v = lane_v + r * a.GS;
+    const int64_t i = (int64_t)v * a.P + p;
+    const bool act = valid_p && v < a.V && a.tile_counts[i] != 0;
+    float x[kCmlpIn], dir[3], il = 0.f;
+    float hs[DEPTH][WIDTH];  // post-ReLU activations
+    float gout[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < kCmlpIn; ++k) x[k] = 0.f;
+#pragma unroll
+    for (int l = 0; l < DEPTH; ++l)
+#pragma unroll
+      for (int o = 0; o < WIDTH; ++o) hs[l][o] = 0.f;
+    if (act) {
+      cmlp_input(a, p, v, x, dir, &il);
+      int off = 0;
+#pragma unroll
+      for (int o = 0; o < WIDTH; ++o) {
+        float acc = Wp[off + kCmlpIn * WIDTH + o];
+#pragma unroll
+        for (int k = 0; k < kCmlpIn; ++k) acc = __builtin_fmaf(Wp[off + o * kCmlpIn + k], x[k], acc);
+        hs[0][o] = fmaxf(acc, 0.f);
+      }
+      off += kCmlpIn * WIDTH + WIDTH;
+#pragma unroll
+      for (int l = 1; l < DEPTH; ++l) {
+#pragma unroll
+        for (int o = 0; o < WIDTH; ++o) {
+          float acc = Wp[off + WIDTH * WIDTH + o];
+#pragma unroll
+          for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], hs[l - 1][k], acc);
+          hs[l][o] = fmaxf(acc, 0.f);
+        }
+        off += WIDTH * WIDTH + WIDTH;
+      }
+      const float* gv = a.gview + i * kGViewFloats;
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        float acc = Wp[off + 3 * WIDTH + o];
+#pragma unroll
+        for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], hs[DEPTH - 1][k], acc);
+        const float sg = 1.0f / (1.0f + expf(-acc));
+        gout[o] = gv[18 + o] * sg * (1.0f - sg);  // d loss / d pre-sigmoid
+      }
+    }
+    // output layer: W (3 x WIDTH), b (3)
+    const int off_last = kCmlpIn * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH);
+    {
+      float delta[WIDTH];
+#pragma unroll
+      for (int k = 0; k < WIDTH; ++k) delta[k] = 0.f;
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+#pragma unroll
+        for (int k = 0; k < WIDTH; ++k) {
+          const float gw = group_sum(gout[o] * hs[DEPTH - 1][k], a.GS);
+          if (writer) gW[off_last + o * WIDTH + k] += gw;
+          delta[k] = __builtin_fmaf(Wp[off_last + o * WIDTH + k], gout[o], delta[k]);
+        }
+        const float gb = group_sum(gout[o], a.GS);
+        if (writer) gW[off_last + 3 * WIDTH + o] += gb;
+      }
+#pragma unroll
+      for (int k = 0; k < WIDTH; ++k) s_delta[k] = hs[DEPTH - 1][k] > 0.f ? delta[k] : 0.f;
+    }
+    // hidden layers DEPTH-1 .. 1
+    cmlp_bwd_hidden<WIDTH, DEPTH, DEPTH - 1>(a, Wp, gW, writer, hs, s_delta);
+    // first layer: W (WIDTH x 11)
+    float gx[kCmlpIn];
+#pragma unroll
+    for (int k = 0; k < kCmlpIn; ++k) gx[k] = 0.f;
+    for (int o = 0; o < WIDTH; ++o) {
+      const float dl = s_delta[o];
+#pragma unroll
+      for (int k = 0; k < kCmlpIn; ++k) {
+        const float gw = group_sum(dl * x[k], a.GS);
+        if (writer) gW[o * kCmlpIn + k] += gw;
+        gx[k] = __builtin_fmaf(Wp[o * kCmlpIn + k], dl, gx[k]);
+      }
+      const float gb = group_sum(dl, a.GS);
+      if (writer) gW[kCmlpIn * WIDTH + o] += gb;
+    }
+    if (act) {
+      float* gv = a.gview + i * kGViewFloats;
+      gv[21] = gx[0];
+      gv[22] = gx[1];
+      gv[23] = gx[2];
+    }
+    if (a.g_xi) {
+#pragma unroll
+      for (int k = 0; k < kXiDim; ++k) {
+        const float g = group_sum(act ? gx[3 + k] : 0.f, a.GS);
+        if (writer) a.g_xi[p * kXiDim + k] += g;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the preprocessing: per primitive, summed over the views
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) preprocess_bwd_kernel(PreBwdArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.P) return;
+  const int N = a.N;
+  double Rp[3][3], qh[4], qnorm;
+  quat_rot_f64(a.quats + 4 * p, Rp, qh, &qnorm);
+  const double xb[3] = {a.centers[3 * p], a.centers[3 * p + 1], a.centers[3 * p + 2]};
+  const double s[3] = {a.scales[3 * p], a.scales[3 * p + 1], a.scales[3 * p + 2]};
+  double U[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) U[r][c] = Rp[c][r] / s[r];
+
+  double gU[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double gxb[3] = {0, 0, 0};
+  double gcol[3] = {0, 0, 0};
+  auto cross = [](const double* u, const double* w, double* out) {
+    out[0] = u[1] * w[2] - u[2] * w[1];
+    out[1] = u[2] * w[0] - u[0] * w[2];
+    out[2] = u[0] * w[1] - u[1] * w[0];
+  };
+  for (int v = 0; v < a.V; ++v) {
+    const int64_t i = (int64_t)v * a.P + p;
+    if (a.tile_counts[i] == 0) continue;
+    const CamDev& cam = a.cams[v];
+    const float* rec = a.records + i * kRecFloats;
+    const float* gv = a.gview + i * kGViewFloats;
+    const double rx = rec[3], ry = rec[7];
+    double om[3] = {cam.o[0] - xb[0], cam.o[1] - xb[1], cam.o[2] - xb[2]};
+    double op[3], G[3][3];
+    for (int r = 0; r < 3; ++r) {
+      op[r] = U[r][0] * om[0] + U[r][1] * om[1] + U[r][2] * om[2];
+      for (int c = 0; c < 3; ++c)
+        G[r][c] = U[r][0] * cam.Rinv[c] + U[r][1] * cam.Rinv[3 + c] + U[r][2] * cam.Rinv[6 + c];
+    }
+    const double vr[3] = {(rx - cam.cx) / cam.fx, (ry - cam.cy) / cam.fy, 1.0};
+    double dc[3], gx[3], gy[3];
+    for (int r = 0; r < 3; ++r) {
+      dc[r] = G[r][0] * vr[0] + G[r][1] * vr[1] + G[r][2] * vr[2];
+      gx[r] = G[r][0] / cam.fx;
+      gy[r] = G[r][1] / cam.fy;
+    }
+    double g_dc[3] = {gv[0], gv[1], gv[2]}, g_gx[3] = {gv[3], gv[4], gv[5]}, g_gy[3] = {gv[6], gv[7], gv[8]};
+    const double g_mc[3] = {gv[9], gv[10], gv[11]}, g_hx[3] = {gv[12], gv[13], gv[14]},
+                 g_hy[3] = {gv[15], gv[16], gv[17]};
+    // m = o' x b  ->  g_o' += b x g_m,  g_b += g_m x o'
+    double g_op[3] = {0, 0, 0}, t3[3];
+    cross(dc, g_mc, t3);
+    for (int r = 0; r < 3; ++r) g_op[r] += t3[r];
+    cross(gx, g_hx, t3);
+    for (int r = 0; r < 3; ++r) g_op[r] += t3[r];
+    cross(gy, g_hy, t3);
+    for (int r = 0; r < 3; ++r) g_op[r] += t3[r];
+    cross(g_mc, op, t3);
+    for (int r = 0; r < 3; ++r) g_dc[r] += t3[r];
+    cross(g_hx, op, t3);
+    for (int r = 0; r < 3; ++r) g_gx[r] += t3[r];
+    cross(g_hy, op, t3);
+    for (int r = 0; r < 3; ++r) g_gy[r] += t3[r];
+    // G: dc = G vr, gx = G e0 / fx, gy = G e1 / fy
+    double gG[3][3];
+    for (int r = 0; r < 3; ++r) {
+      gG[r][0] = g_dc[r] * vr[0] + g_gx[r] / cam.fx;
+      gG[r][1] = g_dc[r] * vr[1] + g_gy[r] / cam.fy;
+      gG[r][2] = g_dc[r] * vr[2];
+    }
+    // G = U Rinv, o' = U (o - x_B)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        gU[r][c] += gG[r][0] * cam.Rinv[3 * c] + gG[r][1] * cam.Rinv[3 * c + 1] + gG[r][2] * cam.Rinv[3 * c + 2];
+        gU[r][c] += g_op[r] * om[c];
+      }
+    for (int c = 0; c < 3; ++c) gxb[c] -= U[0][c] * g_op[0] + U[1][c] * g_op[1] + U[2][c] * g_op[2];
+    // colour
+    if (a.color_mode == 0) {
+      gcol[0] += gv[18];
+      gcol[1] += gv[19];
+      gcol[2] += gv[20];
+    } else {
+      // dir = normalize(x_B - o): d dir / d x_B = (I - dir dir^T) / |x_B - o|
+      const double dvec[3] = {-om[0], -om[1], -om[2]};
+      const double len = sqrt(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
+      const double dir[3] = {dvec[0] / len, dvec[1] / len, dvec[2] / len};
+      const double gd[3] = {gv[21], gv[22], gv[23]};
+      const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
+      for (int c = 0; c < 3; ++c) gxb[c] += (gd[c] - dir[c] * dd) / len;
+    }
+  }
+  // U[r][c] = Rp[c][r] / s[r]
+  double gR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double gs[3] = {0, 0, 0};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      gR[c][r] += gU[r][c] / s[r];
+      gs[r] -= gU[r][c] * Rp[c][r] / (s[r] * s[r]);
+    }
+  // table: Wt_k[j] = K sum_i W1_k[i] Rp[i][j] s_j,  K = omega0 / (2 pi m)
+  const double m = fmax(s[0], fmax(s[1], s[2]));
+  const int am = (s[0] >= s[1] && s[0] >= s[2]) ? 0 : (s[1] >= s[2] ? 1 : 2);
+  const double twopi = 6.283185307179586476925;
+  const double K = (double)a.omega0 / (twopi * m);
+  const int TS = table_stride(N);
+  const float* gt = a.gtable + p * TS;
+  double gK = 0.0;
+  for (int k = 0; k < N; ++k) {
+    const float* wk = a.w1 + (p * N + k) * 3;
+    const double gwt[3] = {gt[4 * k], gt[4 * k + 1], gt[4 * k + 2]};
+    double wt[3];
+    for (int j = 0; j < 3; ++j) wt[j] = K * ((wk[0] * Rp[0][j] + wk[1] * Rp[1][j] + wk[2] * Rp[2][j]) * s[j]);
+    for (int j = 0; j < 3; ++j) gK += gwt[j] * wt[j] / K;
+    if (a.g.w1) {
+      for (int ii = 0; ii < 3; ++ii) {
+        double acc = 0.0;
+        for (int j = 0; j < 3; ++j) acc += gwt[j] * Rp[ii][j] * s[j];
+        a.g.w1[(p * N + k) * 3 + ii] += (float)(K * acc);
+      }
+    }
+    for (int ii = 0; ii < 3; ++ii)
+      for (int j = 0; j < 3; ++j) {
+        gR[ii][j] += K * gwt[j] * wk[ii] * s[j];
+        gs[j] += K * gwt[j] * wk[ii] * Rp[ii][j];
+      }
+    if (a.g.b1) a.g.b1[p * N + k] += (float)((double)gt[4 * k + 3] * a.omega0 / twopi);
+    if (a.g.w2) a.g.w2[p * N + k] += (float)((double)gt[4 * N + k] / twopi);
+  }
+  if (a.g.b2) a.g.b2[p] += gt[5 * N];
+  gs[am] += gK * (-K / m);
+  // rotation -> normalised quaternion -> raw quaternion
+  const double w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  double gq[4];
+  gq[0] = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+  gq[1] = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] + z * gR[2][0] +
+                 w * gR[2][1] - 2.0 * x * gR[2][2]);
+  gq[2] = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] - w * gR[2][0] +
+                 z * gR[2][1] - 2.0 * y * gR[2][2]);
+  gq[3] = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
+                 y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+  const double dq = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+  if (a.g.quats)
+    for (int k = 0; k < 4; ++k) a.g.quats[4 * p + k] += (float)((gq[k] - qh[k] * dq) / qnorm);
+  if (a.g.scales)
+    for (int k = 0; k < 3; ++k) a.g.scales[3 * p + k] += (float)gs[k];
+  if (a.g.centers)
+    for (int k = 0; k < 3; ++k) a.g.centers[3 * p + k] += (float)gxb[k];
+  if (a.color_mode == 0 && a.g.colors)
+    for (int k = 0; k < 3; ++k) a.g.colors[3 * p + k] += (float)gcol[k];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_setup_cams(const CamChunk& ch, CamDev* out, hipStream_t st) {
+  hipLaunchKernelGGL(setup_cams_kernel, dim3(1), dim3(kMaxCamsPerChunk), 0, st, ch, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_prim_table(int N, int64_t P, float omega0, const snp_prims& pr, float* table,
+                             unsigned long long* counters, hipStream_t st) {
+  const dim3 grid((unsigned)((P + 255) / 256)), block(256);
+  switch (N) {
+    case 4: hipLaunchKernelGGL(prim_table_kernel<4>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
+    case 8: hipLaunchKernelGGL(prim_table_kernel<8>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
+    case 16: hipLaunchKernelGGL(prim_table_kernel<16>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
+    case 32: hipLaunchKernelGGL(prim_table_kernel<32>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_views(const ViewArgs& a, hipStream_t st) {
+  const int64_t n = a.P * a.V;
+  hipLaunchKernelGGL(preprocess_views_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+static int group_size(int V) {
+  int gs = 1;
+  while (gs < V && gs < 64) gs <<= 1;
+  return gs;
+}
+
+#define SNP_CMLP_DISPATCH(KERNEL, width, depth, grid, block, st, a)                                  \
+  do {                                                                                                \
+    if (width == 16 && depth == 1) hipLaunchKernelGGL((KERNEL<16, 1>), grid, block, 0, st, a);        \
+    else if (width == 16 && depth == 2) hipLaunchKernelGGL((KERNEL<16, 2>), grid, block, 0, st, a);   \
+    else if (width == 16 && depth == 3) hipLaunchKernelGGL((KERNEL<16, 3>), grid, block, 0, st, a);   \
+    else if (width == 32 && depth == 1) hipLaunchKernelGGL((KERNEL<32, 1>), grid, block, 0, st, a);   \
+    else if (width == 32 && depth == 2) hipLaunchKernelGGL((KERNEL<32, 2>), grid, block, 0, st, a);   \
+    else if (width == 32 && depth == 3) hipLaunchKernelGGL((KERNEL<32, 3>), grid, block, 0, st, a);   \
+    else return hipErrorInvalidValue;                                                                 \
+  } while (0)
+
+hipError_t launch_cmlp_fwd(int width, int depth, CmlpArgs a, hipStream_t st) {
+  a.GS = group_size(a.V);
+  const int64_t n = a.P * a.GS;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  SNP_CMLP_DISPATCH(cmlp_fwd_kernel, width, depth, grid, block, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cmlp_bwd(int width, int depth, CmlpArgs a, hipStream_t st) {
+  a.GS = group_size(a.V);
+  const int64_t n = a.P * a.GS;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  SNP_CMLP_DISPATCH(cmlp_bwd_kernel, width, depth, grid, block, st, a);
+  return hipGetLastError();
+}
+
+bool cmlp_supported(int width, int depth) {
+  return (width == 16 || width == 32) && depth >= 1 && depth <= 3;
+}
+
+int cmlp_param_count(int width, int depth) {
+  return kCmlpIn * width + width + (depth - 1) * (width * width + width) + width * 3 + 3;
+}
+
+hipError_t launch_preprocess_bwd(const PreBwdArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace snp

@@ -1,0 +1,624 @@
+// Tile rasterizer of neural primitives: forward (Eq. 3-4, 7-9) and adjoint.
+//
+// A workgroup renders one tile (TW x TH pixels, PPL pixels per thread, rows
+// stacked).  It walks the tile's depth-sorted instance list in batches of
+// BATCH primitives; each batch's records (24 floats per (view, primitive))
+// and density tables (5N + 4 floats per primitive) are staged in LDS by the
+// whole workgroup and then read as broadcasts.  Per pixel and primitive:
+//
+//   d' = dc + gx dx + gy dy,  m' = mc + hx dx + hy dy          (ray in B's frame)
+//   A = |d'|^2, M = |m'|^2, disc = A - M;  hit iff disc > 0     (line-ellipsoid)
+//   H = sqrt(disc)/A (half chord), p' = d' x m' / A (midpoint), e' = d' H
+//   Q = b2 + sum_k W2_k cos(2 pi (Wt_k.p' + bt_k)) sinc(2 pi Wt_k.e')
+//   integral = 2 L H Q   (L = length of the un-normalised ray direction)
+//
+// which is S(t_out) - S(t_in) of Eq. 8 rearranged around the chord midpoint
+// (sin(u+v) - sin(u-v) = 2 cos u sin v); alpha = 1 - exp(-max(0, integral))
+// (Eq. 9), then C += c alpha T, T *= 1 - alpha (Eq. 4).  A pixel stops taking
+// primitives once T < t_eps; the workgroup leaves the list when every pixel
+// has stopped.
+//
+// The adjoint walks the same list in the same order, recomputing T, and uses
+// the final colour to get the colour of everything behind each primitive:
+//   d loss / d integral = sum_c g_c (c_c T (1 - alpha) - behind_c)
+// (behind = C_final - C_accumulated_after), so no per-pixel history is kept.
+// Per-pair gradients of the table entries and of the record coefficients are
+// summed over the wave with DPP and added to per-primitive / per-(view,
+// primitive) accumulators with one atomic per value per wave.
+#include "snp_internal.h"
+
+namespace snp {
+
+constexpr int BATCH = 64;
+
+
+// sum over the 64 lanes; the total ends in lane 63 (other lanes hold partials)
+__device__ __forceinline__ float dpp_sum_last(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return v;
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dpp_sum_last(v)), 63));
+}
+
+// sinc(2 pi hv) * 2 pi = sin(2 pi hv) / hv, with its limit 2 pi at hv = 0
+__device__ __forceinline__ float sinc_rev(float s, float hv) {
+  return fabsf(hv) < 1e-4f ? kTwoPi : s * fast_rcp(hv);
+}
+
+// per-thread pixel block of a tile
+template <int TW, int TH, int PPL>
+struct PixelBlock {
+  float pxc[PPL], pyc[PPL], L[PPL];
+  int pix[PPL];   // index into the packed image, -1 if outside
+  __device__ void init(const CamDev& cam, int tx, int ty) {
+    const int lx = threadIdx.x % TW;
+    const int ly0 = (threadIdx.x / TW) * PPL;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      const int x = tx * TW + lx, y = ty * TH + ly0 + q;
+      const bool in = x < cam.width && y < cam.height;
+      pix[q] = in ? (int)(y * cam.width + x) : -1;
+      pxc[q] = (float)x + 0.5f;
+      pyc[q] = (float)y + 0.5f;
+      const float cxn = (pxc[q] - cam.cx) / cam.fx;
+      const float cyn = (pyc[q] - cam.cy) / cam.fy;
+      const float Dx = cam.Rinv_f[0] * cxn + cam.Rinv_f[1] * cyn + cam.Rinv_f[2];
+      const float Dy = cam.Rinv_f[3] * cxn + cam.Rinv_f[4] * cyn + cam.Rinv_f[5];
+      const float Dz = cam.Rinv_f[6] * cxn + cam.Rinv_f[7] * cyn + cam.Rinv_f[8];
+      L[q] = sqrtf(Dx * Dx + Dy * Dy + Dz * Dz);
+    }
+  }
+};
+
+template <int N>
+struct Stage {
+  static constexpr int TS = 5 * N + 4;
+  static constexpr int F = 6 + TS / 4;  // float4 per instance
+  float4 rec[BATCH][6];
+  float4 tab[BATCH][TS / 4];
+  uint32_t id[BATCH];
+};
+
+template <int N, int NT>
+__device__ __forceinline__ void stage_batch(Stage<N>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
+  for (int t = threadIdx.x; t < nb; t += NT) S.id[t] = a.values[b0 + t];
+  __syncthreads();
+  const float4* rec4 = reinterpret_cast<const float4*>(a.records);
+  const float4* tab4 = reinterpret_cast<const float4*>(a.table);
+  constexpr int F = Stage<N>::F;
+  constexpr int T4 = Stage<N>::TS / 4;
+  const int64_t vbase = (int64_t)v * a.P;
+  for (int idx = threadIdx.x; idx < nb * F; idx += NT) {
+    const int j = idx / F, c = idx - j * F;
+    const uint32_t p = S.id[j];
+    if (c < 6)
+      S.rec[j][c] = rec4[(vbase + p) * 6 + c];
+    else
+      S.tab[j][c - 6] = tab4[(int64_t)p * T4 + (c - 6)];
+  }
+  __syncthreads();
+}
+
+// geometry of one (pixel, primitive) pair from a staged record
+struct PairGeom {
+  float dx, dy;
+  float d0, d1, d2, m0, m1, m2;
+  float A, rA, sq, H;
+  float p0, p1, p2, e0, e1, e2;
+};
+
+__device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
+                                          const float4& r4, const float4& r5, float px, float py, PairGeom& g) {
+  g.dx = px - r0.w;
+  g.dy = py - r1.w;
+  g.d0 = __builtin_fmaf(r2.x, g.dy, __builtin_fmaf(r1.x, g.dx, r0.x));
+  g.d1 = __builtin_fmaf(r2.y, g.dy, __builtin_fmaf(r1.y, g.dx, r0.y));
+  g.d2 = __builtin_fmaf(r2.z, g.dy, __builtin_fmaf(r1.z, g.dx, r0.z));
+  g.m0 = __builtin_fmaf(r5.x, g.dy, __builtin_fmaf(r4.x, g.dx, r3.x));
+  g.m1 = __builtin_fmaf(r5.y, g.dy, __builtin_fmaf(r4.y, g.dx, r3.y));
+  g.m2 = __builtin_fmaf(r5.z, g.dy, __builtin_fmaf(r4.z, g.dx, r3.z));
+  g.A = __builtin_fmaf(g.d2, g.d2, __builtin_fmaf(g.d1, g.d1, g.d0 * g.d0));
+  const float M = __builtin_fmaf(g.m2, g.m2, __builtin_fmaf(g.m1, g.m1, g.m0 * g.m0));
+  const float disc = g.A - M;
+  if (!(disc > 0.f)) return false;
+  g.rA = fast_rcp(g.A);
+  g.sq = fast_sqrt(disc);
+  g.H = g.sq * g.rA;
+  g.p0 = (g.d1 * g.m2 - g.d2 * g.m1) * g.rA;
+  g.p1 = (g.d2 * g.m0 - g.d0 * g.m2) * g.rA;
+  g.p2 = (g.d0 * g.m1 - g.d1 * g.m0) * g.rA;
+  g.e0 = g.d0 * g.H;
+  g.e1 = g.d1 * g.H;
+  g.e2 = g.d2 * g.H;
+  return true;
+}
+
+__device__ __forceinline__ float alpha_of(float ahat, float alpha_max) {
+  const float al = ahat > 0.f ? 1.0f - exp2_fast(-ahat * kLog2e) : 0.f;
+  return fminf(al, alpha_max);
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+template <int N, int TW, int TH, int PPL, bool PERSIST, bool COUNT>
+__global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a) {
+  constexpr int NT = TW * TH / PPL;
+  __shared__ Stage<N> S;
+  __shared__ int s_item;
+  unsigned long long npairs = 0;
+  int item = blockIdx.x;
+  while (true) {
+    if (PERSIST) {
+      if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.counters[CNT_QUEUE_FWD], 1ull);
+      __syncthreads();
+      item = s_item;
+      __syncthreads();
+    }
+    if (item >= a.total_tiles) break;
+    const int v = view_of_tile(a.cams, a.V, item);
+    const CamDev& cam = a.cams[v];
+    const int local = item - cam.tile_base;
+    const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
+    PixelBlock<TW, TH, PPL> pb;
+    pb.init(cam, tx, ty);
+    float T[PPL], C0[PPL], C1[PPL], C2[PPL];
+    bool done[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      T[q] = 1.f;
+      C0[q] = C1[q] = C2[q] = 0.f;
+      done[q] = pb.pix[q] < 0;
+    }
+    const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
+    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+      const int nb = (int)min((uint32_t)BATCH, end - b0);
+      __syncthreads();
+      stage_batch<N, NT>(S, a, v, b0, nb);
+      for (int j = 0; j < nb; ++j) {
+        const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
+        const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
+        PairGeom g[PPL];
+        bool hit[PPL];
+        bool any = false;
+        float Q[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          hit[q] = !done[q] && pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q]);
+          any |= hit[q];
+          Q[q] = 0.f;
+          if (COUNT) npairs += hit[q] ? 1 : 0;
+        }
+        if (!any) continue;
+        const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
+#pragma unroll 4
+        for (int k = 0; k < N; ++k) {
+          const float4 w = S.tab[j][k];
+          const float w2 = tabf[4 * N + k];
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) {
+            if (hit[q]) {
+              const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
+              const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
+              const float c = cos_rev(ph);
+              const float sn = sinc_rev(sin_rev(hv), hv);
+              Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
+            }
+          }
+        }
+        const float b2 = tabf[5 * N];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          if (hit[q]) {
+            const float ahat = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
+            const float al = alpha_of(ahat, a.alpha_max);
+            if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
+              const float w = al * T[q];
+              C0[q] = __builtin_fmaf(r2.w, w, C0[q]);
+              C1[q] = __builtin_fmaf(r3.w, w, C1[q]);
+              C2[q] = __builtin_fmaf(r4.w, w, C2[q]);
+              T[q] = T[q] * (1.f - al);
+              if (T[q] < a.t_eps) done[q] = true;
+            }
+          }
+        }
+      }
+      bool mine = true;
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) mine = mine && done[q];
+      if (__syncthreads_and(mine)) break;
+    }
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      if (pb.pix[q] >= 0) {
+        const int64_t px = cam.pix_base + pb.pix[q];
+        a.images[3 * px + 0] = C0[q] + T[q] * a.bg0;
+        a.images[3 * px + 1] = C1[q] + T[q] * a.bg1;
+        a.images[3 * px + 2] = C2[q] + T[q] * a.bg2;
+        a.final_T[px] = T[q];
+      }
+    }
+    if (!PERSIST) break;
+  }
+  if (COUNT) {
+    // one atomic per wave
+    unsigned long long tot = npairs;
+    for (int o = 1; o < 64; o <<= 1) tot += __shfl_xor(tot, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&a.counters[CNT_HIT_PAIRS], tot);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+template <int N, int TW, int TH, int PPL, bool PERSIST>
+__global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a) {
+  constexpr int NT = TW * TH / PPL;
+  constexpr int TS = 5 * N + 4;
+  __shared__ Stage<N> S;
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63;
+  int item = blockIdx.x;
+  while (true) {
+    if (PERSIST) {
+      if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.counters[CNT_QUEUE_BWD], 1ull);
+      __syncthreads();
+      item = s_item;
+      __syncthreads();
+    }
+    if (item >= a.total_tiles) break;
+    const int v = view_of_tile(a.cams, a.V, item);
+    const CamDev& cam = a.cams[v];
+    const int local = item - cam.tile_base;
+    const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
+    PixelBlock<TW, TH, PPL> pb;
+    pb.init(cam, tx, ty);
+    float T[PPL], A0[PPL], A1[PPL], A2[PPL], G0[PPL], G1[PPL], G2[PPL], F0[PPL], F1[PPL], F2[PPL];
+    bool done[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      T[q] = 1.f;
+      A0[q] = A1[q] = A2[q] = 0.f;
+      done[q] = pb.pix[q] < 0;
+      const int64_t px = cam.pix_base + (pb.pix[q] < 0 ? 0 : pb.pix[q]);
+      G0[q] = done[q] ? 0.f : a.dL[3 * px + 0];
+      G1[q] = done[q] ? 0.f : a.dL[3 * px + 1];
+      G2[q] = done[q] ? 0.f : a.dL[3 * px + 2];
+      F0[q] = done[q] ? 0.f : a.images_in[3 * px + 0];
+      F1[q] = done[q] ? 0.f : a.images_in[3 * px + 1];
+      F2[q] = done[q] ? 0.f : a.images_in[3 * px + 2];
+    }
+    const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
+    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
+      const int nb = (int)min((uint32_t)BATCH, end - b0);
+      __syncthreads();
+      stage_batch<N, NT>(S, a, v, b0, nb);
+      for (int j = 0; j < nb; ++j) {
+        const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
+        const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
+        const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
+        PairGeom g[PPL];
+        bool hit[PPL];
+        bool any = false;
+        float Q[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          hit[q] = !done[q] && pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q]);
+          any |= hit[q];
+          Q[q] = 0.f;
+        }
+        if (__ballot(any) == 0) continue;  // wave-uniform
+        // pass 1: the integral (same arithmetic as the forward)
+#pragma unroll 4
+        for (int k = 0; k < N; ++k) {
+          const float4 w = S.tab[j][k];
+          const float w2 = tabf[4 * N + k];
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) {
+            if (hit[q]) {
+              const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
+              const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
+              const float c = cos_rev(ph);
+              const float sn = sinc_rev(sin_rev(hv), hv);
+              Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
+            }
+          }
+        }
+        const float b2 = tabf[5 * N];
+        // blending and d loss / d integral
+        float wq[PPL], gHq[PPL];
+        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;
+        bool live = false;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          wq[q] = 0.f;
+          gHq[q] = 0.f;
+          if (hit[q]) {
+            const float ahat = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
+            const float al = alpha_of(ahat, a.alpha_max);
+            if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
+              const float wt = al * T[q];
+              gc0 = __builtin_fmaf(G0[q], wt, gc0);
+              gc1 = __builtin_fmaf(G1[q], wt, gc1);
+              gc2 = __builtin_fmaf(G2[q], wt, gc2);
+              A0[q] = __builtin_fmaf(r2.w, wt, A0[q]);
+              A1[q] = __builtin_fmaf(r3.w, wt, A1[q]);
+              A2[q] = __builtin_fmaf(r4.w, wt, A2[q]);
+              if (ahat > 0.f && al < a.alpha_max) {
+                const float ta = T[q] * (1.f - al);
+                const float G = G0[q] * (r2.w * ta - (F0[q] - A0[q])) + G1[q] * (r3.w * ta - (F1[q] - A1[q])) +
+                                G2[q] * (r4.w * ta - (F2[q] - A2[q]));
+                wq[q] = G * 2.f * pb.L[q] * g[q].H;       // d loss / d Q
+                gHq[q] = G * 2.f * pb.L[q] * (Q[q] + b2);  // d loss / d H (direct)
+                live = true;
+              }
+              T[q] = T[q] * (1.f - al);
+              if (T[q] < a.t_eps) done[q] = true;
+            }
+          }
+        }
+        const bool live_w = __ballot(live) != 0;
+        const uint32_t p = S.id[j];
+        float* gvrow = a.gview + ((int64_t)v * a.P + p) * kGViewFloats;
+        float* gtrow = a.gtable + (int64_t)p * TS;
+        // colour gradient (also when the integral's gradient is clamped)
+        {
+          const float t0 = wave_total(gc0), t1 = wave_total(gc1), t2 = wave_total(gc2);
+          if (lane == 0 && (t0 != 0.f || t1 != 0.f || t2 != 0.f)) {
+            atomic_add_f32(gvrow + 18, t0);
+            atomic_add_f32(gvrow + 19, t1);
+            atomic_add_f32(gvrow + 20, t2);
+          }
+        }
+        if (!live_w) continue;
+        // pass 2: per hidden unit
+        float gp0[PPL], gp1[PPL], gp2[PPL], ge0[PPL], ge1[PPL], ge2[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) gp0[q] = gp1[q] = gp2[q] = ge0[q] = ge1[q] = ge2[q] = 0.f;
+        float gb2 = 0.f;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) gb2 += wq[q];
+        for (int k = 0; k < N; ++k) {
+          const float4 w = S.tab[j][k];
+          const float w2 = tabf[4 * N + k];
+          float sW2 = 0.f, sBt = 0.f, sWx = 0.f, sWy = 0.f, sWz = 0.f;
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) {
+            if (wq[q] != 0.f) {
+              const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
+              const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
+              const float c = cos_rev(ph), s = sin_rev(ph);
+              const float sh = sin_rev(hv), ch = cos_rev(hv);
+              const float sn = sinc_rev(sh, hv);
+              // d sinc_rev / d hv
+              float dsn;
+              if (fabsf(hv) < 0.02f) {
+                const float h = kTwoPi * hv, h2 = h * h;
+                dsn = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
+              } else {
+                dsn = (kTwoPi * ch - sn) * fast_rcp(hv);
+              }
+              const float gph = -wq[q] * w2 * kTwoPi * s * sn;  // d loss / d ph
+              const float ghv = wq[q] * w2 * c * dsn;          // d loss / d hv
+              sW2 = __builtin_fmaf(wq[q], c * sn, sW2);
+              sBt += gph;
+              sWx = __builtin_fmaf(gph, g[q].p0, __builtin_fmaf(ghv, g[q].e0, sWx));
+              sWy = __builtin_fmaf(gph, g[q].p1, __builtin_fmaf(ghv, g[q].e1, sWy));
+              sWz = __builtin_fmaf(gph, g[q].p2, __builtin_fmaf(ghv, g[q].e2, sWz));
+              gp0[q] = __builtin_fmaf(gph, w.x, gp0[q]);
+              gp1[q] = __builtin_fmaf(gph, w.y, gp1[q]);
+              gp2[q] = __builtin_fmaf(gph, w.z, gp2[q]);
+              ge0[q] = __builtin_fmaf(ghv, w.x, ge0[q]);
+              ge1[q] = __builtin_fmaf(ghv, w.y, ge1[q]);
+              ge2[q] = __builtin_fmaf(ghv, w.z, ge2[q]);
+            }
+          }
+          const float tx_ = wave_total(sWx), ty_ = wave_total(sWy), tz_ = wave_total(sWz);
+          const float tb_ = wave_total(sBt), tw_ = wave_total(sW2);
+          if (lane == 0) {
+            atomic_add_f32(gtrow + 4 * k + 0, tx_);
+            atomic_add_f32(gtrow + 4 * k + 1, ty_);
+            atomic_add_f32(gtrow + 4 * k + 2, tz_);
+            atomic_add_f32(gtrow + 4 * k + 3, tb_);
+            atomic_add_f32(gtrow + 4 * N + k, tw_);
+          }
+        }
+        {
+          const float t = wave_total(gb2);
+          if (lane == 0) atomic_add_f32(gtrow + 5 * N, t);
+        }
+        // chain p', e', H -> d', m' -> record coefficients
+        float R[18];
+#pragma unroll
+        for (int r = 0; r < 18; ++r) R[r] = 0.f;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          if (wq[q] != 0.f) {
+            const PairGeom& G = g[q];
+            // e' = d' H
+            const float gH = gHq[q] + ge0[q] * G.d0 + ge1[q] * G.d1 + ge2[q] * G.d2;
+            float gd0 = ge0[q] * G.H, gd1 = ge1[q] * G.H, gd2 = ge2[q] * G.H;
+            // p' = X rA, X = d' x m'
+            const float gX0 = gp0[q] * G.rA, gX1 = gp1[q] * G.rA, gX2 = gp2[q] * G.rA;
+            const float gA_p = -(gp0[q] * G.p0 + gp1[q] * G.p1 + gp2[q] * G.p2) * G.rA;
+            // H = sq rA, sq = sqrt(A - M)
+            const float gdisc = gH * G.rA * 0.5f * fast_rcp(G.sq);
+            const float gA = gdisc - gH * G.H * G.rA + gA_p;
+            const float gM = -gdisc;
+            // d' (A = d'.d', X = d' x m'),  m' (M = m'.m', X)
+            gd0 += 2.f * gA * G.d0 + (G.m1 * gX2 - G.m2 * gX1);
+            gd1 += 2.f * gA * G.d1 + (G.m2 * gX0 - G.m0 * gX2);
+            gd2 += 2.f * gA * G.d2 + (G.m0 * gX1 - G.m1 * gX0);
+            const float gm0 = 2.f * gM * G.m0 + (gX1 * G.d2 - gX2 * G.d1);
+            const float gm1 = 2.f * gM * G.m1 + (gX2 * G.d0 - gX0 * G.d2);
+            const float gm2 = 2.f * gM * G.m2 + (gX0 * G.d1 - gX1 * G.d0);
+            R[0] += gd0;
+            R[1] += gd1;
+            R[2] += gd2;
+            R[3] = __builtin_fmaf(gd0, G.dx, R[3]);
+            R[4] = __builtin_fmaf(gd1, G.dx, R[4]);
+            R[5] = __builtin_fmaf(gd2, G.dx, R[5]);
+            R[6] = __builtin_fmaf(gd0, G.dy, R[6]);
+            R[7] = __builtin_fmaf(gd1, G.dy, R[7]);
+            R[8] = __builtin_fmaf(gd2, G.dy, R[8]);
+            R[9] += gm0;
+            R[10] += gm1;
+            R[11] += gm2;
+            R[12] = __builtin_fmaf(gm0, G.dx, R[12]);
+            R[13] = __builtin_fmaf(gm1, G.dx, R[13]);
+            R[14] = __builtin_fmaf(gm2, G.dx, R[14]);
+            R[15] = __builtin_fmaf(gm0, G.dy, R[15]);
+            R[16] = __builtin_fmaf(gm1, G.dy, R[16]);
+            R[17] = __builtin_fmaf(gm2, G.dy, R[17]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 18; ++r) {
+          const float t = wave_total(R[r]);
+          if (lane == 0) atomic_add_f32(gvrow + r, t);
+        }
+      }
+      bool mine = true;
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) mine = mine && done[q];
+      if (__syncthreads_and(mine)) break;
+    }
+    if (!PERSIST) break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+struct TileShape {
+  int tw, th, ppl;
+};
+static const TileShape kShapes[] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {8, 8, 1}, {32, 16, 2}, {32, 16, 4}};
+static const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+int supported_tiles(int32_t* triples, int32_t max) {
+  for (int i = 0; i < kNumShapes && i < max; ++i) {
+    triples[3 * i] = kShapes[i].tw;
+    triples[3 * i + 1] = kShapes[i].th;
+    triples[3 * i + 2] = kShapes[i].ppl;
+  }
+  return kNumShapes;
+}
+
+bool tile_supported(int tw, int th, int ppl) {
+  for (int i = 0; i < kNumShapes; ++i)
+    if (kShapes[i].tw == tw && kShapes[i].th == th && kShapes[i].ppl == ppl) return true;
+  return false;
+}
+
+template <typename K>
+static int persistent_grid(K kernel, int threads, int total) {
+  int dev = 0, cus = 0, occ = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0);
+  if (occ < 1) occ = 1;
+  int g = cus * occ;
+  if (g > total) g = total;
+  return g < 1 ? 1 : g;
+}
+
+template <int N, int TW, int TH, int PPL>
+static hipError_t fwd_shape(const RasterArgs& a, bool persist, bool count, hipStream_t st) {
+  constexpr int NT = TW * TH / PPL;
+  if (a.total_tiles <= 0) return hipSuccess;
+  if (persist) {
+    if (count) {
+      auto k = render_fwd_kernel<N, TW, TH, PPL, true, true>;
+      hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
+    } else {
+      auto k = render_fwd_kernel<N, TW, TH, PPL, true, false>;
+      hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
+    }
+  } else {
+    if (count)
+      hipLaunchKernelGGL((render_fwd_kernel<N, TW, TH, PPL, false, true>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((render_fwd_kernel<N, TW, TH, PPL, false, false>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int N, int TW, int TH, int PPL>
+static hipError_t bwd_shape(const RasterArgs& a, bool persist, hipStream_t st) {
+  constexpr int NT = TW * TH / PPL;
+  if (a.total_tiles <= 0) return hipSuccess;
+  if (persist) {
+    auto k = render_bwd_kernel<N, TW, TH, PPL, true>;
+    hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((render_bwd_kernel<N, TW, TH, PPL, false>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t fwd_n(const RasterArgs& a, int tw, int th, int ppl, bool persist, bool count, hipStream_t st) {
+  if (tw == 16 && th == 16 && ppl == 1) return fwd_shape<N, 16, 16, 1>(a, persist, count, st);
+  if (tw == 16 && th == 16 && ppl == 2) return fwd_shape<N, 16, 16, 2>(a, persist, count, st);
+  if (tw == 16 && th == 16 && ppl == 4) return fwd_shape<N, 16, 16, 4>(a, persist, count, st);
+  if (tw == 8 && th == 8 && ppl == 1) return fwd_shape<N, 8, 8, 1>(a, persist, count, st);
+  if (tw == 32 && th == 16 && ppl == 2) return fwd_shape<N, 32, 16, 2>(a, persist, count, st);
+  if (tw == 32 && th == 16 && ppl == 4) return fwd_shape<N, 32, 16, 4>(a, persist, count, st);
+  return hipErrorInvalidValue;
+}
+
+template <int N>
+static hipError_t bwd_n(const RasterArgs& a, int tw, int th, int ppl, bool persist, hipStream_t st) {
+  if (tw == 16 && th == 16 && ppl == 1) return bwd_shape<N, 16, 16, 1>(a, persist, st);
+  if (tw == 16 && th == 16 && ppl == 2) return bwd_shape<N, 16, 16, 2>(a, persist, st);
+  if (tw == 16 && th == 16 && ppl == 4) return bwd_shape<N, 16, 16, 4>(a, persist, st);
+  if (tw == 8 && th == 8 && ppl == 1) return bwd_shape<N, 8, 8, 1>(a, persist, st);
+  if (tw == 32 && th == 16 && ppl == 2) return bwd_shape<N, 32, 16, 2>(a, persist, st);
+  if (tw == 32 && th == 16 && ppl == 4) return bwd_shape<N, 32, 16, 4>(a, persist, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
+                             hipStream_t st) {
+  switch (N) {
+    case 4: return fwd_n<4>(a, tw, th, ppl, persist, count, st);
+    case 8: return fwd_n<8>(a, tw, th, ppl, persist, count, st);
+    case 16: return fwd_n<16>(a, tw, th, ppl, persist, count, st);
+    case 32: return fwd_n<32>(a, tw, th, ppl, persist, count, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_render_bwd(int N, int tw, int th, int ppl, bool persist, const RasterArgs& a, hipStream_t st) {
+  switch (N) {
+    case 4: return bwd_n<4>(a, tw, th, ppl, persist, st);
+    case 8: return bwd_n<8>(a, tw, th, ppl, persist, st);
+    case 16: return bwd_n<16>(a, tw, th, ppl, persist, st);
+    case 32: return bwd_n<32>(a, tw, th, ppl, persist, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// self test of the wave reduction (run by the test-suite on the device)
+// ---------------------------------------------------------------------------
+__global__ void wave_sum_selftest_kernel(const float* in, float* out) {
+  const float v = in[blockIdx.x * 64 + threadIdx.x];
+  const float t = wave_total(v);
+  out[blockIdx.x * 64 + threadIdx.x] = t;
+}
+
+hipError_t launch_wave_sum_selftest(const float* in, float* out, int waves, hipStream_t st) {
+  hipLaunchKernelGGL(wave_sum_selftest_kernel, dim3(waves), dim3(64), 0, st, in, out);
+  return hipGetLastError();
+}
+
+}  // namespace snp

@@ -1,0 +1,217 @@
+// Internal layouts and device helpers shared by the kernels of libsnp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/snp.h"
+
+namespace snp {
+
+constexpr float kTwoPi = 6.283185307179586f;
+constexpr float kInvTwoPi = 0.15915494309189535f;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kEpsPx = 1.0 / 64.0;  // slack of the pixel rectangle, in pixels
+constexpr int kRecFloats = 24;         // per-(view, primitive) record
+constexpr int kGViewFloats = 24;       // per-(view, primitive) gradient record
+constexpr int kMaxCamsPerChunk = 16;   // cameras passed by value per launch
+constexpr int kXiDim = 8;
+constexpr int kCmlpIn = 3 + kXiDim;
+
+// Per-view constants on the device.
+struct CamDev {
+  int32_t width, height, ntx, nty;
+  int32_t tile_base;  // global id of the view's first tile
+  int32_t tile_w, tile_h, pad0;
+  int64_t pix_base;   // index of the view's first pixel in the packed images
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float Rinv_f[9];    // camera -> world, float copy for per-pixel directions
+  float o_f[3];
+  double Rinv[9];     // camera -> world (exact inverse of R, float64)
+  double o[3];        // camera centre -R^-1 t
+};
+
+struct CamChunk {  // kernel argument carrying up to kMaxCamsPerChunk cameras
+  snp_camera cam[kMaxCamsPerChunk];
+  int32_t tile_base[kMaxCamsPerChunk];
+  int64_t pix_base[kMaxCamsPerChunk];
+  int32_t first, count, tile_w, tile_h;
+};
+
+// Counters at layout.counters (uint64 each).
+enum Counter {
+  CNT_INSTANCES = 0,
+  CNT_OVERFLOW = 1,
+  CNT_HIT_PAIRS = 2,
+  CNT_RANGE = 3,
+  CNT_QUEUE_FWD = 4,
+  CNT_QUEUE_BWD = 5,
+  CNT_COUNT = 8
+};
+
+// Table row of a primitive, TS = 5N + 4 floats:
+//   [4k .. 4k+3]   (Wt_k.x, Wt_k.y, Wt_k.z, bt_k)  phase coefficients in revolutions
+//   [4N + k]       W2_k / (2 pi)
+//   [5N]           b2
+inline __host__ __device__ int table_stride(int N) { return 5 * N + 4; }
+
+// Record of a (view, primitive) pair, 6 float4:
+//   q0 (dc.xyz, rx)  q1 (gx.xyz, ry)  q2 (gy.xyz, col.r)
+//   q3 (mc.xyz, col.g)  q4 (hx.xyz, col.b)  q5 (hy.xyz, 0)
+// For a pixel centre (px, py), with dx = px - rx, dy = py - ry:
+//   d' = dc + gx dx + gy dy   ray direction in the ellipsoid's unit-sphere frame
+//   m' = mc + hx dx + hy dy   its moment o' x d'
+// where the direction is the un-normalised camera ray R^-1 (x, y, 1).
+
+template <typename T>
+__device__ __forceinline__ T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// sin / cos of 2 pi x (x in revolutions, |x| <= 256)
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+  // butterfly over the 64 lanes; every lane ends with the total
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+__device__ __forceinline__ void atomic_add_f32(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Global tile id -> view index (V small; linear scan over tile bases).
+__device__ __forceinline__ int view_of_tile(const CamDev* cams, int V, int gtile) {
+  int v = 0;
+  while (v + 1 < V && cams[v + 1].tile_base <= gtile) ++v;
+  return v;
+}
+
+}  // namespace snp
+
+// ---------------------------------------------------------------------------
+// kernel arguments and host launchers (implemented in the .hip files)
+// ---------------------------------------------------------------------------
+namespace snp {
+
+struct ViewArgs {
+  int64_t P;
+  int32_t V;
+  float z_near;
+  int32_t color_mode;
+  const float *centers, *scales, *quats, *colors;
+  const CamDev* cams;
+  float* records;
+  int32_t* rects;
+  uint32_t* depth_bits;
+  uint32_t* tile_counts;
+};
+
+struct CmlpArgs {
+  int64_t P;
+  int32_t V, GS;
+  const float *centers, *xi, *cmlp;
+  const CamDev* cams;
+  const uint32_t* tile_counts;
+  float* records;
+  float* gview;
+  float* g_cmlp;
+  float* g_xi;
+};
+
+struct PreBwdArgs {
+  int64_t P;
+  int32_t V, N, color_mode;
+  float omega0;
+  const float *centers, *scales, *quats, *w1;
+  const CamDev* cams;
+  const float* records;
+  const uint32_t* tile_counts;
+  const float* gview;
+  const float* gtable;
+  snp_grads g;
+};
+
+struct EmitArgs {
+  int64_t P;
+  int32_t V;
+  int64_t capacity;
+  const CamDev* cams;
+  const int32_t* rects;
+  const uint32_t* depth_bits;
+  const uint32_t* tile_counts;
+  const uint32_t* offsets;
+  unsigned long long* keys;
+  uint32_t* values;
+};
+
+struct RasterArgs {
+  const CamDev* cams;
+  int32_t V;
+  int64_t P;
+  int32_t total_tiles;
+  const float* table;
+  const float* records;
+  const uint32_t* values;
+  const uint32_t* ranges;
+  float* images;          // forward output
+  float* final_T;         // forward output
+  const float* images_in; // backward: forward's images
+  const float* dL;        // backward: d loss / d images
+  float* gview;
+  float* gtable;
+  unsigned long long* counters;
+  float t_eps, alpha_min, alpha_max;
+  float bg0, bg1, bg2;
+};
+
+// preprocess.hip
+hipError_t launch_setup_cams(const CamChunk& ch, CamDev* out, hipStream_t st);
+hipError_t launch_prim_table(int N, int64_t P, float omega0, const snp_prims& pr, float* table,
+                             unsigned long long* counters, hipStream_t st);
+hipError_t launch_preprocess_views(const ViewArgs& a, hipStream_t st);
+hipError_t launch_cmlp_fwd(int width, int depth, CmlpArgs a, hipStream_t st);
+hipError_t launch_cmlp_bwd(int width, int depth, CmlpArgs a, hipStream_t st);
+bool cmlp_supported(int width, int depth);
+int cmlp_param_count(int width, int depth);
+hipError_t launch_preprocess_bwd(const PreBwdArgs& a, hipStream_t st);
+// binning.hip
+hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+size_t scan_scratch_bytes(int64_t n);
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* scratch, uint64_t* total_out,
+                              hipStream_t st);
+hipError_t launch_emit(const EmitArgs& a, unsigned long long* counters, hipStream_t st);
+size_t sort_scratch_bytes(int64_t capacity);
+hipError_t radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1, int64_t capacity,
+                      const unsigned long long* counters, int key_bits, void* scratch, hipStream_t st);
+int radix_passes(int key_bits);
+hipError_t launch_ranges(const unsigned long long* keys, const unsigned long long* counters, int64_t capacity,
+                         uint32_t* ranges, int64_t n_tiles, hipStream_t st);
+// raster.hip
+int supported_tiles(int32_t* triples, int32_t max);
+bool tile_supported(int tw, int th, int ppl);
+hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
+                             hipStream_t st);
+hipError_t launch_render_bwd(int N, int tw, int th, int ppl, bool persist, const RasterArgs& a, hipStream_t st);
+hipError_t launch_wave_sum_selftest(const float* in, float* out, int waves, hipStream_t st);
+// loss.hip
+size_t loss_scratch_bytes();
+hipError_t launch_l1(const float* img, const float* tgt, int64_t n, double n_norm, float* grad, double* partials,
+                     double* out, hipStream_t st);
+hipError_t zero_f32(float* p, int64_t n, hipStream_t st);
+hipError_t zero_counters(unsigned long long* p, int n, hipStream_t st);
+hipError_t zero_counter(unsigned long long* p, hipStream_t st);
+
+}  // namespace snp

@@ -1,0 +1,75 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function
+include/snp.h declares, and validates arguments on the host (nothing is
+enqueued for an invalid call, so no GPU is needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import synthetic as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "snp.h")
+
+
+def _lib():
+    from paper_2510_08491_amd import _lib
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(snp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib().lib()
+    names = declared_functions()
+    assert "snp_render_forward" in names and "snp_render_backward" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(_lib().EXPORTED)
+
+
+def _cfg(**kw):
+    from paper_2510_08491_amd import RenderConfig
+    return RenderConfig(**kw).to_c()
+
+
+def test_layout_and_validation():
+    L = _lib()
+    lib = L.lib()
+    from paper_2510_08491_amd.render import camera_array
+    cams = camera_array(S.make_cameras([(64, 64), (100, 40)], seed=1))
+    lay = L.SnpLayout()
+    assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=16)), 1000, 2, cams, 5000, C.byref(lay)) == L.SNP_OK
+    assert lay.capacity == 5000 and lay.total_tiles == 16 + 7 * 3 and lay.table_stride == 84
+    offs = [lay.counters, lay.loss, lay.cams, lay.table, lay.records, lay.rects, lay.depth_bits, lay.tile_counts,
+            lay.offsets, lay.keys, lay.values, lay.ranges, lay.gview, lay.gtable]
+    assert all(o % 256 == 0 for o in offs) and max(offs) < lay.bytes
+    # unsupported / invalid configurations are rejected before any device work
+    assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
+    assert lib.snp_workspace_layout(C.byref(_cfg(tile_w=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
+    assert lib.snp_workspace_layout(C.byref(_cfg(alpha_max=1.0)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
+    assert lib.snp_workspace_layout(C.byref(_cfg()), 0, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
+    assert lib.snp_workspace_layout(C.byref(_cfg()), 10, 0, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
+    assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=1, cmlp_width=24, cmlp_depth=2)), 10, 2, cams, 100,
+                                    C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
+    bad = camera_array(S.make_cameras([(64, 64)], seed=1))
+    bad[0].fx = 0.0
+    assert lib.snp_workspace_layout(C.byref(_cfg()), 10, 1, bad, 100, C.byref(lay)) == L.SNP_ERR_INVALID
+    # a call whose layout does not match its arguments is rejected
+    assert lib.snp_workspace_layout(C.byref(_cfg()), 1000, 2, cams, 5000, C.byref(lay)) == L.SNP_OK
+    assert lib.snp_bin(C.byref(_cfg()), 999, 2, cams, C.c_void_p(256), C.byref(lay), None) == L.SNP_ERR_INVALID
+    assert lib.snp_bin(C.byref(_cfg()), 1000, 2, cams, None, C.byref(lay), None) == L.SNP_ERR_INVALID
+    assert lib.snp_status_string(L.SNP_ERR_CAPACITY).decode().startswith("tile instances")
+
+
+def test_supported_tiles():
+    lib = _lib().lib()
+    arr = (C.c_int32 * 64)()
+    n = lib.snp_supported_tiles(arr, 21)
+    triples = [tuple(arr[3 * i:3 * i + 3]) for i in range(n)]
+    assert (16, 16, 1) in triples and all(tw * th % (64 * ppl) == 0 for tw, th, ppl in triples)

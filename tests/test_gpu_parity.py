@@ -1,0 +1,253 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: tile lists, sort order, rectangles and depth keys bit-exact; images and
+transmittance within 1e-4 max abs; gradients within 1e-3 (max error over a
+tensor relative to its largest entry, and elementwise on entries above 1% of
+it); hit-pair counts equal up to silhouette pixels whose float32 and float64
+discriminants disagree in sign."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle.grad import autograd_loss_and_grads
+from oracle.keys import project_all, sorted_instances, tile_lists, tile_ranges
+from oracle.render import render_pixels, render_view
+from tests.gpu_helpers import config_for, grad_close, options_for, run_backward, run_forward, say
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    say(f"[gpu-test] {request.node.name}")
+    yield
+    torch.cuda.synchronize()
+
+
+def _check_keys(fw, scene, cams, cfg):
+    lists = tile_lists(scene, cams, cfg.tile_w, cfg.tile_h, cfg.z_near)
+    keys, vals = sorted_instances(lists)
+    ranges = tile_ranges(lists)
+    assert fw["instances"] == len(keys)
+    assert np.array_equal(fw["keys"], keys)
+    assert np.array_equal(fw["values"], vals)
+    assert np.array_equal(fw["ranges"], ranges)
+    for v, cam in enumerate(cams):
+        pr = project_all(scene, cam, cfg.tile_w, cfg.tile_h, cfg.z_near)
+        ne = pr["nonempty"]
+        assert np.array_equal(fw["tile_counts"][v], pr["n_tiles"].astype(np.int32))
+        assert np.array_equal(fw["rects"][v][ne], pr["rect"][ne].astype(np.int32))
+        assert np.array_equal(fw["depth_bits"][v][ne], pr["depth_bits"][ne])
+
+
+def _check_images(fw, scene, cams, cfg, tol=IMG_TOL):
+    opts = options_for(cfg)
+    pairs = 0
+    for v, cam in enumerate(cams):
+        ref = render_view(scene, cam, opts)
+        err = np.max(np.abs(fw["images"][v] - ref["image"]))
+        terr = np.max(np.abs(fw["T"][v] - ref["T"]))
+        say(f"  view {v} {cam.width}x{cam.height}: image err {err:.2e}, T err {terr:.2e}")
+        assert err <= tol and terr <= tol
+        pairs += ref["hit_pairs"]
+    say(f"  hit pairs gpu {fw['hit_pairs']} oracle {pairs}")
+    assert abs(fw["hit_pairs"] - pairs) <= 1e-3 * pairs + 2
+
+
+def test_wave_reduction_selftest():
+    import ctypes as C
+    from paper_2510_08491_amd import _lib
+    x = torch.randn(64 * 8, device="cuda")
+    y = torch.empty_like(x)
+    _lib.check(_lib.lib().snp_selftest_wave_sum(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), 8,
+                                                 C.c_void_p(torch.cuda.current_stream().cuda_stream)), "selftest")
+    torch.cuda.synchronize()
+    ref = x.view(8, 64).double().sum(1)
+    assert torch.allclose(y.view(8, 64)[:, 0].double(), ref, atol=1e-4)
+
+
+def test_c1_keys_and_image():
+    cfg0, scene, cams, _ = S.make_workload("C1")
+    cfg = config_for(scene)
+    fw = run_forward(scene, cams, cfg)
+    _check_keys(fw, scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+
+
+@pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 2), (16, 16, 4), (8, 8, 1), (32, 16, 2), (32, 16, 4)])
+def test_tile_shapes_ragged_image(tile):
+    """A 200 x 120 image (not a multiple of any tile) with 1500 primitives."""
+    scene = S.custom_scene(1500, 16, seed=51)
+    cams = S.make_cameras([(200, 120)], seed=52)
+    cfg = config_for(scene, tile=tile)
+    fw = run_forward(scene, cams, cfg)
+    _check_keys(fw, scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+
+
+@pytest.mark.parametrize("N", [4, 8, 32])
+def test_hidden_widths(N):
+    scene = S.custom_scene(800, N, seed=60 + N, omega0=30.0 if N == 32 else 10.0)
+    cams = S.make_cameras([(96, 80)], seed=61)
+    cfg = config_for(scene, tile=(16, 16, 2))
+    fw = run_forward(scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+
+
+def test_multiview_batched_and_persistent():
+    scene = S.custom_scene(1200, 16, seed=71)
+    cams = S.make_cameras([(96, 64), (130, 70), (64, 64), (40, 90)], seed=72)
+    a = run_forward(scene, cams, config_for(scene, persistent=0))
+    b = run_forward(scene, cams, config_for(scene, persistent=1))
+    _check_keys(a, scene, cams, config_for(scene))
+    for v in range(len(cams)):
+        assert np.array_equal(a["images"][v], b["images"][v])
+    _check_images(b, scene, cams, config_for(scene, persistent=1))
+
+
+@pytest.mark.parametrize("width,depth,N", [(16, 2, 16), (32, 2, 16), (32, 3, 32)])
+def test_colour_mlp_image(width, depth, N):
+    scene = S.custom_scene(1500, N, color_mode=1, cmlp_width=width, cmlp_depth=depth, seed=81)
+    cams = S.make_cameras([(120, 90), (64, 48)], seed=82)
+    cfg = config_for(scene, tile=(16, 16, 2))
+    fw = run_forward(scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+
+
+def test_dense_scene_early_termination():
+    scene = S.custom_scene(400, 8, seed=12, scale_lo=0.15, scale_hi=0.4)
+    scene["w2"] = scene["w2"] * np.float32(20.0)
+    cams = S.make_cameras([(48, 48)], seed=13)
+    for t_eps in (1e-4, 0.0):
+        cfg = config_for(scene, t_eps=t_eps)
+        fw = run_forward(scene, cams, cfg)
+        assert np.sum(fw["T"][0] < 1e-3) > 10
+        _check_images(fw, scene, cams, cfg)
+
+
+def test_background_alpha_min_alpha_max():
+    scene = S.custom_scene(600, 8, seed=91, scale_lo=0.1, scale_hi=0.3)
+    scene["w2"] = scene["w2"] * np.float32(8.0)
+    cams = S.make_cameras([(64, 56)], seed=92)
+    cfg = config_for(scene, alpha_min=1.0 / 255.0, alpha_max=0.5, bg=(0.25, 0.5, 1.0))
+    fw = run_forward(scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+
+
+def _grad_parity(scene, cams, targets, cfg, keys):
+    fw = run_forward(scene, cams, cfg)
+    loss, g = run_backward(fw, targets)
+    L_ref, g_ref, _ = autograd_loss_and_grads(scene, cams, targets, options_for(cfg))
+    say(f"  loss gpu {loss:.8f} oracle {L_ref:.8f}")
+    assert abs(loss - L_ref) <= 1e-5
+    for k in keys:
+        ok, err, erel = grad_close(g[k], g_ref[k])
+        say(f"  grad {k}: max err / max {err:.2e}, elementwise rel {erel:.2e}")
+        assert ok, k
+
+
+def test_c1_gradients():
+    _, scene, cams, targets = S.make_workload("C1")
+    cfg = config_for(scene)
+    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
+
+
+@pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 4), (32, 16, 2)])
+def test_gradients_multiview_tiles(tile):
+    scene = S.custom_scene(400, 8, seed=101)
+    cams = S.make_cameras([(72, 56), (48, 64)], seed=102)
+    targets = S.make_targets(cams, seed=103)
+    cfg = config_for(scene, tile=tile, persistent=1)
+    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
+
+
+def test_colour_mlp_gradients():
+    scene = S.custom_scene(300, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=111)
+    cams = S.make_cameras([(64, 48), (48, 40), (56, 56)], seed=112)
+    targets = S.make_targets(cams, seed=113)
+    cfg = config_for(scene, tile=(16, 16, 2))
+    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
+
+
+@pytest.mark.parametrize("name", ["C2", "C3"])
+def test_full_size_sampled(name):
+    """Full-size configurations: sampled pixels against the oracle computed
+    pixel by pixel, and the instance lists of sampled tiles bit-exact."""
+    cfg0, scene, cams, _ = S.make_workload(name)
+    cfg = config_for(scene, tile=(16, 16, 2))
+    fw = run_forward(scene, cams, cfg)
+    cam = cams[0]
+    rng = np.random.default_rng(7)
+    cols = rng.integers(0, cam.width, 24)
+    rows = rng.integers(0, cam.height, 24)
+    pr = project_all(scene, cam, cfg.tile_w, cfg.tile_h, cfg.z_near)
+    c, t, h = render_pixels(scene, cam, cols, rows, options_for(cfg), proj=pr)
+    err = np.max(np.abs(fw["images"][0][rows, cols] - c))
+    terr = np.max(np.abs(fw["T"][0][rows, cols] - t))
+    say(f"  {name}: sampled image err {err:.2e}, T err {terr:.2e}, instances {fw['instances']}, pairs {fw['hit_pairs']}")
+    assert err <= IMG_TOL and terr <= IMG_TOL
+    ntx = (cam.width + cfg.tile_w - 1) // cfg.tile_w
+    ids = np.nonzero(pr["nonempty"])[0]
+    tr = pr["trect"][ids]
+    for g in rng.integers(0, fw["ranges"].shape[0], 6):
+        ty, tx = divmod(int(g), ntx)
+        sel = (tr[:, 0] <= tx) & (tx <= tr[:, 1]) & (tr[:, 2] <= ty) & (ty <= tr[:, 3])
+        lst = sorted(zip(pr["depth_bits"][ids][sel].tolist(), ids[sel].tolist()))
+        s, e = fw["ranges"][g]
+        assert fw["values"][s:e].tolist() == [p for _, p in lst]
+
+
+def test_capacity_overflow_is_reported_then_grown():
+    import paper_2510_08491_amd as snp
+    from paper_2510_08491_amd import _lib
+    _, scene, cams, _ = S.make_workload("C1")
+    cfg = config_for(scene)
+    params = snp.params_to_device(scene)
+    rast = snp.Rasterizer(cfg, scene["P"], cams, capacity=16)
+    rast.preprocess(params)
+    rast.bin()
+    code, inst, _ = rast.read_status(raise_on_error=False)
+    assert code == _lib.SNP_ERR_CAPACITY and inst > 16
+    fw = run_forward(scene, cams, cfg, capacity=16)
+    assert fw["rast"].capacity >= fw["instances"]
+    _check_images(fw, scene, cams, cfg)
+
+
+def test_graph_replay_matches_eager():
+    import paper_2510_08491_amd as snp
+    scene = S.custom_scene(600, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=121)
+    cams = S.make_cameras([(80, 64), (64, 64), (96, 48)], seed=122)
+    targets = S.make_targets(cams, seed=123)
+    cfg = config_for(scene, tile=(16, 16, 2), persistent=1)
+    params = snp.params_to_device(scene)
+    rast = snp.Rasterizer(cfg, scene["P"], cams)
+    rast.prepare(params)
+    tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()
+    n = float(tg.numel())
+    # eager step through the C ABI
+    images, T = rast.new_images()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dL = torch.empty_like(images)
+    grads = snp.zeros_like_params(params)
+    rast.step(params, images, T, tg, n, loss, dL, grads)
+    torch.cuda.synchronize()
+    ref_img, ref_g, ref_loss = images.clone(), {k: v.clone() for k, v in grads.items()}, loss.item()
+    step = snp.GraphStep(rast, params, tg, n)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        step.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(step.images, ref_img), rep
+        assert abs(step.loss.item() - ref_loss) <= 1e-12
+        for k in ref_g:
+            ok, err, erel = grad_close(step.grads[k].cpu().numpy(), ref_g[k].cpu().numpy(), rel=1e-4, elem_rel=1e-3)
+            assert ok, (rep, k, err, erel)
+        del junk
+    # and the eager result itself matches the oracle
+    fw_imgs = rast.split_images(ref_img)
+    opts = options_for(cfg)
+    for v, cam in enumerate(cams):
+        assert np.max(np.abs(fw_imgs[v].cpu().numpy() - render_view(scene, cam, opts)["image"])) <= IMG_TOL

@@ -203,7 +203,7 @@ def test_tile_lists_cover_hits_and_are_ordered():
                 assert all((z[i], lst[i]) < (z[i + 1], lst[i + 1]) for i in range(len(lst) - 1))
                 s, e = ranges[g]
                 assert list(vals[s:e]) == lst
-                assert np.all((keys[s:e] >> np.uint64(32)) == g)
+                assert np.all((keys[s:e] >> np.uint64(31)) == g)
             rows, cols = np.mgrid[0:cam.height, 0:cam.width]
             o, d = pixel_rays(cam, cols.ravel(), rows.ravel())
             Rs = quat_to_rotmat(scene["quats"].astype(float))
