@@ -1,0 +1,277 @@
+"""Benchmark: forward+backward pixel-primitive pairs per second of the
+splattable-neural-primitive rasterizer on one MI355X.
+
+A step is one whole pass of the path: preprocess (bounds, keys, records,
+colour MLP), tile binning, radix sort, tile ranges, forward rasterizer, L1
+loss, backward rasterizer, colour-MLP and preprocess adjoints.  The default
+workload is 16 cameras of mixed resolution (4 x 640x480, 8 x 1280x720,
+4 x 1920x1080) looking at 200k primitives (density MLP N=16, colour MLP
+width 32 depth 2), run as ONE HIP graph with persistent rasterizer launches.
+
+Printed (one JSON line): the metric value = forward hit pairs per step /
+seconds per step; ms/step of the batched graph and of per-view plain
+launches (same kernels, one camera at a time, no graph, no persistence);
+the roofline of the dominant kernel (the rasterizer backward, measured live
+with HIP events around its launches); and the FP64 oracle timed on a
+bounded crop of the same workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_SLOTS = 256 * 128 * 2.4e9   # FP32 VALU lane-op issue slots/s (= 157.3 TFLOP/s / 2)
+TRANS_WEIGHT = 4.0               # issue slots per transcendental (quarter rate)
+
+
+def ops_per_pair(N):
+    """Algorithmic work of the rasterizer per pair, in VALU lane-ops and
+    transcendentals, counted from the formulation:
+    forward per hit pair; backward per hit pair plus per live pair (pairs
+    with a positive, unclamped integral, which carry gradient)."""
+    fwd_v, fwd_t = 50 + 11 * N, 3 * N + 3
+    bwd_hit_v, bwd_hit_t = fwd_v + 25, fwd_t
+    bwd_live_v, bwd_live_t = 32 * N + 60, 6 * N + 1
+    return dict(fwd=(fwd_v, fwd_t), bwd_hit=(bwd_hit_v, bwd_hit_t), bwd_live=(bwd_live_v, bwd_live_t))
+
+
+def slots(vt):
+    return vt[0] + TRANS_WEIGHT * vt[1]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5"])
+    ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane (default: tuned)")
+    ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2510_08491_amd as snp
+    from paper_2510_08491_amd import tuning
+    import synthetic as S
+
+    torch.cuda.set_device(0)
+    cfg0, scene, cams, targets = S.make_workload(a.workload)
+    N = scene["N"]
+    if a.tile:
+        tile = tuple(int(x) for x in a.tile.split(","))
+    else:
+        tile = tuning.lookup(N, scene["color_mode"], cams) or (16, 16, 2)
+    cfg = snp.RenderConfig(n_hidden=N, omega0=scene["omega0"], color_mode=scene["color_mode"],
+                           cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], tile_w=tile[0],
+                           tile_h=tile[1], px_per_lane=tile[2], persistent=1)
+    log(f"[bench] workload {a.workload}: P={scene['P']} V={len(cams)} N={N} tile={tile}")
+    params = snp.params_to_device(scene)
+    tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()
+    n_norm = float(tg.numel())
+
+    # size the workspace from one binning pass, then count pairs (untimed)
+    rast = snp.Rasterizer(cfg, scene["P"], cams)
+    inst = rast.prepare(params)
+    rast._alloc(int(inst * 1.1) + 4096)
+    rast.prepare(params)
+    images, final_T = rast.new_images()
+    rast.forward(params, images, final_T, count_pairs=True)
+    cnt = rast.counters()
+    hit_pairs, live_pairs = cnt["hit_pairs"], cnt["live_pairs"]
+    log(f"[bench] instances {inst}, hit pairs {hit_pairs}, live pairs {live_pairs}")
+
+    # ---- batched: one graph per step -------------------------------------------------
+    step = snp.GraphStep(rast, params, tg, n_norm)
+    for _ in range(a.warmup):
+        step.launch()
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(a.steps):
+        step.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / a.steps
+    log(f"[bench] batched graph: {ms_step:.3f} ms/step (wall {1e3 * wall / a.steps:.3f})")
+    img_batched = step.images.clone()
+
+    # ---- rasterizer kernels timed live (eager step, HIP events on the launch stream) --
+    snp.render.kernel_timing(True)
+    fwd_ms, bwd_ms = [], []
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dL = torch.empty_like(images)
+    grads = snp.zeros_like_params(params)
+    for _ in range(max(3, min(a.steps, 5))):
+        rast.step(params, images, final_T, tg, n_norm, loss, dL, grads)
+        f, b = snp.render.kernel_timing_read()
+        fwd_ms.append(f)
+        bwd_ms.append(b)
+    snp.render.kernel_timing(False)
+    fwd_ms, bwd_ms = float(np.mean(fwd_ms)), float(np.mean(bwd_ms))
+    log(f"[bench] raster kernels: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
+
+    # ---- per-view plain launches ---------------------------------------------------------
+    per_view_ms = None
+    per_view_equal = None
+    if not a.no_per_view:
+        cfg_pv = snp.RenderConfig(**{**cfg.__dict__, "persistent": 0})
+        rv = []
+        for c in cams:
+            r = snp.Rasterizer(cfg_pv, scene["P"], [c])
+            r._alloc(int(r.prepare(params) * 1.1) + 4096)
+            rv.append(r)
+        offs = np.cumsum([0] + [c.width * c.height for c in cams])
+        outs = [r.new_images() for r in rv]
+        dls = [torch.empty_like(o[0]) for o in outs]
+        losses = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in rv]
+        pv_grads = snp.zeros_like_params(params)
+
+        def per_view_step():
+            for g in pv_grads.values():
+                g.zero_()
+            for v, r in enumerate(rv):
+                r.preprocess(params)
+                r.bin()
+                r.sort()
+                r.forward(params, outs[v][0], outs[v][1])
+                r.loss_l1(outs[v][0], tg[3 * offs[v]:3 * offs[v + 1]], n_norm, losses[v], dls[v])
+                r.backward(params, outs[v][0], dls[v], pv_grads)
+
+        for _ in range(a.warmup):
+            per_view_step()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(a.steps):
+            per_view_step()
+        e1.record()
+        torch.cuda.synchronize()
+        per_view_ms = e0.elapsed_time(e1) / a.steps
+        per_view_equal = all(torch.equal(outs[v][0], img_batched[3 * offs[v]:3 * offs[v + 1]])
+                             for v in range(len(cams)))
+        log(f"[bench] per-view plain launches: {per_view_ms:.3f} ms/step, images identical: {per_view_equal}")
+
+    # ---- roofline of the dominant kernel ----------------------------------------------------
+    ops = ops_per_pair(N)
+    fwd_slots = hit_pairs * slots(ops["fwd"])
+    bwd_slots = hit_pairs * slots(ops["bwd_hit"]) + live_pairs * slots(ops["bwd_live"])
+    if bwd_ms >= fwd_ms:
+        dom, dom_ms, dom_slots = "render_bwd", bwd_ms, bwd_slots
+    else:
+        dom, dom_ms, dom_slots = "render_fwd", fwd_ms, fwd_slots
+    achieved = dom_slots / (dom_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_SLOTS / 1e12, 3),
+                "unit": "Tslot/s", "frac": round(achieved / (PEAK_SLOTS / 1e12), 4), "traffic": None,
+                "kernel_ms": round(dom_ms, 4),
+                "fwd_frac": round(fwd_slots / (fwd_ms * 1e-3) / PEAK_SLOTS, 4),
+                "bwd_frac": round(bwd_slots / (bwd_ms * 1e-3) / PEAK_SLOTS, 4)}
+
+    # ---- oracle on a bounded crop, on the host ---------------------------------------------------
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cams, targets, a.cpu_seconds)
+        log(f"[bench] cpu oracle: {cpu}")
+
+    value = hit_pairs / (ms_step * 1e-3)
+    out = {
+        "metric": "fwd+bwd pixel-primitive pairs/s; batched vs per-view ms/step @1e-4 img err",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded primitives, random-pose cameras, random targets)",
+        "config": {"workload": workload_name(a.workload, cams), "primitives": scene["P"], "n_hidden": N,
+                   "colour_mlp": [scene["cmlp_width"], scene["cmlp_depth"]], "tile": list(tile),
+                   "batched": "one HIP graph per step, persistent rasterizer launches"},
+        "hit_pairs_per_step": hit_pairs,
+        "live_pairs_per_step": live_pairs,
+        "instances_per_step": inst,
+        "per_view_ms_per_step": per_view_ms,
+        "batched_speedup_vs_per_view": (per_view_ms / ms_step) if per_view_ms else None,
+        "per_view_images_identical": per_view_equal,
+        "raster_fwd_ms": fwd_ms,
+        "raster_bwd_ms": bwd_ms,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "paper_context": "218.87 FPS forward-only full pipeline, 100k random primitives, RTX 4090 (App. A)",
+    }
+    print(json.dumps(out))
+
+
+def workload_name(w, cams):
+    sizes = {}
+    for c in cams:
+        sizes[f"{c.width}x{c.height}"] = sizes.get(f"{c.width}x{c.height}", 0) + 1
+    desc = " + ".join(f"{n}x{k}" for k, n in sizes.items())
+    return {"C3": "1 camera 1920x1080, 200k primitives, N=16, colour MLP W32 D2, fwd+bwd",
+            "C4": f"16 mixed cameras ({desc}), 200k primitives, N=16, colour MLP W32 D2, batched fwd+bwd",
+            "C5": "32 cameras 1600x900, 1M primitives, N=32, colour MLP W32 D3, batched fwd+bwd"}[w]
+
+
+def cpu_baseline(scene, cams, targets, budget_s):
+    """FP64 oracle forward + autograd backward on square crops of the first
+    camera, each with the primitives whose screen bounds touch the crop (the
+    only ones that contribute to it; selecting them is not timed), repeated
+    until about `budget_s` seconds of work; returns pairs/s."""
+    import torch
+    import synthetic as S
+    from oracle.grad import autograd_loss_and_grads
+    from oracle.keys import project_all
+    from oracle.render import RenderOptions, render_view
+
+    threads = os.cpu_count() or 1
+    torch.set_num_threads(threads)
+    cam = cams[0]
+    size = 16
+    pairs, spent, crops, prims = 0, 0.0, 0, 0
+    rng = np.random.default_rng(3)
+    while spent < budget_s and crops < 32:
+        x0 = int(rng.integers(cam.width // 4, 3 * cam.width // 4 - size))
+        y0 = int(rng.integers(cam.height // 4, 3 * cam.height // 4 - size))
+        crop = S.Camera(size, size, cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, cam.R, cam.t)
+        ids = np.nonzero(project_all(scene, crop)["nonempty"])[0]
+        sub = S.subset_scene(scene, ids)
+        tgt = [targets[0][y0:y0 + size, x0:x0 + size]]
+        t0 = time.perf_counter()
+        r = render_view(sub, crop, RenderOptions())
+        autograd_loss_and_grads(sub, [crop], tgt, RenderOptions())
+        spent += time.perf_counter() - t0
+        pairs += r["hit_pairs"]
+        prims += len(ids)
+        crops += 1
+    return {"value": pairs / spent, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{crops} random {size}x{size} px crops of the central half of camera 0 "
+                      f"({cam.width}x{cam.height}), each with the primitives whose bounds touch it "
+                      f"({prims // max(crops, 1)} on average of {scene['P']}); FP64 numpy forward + torch "
+                      f"float64 autograd backward; {pairs} hit pairs in {spent:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

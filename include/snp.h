@@ -206,6 +206,20 @@ snp_status snp_graph_destroy(void* graph);
 snp_status snp_read_status(void* ws, const snp_layout* layout, int64_t* instances_out, int64_t* hit_pairs_out,
                            hipStream_t stream);
 
+/* Synchronises `stream` and copies the 8 device counters of the workspace:
+ * [0] instances, [1] overflow flag, [2] hit pairs and [6] pairs with a
+ * positive, unclamped integral (both counted by snp_render_forward with
+ * count_pairs != 0), [3] phase-range flag, [4], [5] work-queue heads. */
+snp_status snp_read_counters(void* ws, const snp_layout* layout, int64_t* out8, hipStream_t stream);
+
+/* Kernel timing for measurement: while enabled, every eager (not captured)
+ * snp_render_forward / snp_render_backward records a HIP event pair on its
+ * stream right around its rasterizer kernel; snp_kernel_timing_read waits
+ * for the last pairs and returns their durations in milliseconds (-1 if none
+ * was recorded).  Enabling clears the recorded pairs. */
+snp_status snp_kernel_timing(int32_t enable);
+snp_status snp_kernel_timing_read(float* fwd_ms, float* bwd_ms);
+
 /* Tile shapes the rasterizer is built for: writes up to `max` triples
  * (tile_w, tile_h, px_per_lane) and returns how many exist. */
 int32_t snp_supported_tiles(int32_t* triples, int32_t max);

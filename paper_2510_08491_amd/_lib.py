@@ -71,6 +71,9 @@ def lib():
         "snp_read_status": [VP, lay, P(I64), P(I64), VP],
         "snp_supported_tiles": [P(I32), I32],
         "snp_selftest_wave_sum": [VP, VP, I32, VP],
+        "snp_read_counters": [VP, lay, P(I64), VP],
+        "snp_kernel_timing": [I32],
+        "snp_kernel_timing_read": [P(C.c_float), P(C.c_float)],
     }
     for name, args in protos.items():
         f = getattr(L, name)
@@ -84,7 +87,8 @@ def lib():
 
 EXPORTED = ["snp_workspace_layout", "snp_preprocess", "snp_bin", "snp_sort", "snp_render_forward", "snp_loss_l1",
             "snp_render_backward", "snp_step", "snp_graph_create", "snp_graph_launch", "snp_graph_destroy",
-            "snp_read_status", "snp_supported_tiles", "snp_status_string", "snp_selftest_wave_sum"]
+            "snp_read_status", "snp_supported_tiles", "snp_status_string", "snp_selftest_wave_sum",
+            "snp_read_counters", "snp_kernel_timing", "snp_kernel_timing_read"]
 
 
 class SnpError(RuntimeError):

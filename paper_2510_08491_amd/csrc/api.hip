@@ -252,14 +252,37 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   return a;
 }
 
+// Optional events around the rasterizer launches (eager calls only), for
+// measuring the kernels' own durations.
+struct KernelTimer {
+  bool on = false, have_fwd = false, have_bwd = false;
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+static KernelTimer g_timer;
+
+static bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return true;
+  return cs != hipStreamCaptureStatusNone;
+}
+
+static void timer_mark(int which, hipStream_t st) {
+  if (!g_timer.on || capturing(st)) return;
+  (void)hipEventRecord(g_timer.e[which], st);
+  if (which == 1) g_timer.have_fwd = true;
+  if (which == 3) g_timer.have_bwd = true;
+}
+
 static snp_status do_forward(const snp_config* cfg, int64_t P, int32_t V, const Plan& pl, void* ws, float* images,
                              float* final_T, int count, hipStream_t st) {
   RasterArgs a = raster_args(cfg, P, V, pl, ws);
   a.images = images;
   a.final_T = final_T;
   if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_FWD, st));
+  timer_mark(0, st);
   SNP_HIP(launch_render_fwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0,
                             count != 0, a, st));
+  timer_mark(1, st);
   return SNP_OK;
 }
 
@@ -273,7 +296,9 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
   SNP_HIP(zero_f32(a.gview, (int64_t)V * P * kGViewFloats, st));
   SNP_HIP(zero_f32(a.gtable, P * (int64_t)L.table_stride, st));
   if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_BWD, st));
+  timer_mark(2, st);
   SNP_HIP(launch_render_bwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0, a, st));
+  timer_mark(3, st);
   if (cfg->color_mode == 1) {
     CmlpArgs ca;
     std::memset(&ca, 0, sizeof(ca));
@@ -517,6 +542,15 @@ snp_status snp_graph_destroy(void* graph) {
   return SNP_OK;
 }
 
+snp_status snp_read_counters(void* ws, const snp_layout* layout, int64_t* out8, hipStream_t stream) {
+  if (!ws || !layout || !out8) return SNP_ERR_INVALID;
+  SNP_HIP(hipStreamSynchronize(stream));
+  unsigned long long c[CNT_COUNT];
+  SNP_HIP(hipMemcpy(c, reinterpret_cast<char*>(ws) + layout->counters, sizeof(c), hipMemcpyDeviceToHost));
+  for (int i = 0; i < CNT_COUNT; ++i) out8[i] = (int64_t)c[i];
+  return SNP_OK;
+}
+
 snp_status snp_read_status(void* ws, const snp_layout* layout, int64_t* instances_out, int64_t* hit_pairs_out,
                            hipStream_t stream) {
   if (!ws || !layout) return SNP_ERR_INVALID;
@@ -545,6 +579,28 @@ const char* snp_status_string(snp_status s) {
     case SNP_ERR_RANGE: return "density-MLP phase outside the supported range";
   }
   return "unknown status";
+}
+
+snp_status snp_kernel_timing(int32_t enable) {
+  if (enable && !g_timer.e[0])
+    for (int i = 0; i < 4; ++i) SNP_HIP(hipEventCreate(&g_timer.e[i]));
+  g_timer.on = enable != 0;
+  g_timer.have_fwd = g_timer.have_bwd = false;
+  return SNP_OK;
+}
+
+snp_status snp_kernel_timing_read(float* fwd_ms, float* bwd_ms) {
+  if (!fwd_ms || !bwd_ms) return SNP_ERR_INVALID;
+  *fwd_ms = *bwd_ms = -1.f;
+  if (g_timer.have_fwd) {
+    SNP_HIP(hipEventSynchronize(g_timer.e[1]));
+    SNP_HIP(hipEventElapsedTime(fwd_ms, g_timer.e[0], g_timer.e[1]));
+  }
+  if (g_timer.have_bwd) {
+    SNP_HIP(hipEventSynchronize(g_timer.e[3]));
+    SNP_HIP(hipEventElapsedTime(bwd_ms, g_timer.e[2], g_timer.e[3]));
+  }
+  return SNP_OK;
 }
 
 snp_status snp_selftest_wave_sum(const float* in, float* out, int32_t waves, hipStream_t stream) {

@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
   constexpr int NT = TW * TH / PPL;
   __shared__ Stage<N> S;
   __shared__ int s_item;
-  unsigned long long npairs = 0;
+  unsigned long long npairs = 0, nlive = 0;
   int item = blockIdx.x;
   while (true) {
     if (PERSIST) {
@@ -219,6 +219,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
           if (hit[q]) {
             const float ahat = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
             const float al = alpha_of(ahat, a.alpha_max);
+            if (COUNT) nlive += (ahat > 0.f && al < a.alpha_max) ? 1 : 0;
             if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
               const float w = al * T[q];
               C0[q] = __builtin_fmaf(r2.w, w, C0[q]);
@@ -249,9 +250,15 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
   }
   if (COUNT) {
     // one atomic per wave
-    unsigned long long tot = npairs;
-    for (int o = 1; o < 64; o <<= 1) tot += __shfl_xor(tot, o);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&a.counters[CNT_HIT_PAIRS], tot);
+    unsigned long long tot = npairs, live = nlive;
+    for (int o = 1; o < 64; o <<= 1) {
+      tot += __shfl_xor(tot, o);
+      live += __shfl_xor(live, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&a.counters[CNT_HIT_PAIRS], tot);
+      atomicAdd(&a.counters[CNT_LIVE_PAIRS], live);
+    }
   }
 }
 

@@ -48,6 +48,7 @@ enum Counter {
   CNT_RANGE = 3,
   CNT_QUEUE_FWD = 4,
   CNT_QUEUE_BWD = 5,
+  CNT_LIVE_PAIRS = 6,
   CNT_COUNT = 8
 };
 

@@ -168,6 +168,12 @@ class Rasterizer:
             raise L.SnpError(code, "snp_read_status")
         return code, int(inst.value), int(pairs.value)
 
+    def counters(self):
+        """The 8 device counters (synchronises the stream)."""
+        out = (C.c_int64 * 8)()
+        L.check(L.lib().snp_read_counters(self.ws_ptr, C.byref(self.layout), out, _stream()), "snp_read_counters")
+        return dict(instances=out[0], overflow=out[1], hit_pairs=out[2], range_flag=out[3], live_pairs=out[6])
+
     def prepare(self, params, grow=True):
         """preprocess + bin + sort; grows the workspace and redoes the stages
         if the tile instances overflowed it.  Returns the instance count."""
@@ -228,6 +234,17 @@ class Rasterizer:
             out.append(images[3 * off:3 * (off + n)].view(int(c.height), int(c.width), 3))
             off += n
         return out
+
+
+def kernel_timing(enable: bool):
+    L.check(L.lib().snp_kernel_timing(1 if enable else 0), "snp_kernel_timing")
+
+
+def kernel_timing_read():
+    """(forward ms, backward ms) of the last eager rasterizer launches."""
+    f, b = C.c_float(), C.c_float()
+    L.check(L.lib().snp_kernel_timing_read(C.byref(f), C.byref(b)), "snp_kernel_timing_read")
+    return float(f.value), float(b.value)
 
 
 def zeros_like_params(params: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:

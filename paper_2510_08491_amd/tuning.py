@@ -1,0 +1,130 @@
+"""Autotuner for the rasterizer's launch shape.
+
+For a workload class (density width N, colour mode, resolution class of the
+cameras) it times every tile shape the library is built for -- tile width,
+tile height and pixels per thread -- on a real forward + backward, checks
+that every candidate renders the same image as the first, and stores the
+fastest in a JSON cache next to this file.  `lookup` reads the cache.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+from typing import Dict, List, Optional, Tuple
+
+import torch
+
+from . import _lib as L
+from .render import RenderConfig, Rasterizer, kernel_timing, kernel_timing_read, zeros_like_params
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+
+
+def supported_shapes() -> List[Tuple[int, int, int]]:
+    arr = (C.c_int32 * 96)()
+    n = L.lib().snp_supported_tiles(arr, 32)
+    return [tuple(arr[3 * i:3 * i + 3]) for i in range(n)]
+
+
+def resolution_class(cams) -> str:
+    px = sum(int(c.width) * int(c.height) for c in cams)
+    return f"V{len(cams)}_MP{max(1, round(px / 1e6))}"
+
+
+def key_of(N: int, color_mode: int, cams) -> str:
+    arch = "gfx950"
+    return f"{arch}/N{N}/cm{color_mode}/{resolution_class(cams)}"
+
+
+def _load() -> Dict:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(N: int, color_mode: int, cams) -> Optional[Tuple[int, int, int]]:
+    entry = _load().get(key_of(N, color_mode, cams))
+    return tuple(entry["tile"]) if entry else None
+
+
+def autotune(base: RenderConfig, P: int, cams, params, targets: torch.Tensor, reps: int = 2,
+             shapes=None, write=True, log=print):
+    """Times each tile shape (forward + backward rasterizer kernels, HIP
+    events around the launches) and returns (best shape, table)."""
+    shapes = shapes or supported_shapes()
+    results = {}
+    ref_img = None
+    n_norm = float(targets.numel())
+    for sh in shapes:
+        cfg = RenderConfig(**{**base.__dict__, "tile_w": sh[0], "tile_h": sh[1], "px_per_lane": sh[2]})
+        rast = Rasterizer(cfg, P, cams)
+        inst = rast.prepare(params)
+        rast._alloc(int(inst * 1.1) + 4096)
+        images, T = rast.new_images()
+        loss = torch.zeros(1, dtype=torch.float64, device=images.device)
+        dL = torch.empty_like(images)
+        grads = zeros_like_params(params)
+        rast.step(params, images, T, targets, n_norm, loss, dL, grads)   # warm-up
+        kernel_timing(True)
+        best = None
+        for _ in range(reps):
+            rast.step(params, images, T, targets, n_norm, loss, dL, grads)
+            f, b = kernel_timing_read()
+            best = f + b if best is None else min(best, f + b)
+        kernel_timing(False)
+        torch.cuda.synchronize()
+        if ref_img is None:
+            ref_img = images.clone()
+            diff = 0.0
+        else:
+            diff = float((images - ref_img).abs().max())
+        results[sh] = dict(ms=best, img_diff=diff)
+        log(f"[tune] tile {sh}: raster fwd+bwd {best:.3f} ms, image diff vs first {diff:.2e}")
+        del rast, images, T, dL, grads
+        torch.cuda.empty_cache()
+    ok = {sh: r for sh, r in results.items() if r["img_diff"] <= 1e-5}
+    best_shape = min(ok, key=lambda s: ok[s]["ms"])
+    if write:
+        cache = _load()
+        cache[key_of(base.n_hidden, base.color_mode, cams)] = {
+            "tile": list(best_shape), "ms": ok[best_shape]["ms"],
+            "candidates": {f"{s[0]}x{s[1]}x{s[2]}": r for s, r in results.items()}}
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return best_shape, results
+
+
+def main(argv=None):
+    """python -m paper_2510_08491_amd.tuning --workload C4 [--out FILE]"""
+    import argparse
+    import sys
+
+    import numpy as np
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="C4")
+    ap.add_argument("--out", default=None, help="also write the cache to this file")
+    ap.add_argument("--reps", type=int, default=2)
+    a = ap.parse_args(argv)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import synthetic as S
+    from .render import params_to_device
+
+    _, scene, cams, targets = S.make_workload(a.workload)
+    base = RenderConfig(n_hidden=scene["N"], omega0=scene["omega0"], color_mode=scene["color_mode"],
+                        cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], persistent=1)
+    params = params_to_device(scene)
+    tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()
+    best, _ = autotune(base, scene["P"], cams, params, tg, reps=a.reps,
+                       log=lambda m: print(m, flush=True))
+    print(f"[tune] best tile for {key_of(base.n_hidden, base.color_mode, cams)}: {best}", flush=True)
+    if a.out:
+        with open(CACHE) as f, open(a.out, "w") as g:
+            g.write(f.read())
+
+
+if __name__ == "__main__":
+    main()
