@@ -70,6 +70,7 @@ def main(argv=None):
     import torch
     import paper_2510_08491_amd as snp
     from paper_2510_08491_amd import tuning
+    import paper_2510_08491_amd.render as rmod
     import synthetic as S
 
     torch.cuda.set_device(0)
@@ -118,17 +119,17 @@ def main(argv=None):
     img_batched = step.images.clone()
 
     # ---- rasterizer kernels timed live (eager step, HIP events on the launch stream) --
-    snp.render.kernel_timing(True)
+    rmod.kernel_timing(True)
     fwd_ms, bwd_ms = [], []
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     dL = torch.empty_like(images)
     grads = snp.zeros_like_params(params)
     for _ in range(max(3, min(a.steps, 5))):
         rast.step(params, images, final_T, tg, n_norm, loss, dL, grads)
-        f, b = snp.render.kernel_timing_read()
+        f, b = rmod.kernel_timing_read()
         fwd_ms.append(f)
         bwd_ms.append(b)
-    snp.render.kernel_timing(False)
+    rmod.kernel_timing(False)
     fwd_ms, bwd_ms = float(np.mean(fwd_ms)), float(np.mean(bwd_ms))
     log(f"[bench] raster kernels: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
 

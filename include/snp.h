@@ -126,6 +126,7 @@ typedef struct {
   size_t gview;           /* backward: per-(view, primitive) gradient records */
   size_t gtable;          /* backward: per-primitive table gradients */
   size_t loss;            /* loss partial sums (float64) */
+  size_t disc_coef;       /* per-(view, primitive) 6 float64 coefficients of the ray discriminant */
   int64_t capacity;       /* tile-instance capacity */
   int32_t table_stride;   /* floats per table row */
   int32_t total_tiles;    /* tiles over all views */

@@ -38,7 +38,7 @@ class SnpGrads(C.Structure):
 class SnpLayout(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in
                 ("bytes", "cams", "table", "records", "rects", "depth_bits", "tile_counts", "offsets", "keys",
-                 "values", "ranges", "counters", "gview", "gtable", "loss")] + \
+                 "values", "ranges", "counters", "gview", "gtable", "loss", "disc_coef")] + \
                [("capacity", C.c_int64), ("table_stride", C.c_int32), ("total_tiles", C.c_int32)]
 
 

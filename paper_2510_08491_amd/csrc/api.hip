@@ -93,6 +93,7 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   L.cams = take(sizeof(CamDev) * (size_t)V);
   L.table = take(sizeof(float) * (size_t)P * TS);
   L.records = take(sizeof(float) * (size_t)VP * kRecFloats);
+  L.disc_coef = take(sizeof(double) * 6 * (size_t)VP);
   L.rects = take(sizeof(int32_t) * 4 * (size_t)VP);
   L.depth_bits = take(sizeof(uint32_t) * (size_t)VP);
   L.tile_counts = take(sizeof(uint32_t) * (size_t)VP);
@@ -172,6 +173,7 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
   va.rects = wsp<int32_t>(ws, L.rects);
   va.depth_bits = wsp<uint32_t>(ws, L.depth_bits);
   va.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
+  va.disc_coef = wsp<double>(ws, L.disc_coef);
   SNP_HIP(launch_preprocess_views(va, st));
   if (cfg->color_mode == 1) {
     CmlpArgs ca;
@@ -242,6 +244,7 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   a.ranges = wsp<uint32_t>(ws, L.ranges);
   a.gview = wsp<float>(ws, L.gview);
   a.gtable = wsp<float>(ws, L.gtable);
+  a.disc_coef = wsp<double>(ws, L.disc_coef);
   a.counters = wsp<unsigned long long>(ws, L.counters);
   a.t_eps = cfg->t_eps;
   a.alpha_min = cfg->alpha_min;
@@ -383,6 +386,7 @@ static bool same_layout(const snp_layout& a, const snp_layout& b) {
          a.rects == b.rects && a.depth_bits == b.depth_bits && a.tile_counts == b.tile_counts &&
          a.offsets == b.offsets && a.keys == b.keys && a.values == b.values && a.ranges == b.ranges &&
          a.counters == b.counters && a.gview == b.gview && a.gtable == b.gtable && a.loss == b.loss &&
+         a.disc_coef == b.disc_coef &&
          a.capacity == b.capacity && a.table_stride == b.table_stride && a.total_tiles == b.total_tiles;
 }
 

@@ -260,6 +260,14 @@ __global__ void __launch_bounds__(256) preprocess_views_kernel(ViewArgs a) {
       r4[3] = make_float4((float)mc[0], (float)mc[1], (float)mc[2], cg);
       r4[4] = make_float4((float)hx[0], (float)hx[1], (float)hx[2], cb);
       r4[5] = make_float4((float)hy[0], (float)hy[1], (float)hy[2], 0.f);
+      auto dot = [](const double* u, const double* w) { return u[0] * w[0] + u[1] * w[1] + u[2] * w[2]; };
+      double* dq = a.disc_coef + i * 6;
+      dq[0] = dot(dc, dc) - dot(mc, mc);
+      dq[1] = 2.0 * (dot(dc, gx) - dot(mc, hx));
+      dq[2] = 2.0 * (dot(dc, gy) - dot(mc, hy));
+      dq[3] = dot(gx, gx) - dot(hx, hx);
+      dq[4] = 2.0 * (dot(gx, gy) - dot(hx, hy));
+      dq[5] = dot(gy, gy) - dot(hy, hy);
     }
   }
   a.rects[4 * i + 0] = rect[0];

@@ -77,31 +77,38 @@ struct PixelBlock {
   }
 };
 
-template <int N>
+// LDS stage of one batch; the backward also stages the float64
+// discriminant coefficients (3 float4 = 6 doubles per instance).
+template <int N, bool BWD>
 struct Stage {
   static constexpr int TS = 5 * N + 4;
-  static constexpr int F = 6 + TS / 4;  // float4 per instance
+  static constexpr int DQ4 = BWD ? 3 : 0;
+  static constexpr int F = 6 + TS / 4 + DQ4;  // float4 per instance
   float4 rec[BATCH][6];
   float4 tab[BATCH][TS / 4];
+  float4 dq[BWD ? BATCH : 1][3];
   uint32_t id[BATCH];
 };
 
-template <int N, int NT>
-__device__ __forceinline__ void stage_batch(Stage<N>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
+template <int N, bool BWD, int NT>
+__device__ __forceinline__ void stage_batch(Stage<N, BWD>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
   for (int t = threadIdx.x; t < nb; t += NT) S.id[t] = a.values[b0 + t];
   __syncthreads();
   const float4* rec4 = reinterpret_cast<const float4*>(a.records);
   const float4* tab4 = reinterpret_cast<const float4*>(a.table);
-  constexpr int F = Stage<N>::F;
-  constexpr int T4 = Stage<N>::TS / 4;
+  const float4* dq4 = reinterpret_cast<const float4*>(a.disc_coef);
+  constexpr int F = Stage<N, BWD>::F;
+  constexpr int T4 = Stage<N, BWD>::TS / 4;
   const int64_t vbase = (int64_t)v * a.P;
   for (int idx = threadIdx.x; idx < nb * F; idx += NT) {
     const int j = idx / F, c = idx - j * F;
     const uint32_t p = S.id[j];
     if (c < 6)
       S.rec[j][c] = rec4[(vbase + p) * 6 + c];
-    else
+    else if (c < 6 + T4)
       S.tab[j][c - 6] = tab4[(int64_t)p * T4 + (c - 6)];
+    else if (BWD)
+      S.dq[j][c - 6 - T4] = dq4[(vbase + p) * 3 + (c - 6 - T4)];
   }
   __syncthreads();
 }
@@ -114,8 +121,11 @@ struct PairGeom {
   float p0, p1, p2, e0, e1, e2;
 };
 
+// dq: float64 discriminant coefficients (backward only, else null): pairs
+// within 1% of A of the silhouette take their discriminant from them.
 __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
-                                          const float4& r4, const float4& r5, float px, float py, PairGeom& g) {
+                                          const float4& r4, const float4& r5, float px, float py, PairGeom& g,
+                                          const double* dq = nullptr) {
   g.dx = px - r0.w;
   g.dy = py - r1.w;
   g.d0 = __builtin_fmaf(r2.x, g.dy, __builtin_fmaf(r1.x, g.dx, r0.x));
@@ -126,7 +136,11 @@ __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, co
   g.m2 = __builtin_fmaf(r5.z, g.dy, __builtin_fmaf(r4.z, g.dx, r3.z));
   g.A = __builtin_fmaf(g.d2, g.d2, __builtin_fmaf(g.d1, g.d1, g.d0 * g.d0));
   const float M = __builtin_fmaf(g.m2, g.m2, __builtin_fmaf(g.m1, g.m1, g.m0 * g.m0));
-  const float disc = g.A - M;
+  float disc = g.A - M;
+  if (dq && fabsf(disc) < 0.01f * g.A) {
+    const double x = g.dx, y = g.dy;
+    disc = (float)(dq[0] + x * (dq[1] + dq[3] * x + dq[4] * y) + y * (dq[2] + dq[5] * y));
+  }
   if (!(disc > 0.f)) return false;
   g.rA = fast_rcp(g.A);
   g.sq = fast_sqrt(disc);
@@ -151,7 +165,7 @@ __device__ __forceinline__ float alpha_of(float ahat, float alpha_max) {
 template <int N, int TW, int TH, int PPL, bool PERSIST, bool COUNT>
 __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH / PPL;
-  __shared__ Stage<N> S;
+  __shared__ Stage<N, false> S;
   __shared__ int s_item;
   unsigned long long npairs = 0, nlive = 0;
   int item = blockIdx.x;
@@ -181,7 +195,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
       const int nb = (int)min((uint32_t)BATCH, end - b0);
       __syncthreads();
-      stage_batch<N, NT>(S, a, v, b0, nb);
+      stage_batch<N, decltype(S)::DQ4 != 0, NT>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
@@ -269,7 +283,7 @@ template <int N, int TW, int TH, int PPL, bool PERSIST>
 __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH / PPL;
   constexpr int TS = 5 * N + 4;
-  __shared__ Stage<N> S;
+  __shared__ Stage<N, true> S;
   __shared__ int s_item;
   const int lane = threadIdx.x & 63;
   int item = blockIdx.x;
@@ -306,7 +320,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
       const int nb = (int)min((uint32_t)BATCH, end - b0);
       __syncthreads();
-      stage_batch<N, NT>(S, a, v, b0, nb);
+      stage_batch<N, decltype(S)::DQ4 != 0, NT>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
@@ -317,7 +331,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
         float Q[PPL];
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-          hit[q] = !done[q] && pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q]);
+          hit[q] = !done[q] && pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q],
+                                         reinterpret_cast<const double*>(S.dq[j]));
           any |= hit[q];
           Q[q] = 0.f;
         }

@@ -65,6 +65,12 @@ inline __host__ __device__ int table_stride(int N) { return 5 * N + 4; }
 //   d' = dc + gx dx + gy dy   ray direction in the ellipsoid's unit-sphere frame
 //   m' = mc + hx dx + hy dy   its moment o' x d'
 // where the direction is the un-normalised camera ray R^-1 (x, y, 1).
+// The discriminant A - M = |d'|^2 - |m'|^2 as a float64 quadratic form in the
+// same offsets is kept beside the record (6 doubles c0..c5):
+//   disc = c0 + dx (c1 + c3 dx + c4 dy) + dy (c2 + c5 dy)
+// The backward evaluates it for pairs close to the silhouette, where the
+// float32 difference A - M has too few correct digits for the 1/sqrt(disc)
+// factor of the geometry gradient.
 
 template <typename T>
 __device__ __forceinline__ T* at(void* base, size_t off) {
@@ -118,6 +124,7 @@ struct ViewArgs {
   int32_t* rects;
   uint32_t* depth_bits;
   uint32_t* tile_counts;
+  double* disc_coef;
 };
 
 struct CmlpArgs {
@@ -173,6 +180,7 @@ struct RasterArgs {
   const float* dL;        // backward: d loss / d images
   float* gview;
   float* gtable;
+  const double* disc_coef;  // backward: float64 discriminant near silhouettes
   unsigned long long* counters;
   float t_eps, alpha_min, alpha_max;
   float bg0, bg1, bg2;

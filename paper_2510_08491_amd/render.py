@@ -313,6 +313,6 @@ class SplatRender(torch.autograd.Function):
         return tuple(out)
 
 
-def render(rast: Rasterizer, params: Dict[str, torch.Tensor]):
+def splat_render(rast: Rasterizer, params: Dict[str, torch.Tensor]):
     """Differentiable render: returns (images packed per view, final_T)."""
     return SplatRender.apply(rast, *[params.get(k) for k in PARAM_KEYS])

@@ -146,10 +146,14 @@ def _grad_parity(scene, cams, targets, cfg, keys):
     L_ref, g_ref, _ = autograd_loss_and_grads(scene, cams, targets, options_for(cfg))
     say(f"  loss gpu {loss:.8f} oracle {L_ref:.8f}")
     assert abs(loss - L_ref) <= 1e-5
+    bad = []
     for k in keys:
         ok, err, erel = grad_close(g[k], g_ref[k])
-        say(f"  grad {k}: max err / max {err:.2e}, elementwise rel {erel:.2e}")
-        assert ok, k
+        worst = np.unravel_index(np.argmax(np.abs(g[k] - g_ref[k])), g[k].shape)
+        say(f"  grad {k}: max err / max {err:.2e}, elementwise rel {erel:.2e}, worst at {worst}")
+        if not ok:
+            bad.append(k)
+    assert not bad, bad
 
 
 def test_c1_gradients():
