@@ -150,3 +150,27 @@ def test_autograd_matches_finite_differences_colour_mlp():
     cams = S.make_cameras([(32, 32), (24, 32)], seed=16)
     targets = S.make_targets(cams, seed=17)
     _grad_check(scene, cams, targets, ["centers", "quats", "cmlp", "xi", "w1"], n_per_key=5)
+
+
+def test_colour_mlp_identity_weights():
+    """Colour MLP with identity hidden layers: colour = sigmoid(relu(dir)), dir =
+    normalize(x_B - o); with zero weights it is sigmoid(output bias).  Pins the
+    packing (each layer W (out x in, row-major) then b) and the activations."""
+    from oracle.color import primitive_colors
+    from oracle.geometry import camera_center
+    scene = S.custom_scene(20, 8, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=131)
+    cam = S.make_cameras([(32, 32)], seed=132)[0]
+    W0 = np.zeros((16, 11)); W0[:11, :11] = np.eye(11)
+    W1 = np.eye(16)
+    W2 = np.zeros((3, 16)); W2[:, :3] = np.eye(3)
+    vec = np.concatenate([W0.ravel(), np.zeros(16), W1.ravel(), np.zeros(16), W2.ravel(), np.zeros(3)])
+    scene["cmlp"] = np.tile(vec, (20, 1)).astype(np.float32)
+    dirv = scene["centers"].astype(float) - camera_center(cam)
+    dirv /= np.linalg.norm(dirv, axis=1, keepdims=True)
+    expect = 1.0 / (1.0 + np.exp(-np.maximum(dirv, 0.0)))
+    assert np.max(np.abs(primitive_colors(scene, cam) - expect)) < 1e-12
+    bias = np.array([0.3, -1.2, 2.0])
+    vec2 = np.zeros_like(vec); vec2[-3:] = bias
+    scene["cmlp"] = np.tile(vec2, (20, 1)).astype(np.float32)
+    expect2 = 1.0 / (1.0 + np.exp(-bias.astype(np.float32).astype(float)))
+    assert np.max(np.abs(primitive_colors(scene, cam) - expect2)) < 1e-12
