@@ -79,26 +79,27 @@ struct PixelBlock {
 
 // LDS stage of one batch; the backward also stages the float64
 // discriminant coefficients (3 float4 = 6 doubles per instance).
-template <int N, bool BWD>
+template <int N, bool BWD, int B = BATCH>
 struct Stage {
+  static constexpr int NB = B;
   static constexpr int TS = 5 * N + 4;
   static constexpr int DQ4 = BWD ? 3 : 0;
   static constexpr int F = 6 + TS / 4 + DQ4;  // float4 per instance
-  float4 rec[BATCH][6];
-  float4 tab[BATCH][TS / 4];
-  float4 dq[BWD ? BATCH : 1][3];
-  uint32_t id[BATCH];
+  float4 rec[B][6];
+  float4 tab[B][TS / 4];
+  float4 dq[BWD ? B : 1][3];
+  uint32_t id[B];
 };
 
-template <int N, bool BWD, int NT>
-__device__ __forceinline__ void stage_batch(Stage<N, BWD>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
+template <int N, bool BWD, int NT, int B>
+__device__ __forceinline__ void stage_batch(Stage<N, BWD, B>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
   for (int t = threadIdx.x; t < nb; t += NT) S.id[t] = a.values[b0 + t];
   __syncthreads();
   const float4* rec4 = reinterpret_cast<const float4*>(a.records);
   const float4* tab4 = reinterpret_cast<const float4*>(a.table);
   const float4* dq4 = reinterpret_cast<const float4*>(a.disc_coef);
-  constexpr int F = Stage<N, BWD>::F;
-  constexpr int T4 = Stage<N, BWD>::TS / 4;
+  constexpr int F = Stage<N, BWD, B>::F;
+  constexpr int T4 = Stage<N, BWD, B>::TS / 4;
   const int64_t vbase = (int64_t)v * a.P;
   for (int idx = threadIdx.x; idx < nb * F; idx += NT) {
     const int j = idx / F, c = idx - j * F;
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
     for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
       const int nb = (int)min((uint32_t)BATCH, end - b0);
       __syncthreads();
-      stage_batch<N, decltype(S)::DQ4 != 0, NT>(S, a, v, b0, nb);
+      stage_batch<N, decltype(S)::DQ4 != 0, NT, decltype(S)::NB>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
@@ -279,13 +280,45 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
+// sum over each row of 16 lanes; every lane of the row ends with its row's sum
+__device__ __forceinline__ float dpp_row_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
+  return v;
+}
+
+// adds the wave's sum of v into an LDS accumulator: row sums, then one LDS
+// atomic per row (4 lanes)
+__device__ __forceinline__ void wave_accumulate(float* slot, float v, int lane) {
+  v = dpp_row_sum(v);
+  if ((lane & 15) == 0) atomicAdd(slot, v);
+}
+
+template <int N>
+struct BwdBatch {
+  static constexpr int value = N >= 16 ? 32 : BATCH;
+};
+
+// Per (instance, pixel) the backward needs, for every hidden unit k,
+//   cs_k = cos(ph_k) sinc(hv_k),  ss_k = sin(ph_k) sinc(hv_k),  cd_k = cos(ph_k) sinc'(hv_k)
+// (sinc in the revolution form sin(2 pi hv) / hv).  When N * PPL <= 32 they
+// are kept in registers from the first unit loop (which needs cos and sinc
+// anyway for the integral), so the second loop has no transcendentals;
+// otherwise the second loop recomputes them.
 template <int N, int TW, int TH, int PPL, bool PERSIST>
 __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH / PPL;
   constexpr int TS = 5 * N + 4;
-  __shared__ Stage<N, true> S;
+  constexpr int NB = BwdBatch<N>::value;
+  constexpr int ACC = TS + kGViewFloats;  // per instance: table grads, then record grads
+  constexpr bool CACHE = N * PPL <= 32;
+  __shared__ Stage<N, true, NB> S;
+  __shared__ float s_acc[NB][ACC];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63;
+  for (int idx = threadIdx.x; idx < NB * ACC; idx += NT) (&s_acc[0][0])[idx] = 0.f;
   int item = blockIdx.x;
   while (true) {
     if (PERSIST) {
@@ -317,14 +350,15 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
       F2[q] = done[q] ? 0.f : a.images_in[3 * px + 2];
     }
     const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
-    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
-      const int nb = (int)min((uint32_t)BATCH, end - b0);
+    for (uint32_t b0 = start; b0 < end; b0 += NB) {
+      const int nb = (int)min((uint32_t)NB, end - b0);
       __syncthreads();
-      stage_batch<N, decltype(S)::DQ4 != 0, NT>(S, a, v, b0, nb);
+      stage_batch<N, true, NT, NB>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
         const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
+        float* acc = s_acc[j];
         PairGeom g[PPL];
         bool hit[PPL];
         bool any = false;
@@ -337,8 +371,9 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
           Q[q] = 0.f;
         }
         if (__ballot(any) == 0) continue;  // wave-uniform
-        // pass 1: the integral (same arithmetic as the forward)
-#pragma unroll 4
+        float cs[CACHE ? N : 1][PPL], ss[CACHE ? N : 1][PPL], cd[CACHE ? N : 1][PPL];
+        // pass 1: the integral (same arithmetic as the forward), caching the unit terms
+#pragma unroll
         for (int k = 0; k < N; ++k) {
           const float4 w = S.tab[j][k];
           const float w2 = tabf[4 * N + k];
@@ -348,8 +383,22 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
               const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
               const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
               const float c = cos_rev(ph);
-              const float sn = sinc_rev(sin_rev(hv), hv);
+              const float sh = sin_rev(hv);
+              const float sn = sinc_rev(sh, hv);
               Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
+              if constexpr (CACHE) {
+                const float s = sin_rev(ph), ch = cos_rev(hv);
+                float dsn;
+                if (fabsf(hv) < 0.02f) {
+                  const float h = kTwoPi * hv, h2 = h * h;
+                  dsn = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
+                } else {
+                  dsn = (kTwoPi * ch - sn) * fast_rcp(hv);
+                }
+                cs[k][q] = c * sn;
+                ss[k][q] = s * sn;
+                cd[k][q] = c * dsn;
+              }
             }
           }
         }
@@ -386,20 +435,11 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
             }
           }
         }
-        const bool live_w = __ballot(live) != 0;
-        const uint32_t p = S.id[j];
-        float* gvrow = a.gview + ((int64_t)v * a.P + p) * kGViewFloats;
-        float* gtrow = a.gtable + (int64_t)p * TS;
         // colour gradient (also when the integral's gradient is clamped)
-        {
-          const float t0 = wave_total(gc0), t1 = wave_total(gc1), t2 = wave_total(gc2);
-          if (lane == 0 && (t0 != 0.f || t1 != 0.f || t2 != 0.f)) {
-            atomic_add_f32(gvrow + 18, t0);
-            atomic_add_f32(gvrow + 19, t1);
-            atomic_add_f32(gvrow + 20, t2);
-          }
-        }
-        if (!live_w) continue;
+        wave_accumulate(acc + TS + 18, gc0, lane);
+        wave_accumulate(acc + TS + 19, gc1, lane);
+        wave_accumulate(acc + TS + 20, gc2, lane);
+        if (__ballot(live) == 0) continue;
         // pass 2: per hidden unit
         float gp0[PPL], gp1[PPL], gp2[PPL], ge0[PPL], ge1[PPL], ge2[PPL];
 #pragma unroll
@@ -407,6 +447,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
         float gb2 = 0.f;
 #pragma unroll
         for (int q = 0; q < PPL; ++q) gb2 += wq[q];
+#pragma unroll
         for (int k = 0; k < N; ++k) {
           const float4 w = S.tab[j][k];
           const float w2 = tabf[4 * N + k];
@@ -414,22 +455,32 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
 #pragma unroll
           for (int q = 0; q < PPL; ++q) {
             if (wq[q] != 0.f) {
-              const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
-              const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
-              const float c = cos_rev(ph), s = sin_rev(ph);
-              const float sh = sin_rev(hv), ch = cos_rev(hv);
-              const float sn = sinc_rev(sh, hv);
-              // d sinc_rev / d hv
-              float dsn;
-              if (fabsf(hv) < 0.02f) {
-                const float h = kTwoPi * hv, h2 = h * h;
-                dsn = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
+              float csq, ssq, cdq;
+              if constexpr (CACHE) {
+                csq = cs[k][q];
+                ssq = ss[k][q];
+                cdq = cd[k][q];
               } else {
-                dsn = (kTwoPi * ch - sn) * fast_rcp(hv);
+                const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
+                const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
+                const float c = cos_rev(ph), s = sin_rev(ph);
+                const float sh = sin_rev(hv), ch = cos_rev(hv);
+                const float sn = sinc_rev(sh, hv);
+                float dsn;
+                if (fabsf(hv) < 0.02f) {
+                  const float h = kTwoPi * hv, h2 = h * h;
+                  dsn = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
+                } else {
+                  dsn = (kTwoPi * ch - sn) * fast_rcp(hv);
+                }
+                csq = c * sn;
+                ssq = s * sn;
+                cdq = c * dsn;
               }
-              const float gph = -wq[q] * w2 * kTwoPi * s * sn;  // d loss / d ph
-              const float ghv = wq[q] * w2 * c * dsn;          // d loss / d hv
-              sW2 = __builtin_fmaf(wq[q], c * sn, sW2);
+              const float ww = wq[q] * w2;
+              const float gph = -kTwoPi * ww * ssq;  // d loss / d ph
+              const float ghv = ww * cdq;            // d loss / d hv
+              sW2 = __builtin_fmaf(wq[q], csq, sW2);
               sBt += gph;
               sWx = __builtin_fmaf(gph, g[q].p0, __builtin_fmaf(ghv, g[q].e0, sWx));
               sWy = __builtin_fmaf(gph, g[q].p1, __builtin_fmaf(ghv, g[q].e1, sWy));
@@ -442,20 +493,13 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
               ge2[q] = __builtin_fmaf(ghv, w.z, ge2[q]);
             }
           }
-          const float tx_ = wave_total(sWx), ty_ = wave_total(sWy), tz_ = wave_total(sWz);
-          const float tb_ = wave_total(sBt), tw_ = wave_total(sW2);
-          if (lane == 0) {
-            atomic_add_f32(gtrow + 4 * k + 0, tx_);
-            atomic_add_f32(gtrow + 4 * k + 1, ty_);
-            atomic_add_f32(gtrow + 4 * k + 2, tz_);
-            atomic_add_f32(gtrow + 4 * k + 3, tb_);
-            atomic_add_f32(gtrow + 4 * N + k, tw_);
-          }
+          wave_accumulate(acc + 4 * k + 0, sWx, lane);
+          wave_accumulate(acc + 4 * k + 1, sWy, lane);
+          wave_accumulate(acc + 4 * k + 2, sWz, lane);
+          wave_accumulate(acc + 4 * k + 3, sBt, lane);
+          wave_accumulate(acc + 4 * N + k, sW2, lane);
         }
-        {
-          const float t = wave_total(gb2);
-          if (lane == 0) atomic_add_f32(gtrow + 5 * N, t);
-        }
+        wave_accumulate(acc + 5 * N, gb2, lane);
         // chain p', e', H -> d', m' -> record coefficients
         float R[18];
 #pragma unroll
@@ -502,9 +546,22 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
           }
         }
 #pragma unroll
-        for (int r = 0; r < 18; ++r) {
-          const float t = wave_total(R[r]);
-          if (lane == 0) atomic_add_f32(gvrow + r, t);
+        for (int r = 0; r < 18; ++r) wave_accumulate(acc + TS + r, R[r], lane);
+      }
+      // flush the batch's accumulators to HBM (one float atomic per nonzero
+      // value, spread over the workgroup) and clear them
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < nb * ACC; idx += NT) {
+        const int jj = idx / ACC, c = idx - jj * ACC;
+        float* slot = &s_acc[jj][c];
+        const float val = *slot;
+        if (val != 0.f) {
+          const uint32_t p = S.id[jj];
+          if (c < TS)
+            atomic_add_f32(a.gtable + (int64_t)p * TS + c, val);
+          else
+            atomic_add_f32(a.gview + ((int64_t)v * a.P + p) * kGViewFloats + (c - TS), val);
+          *slot = 0.f;
         }
       }
       bool mine = true;
