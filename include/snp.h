@@ -81,7 +81,9 @@ typedef struct {
  *  alpha_max  alpha is clamped to at most alpha_max (< 1).
  *  bg         background colour added as T_final * bg.
  *  persistent 1 = one persistent launch over all (view, tile) work items
- *             with a device work queue; 0 = one workgroup per tile. */
+ *             with a device work queue; 0 = one workgroup per tile.
+ *  px_per_lane_bwd  pixels per thread of the backward rasterizer (0 = same
+ *             as px_per_lane); the tile shape is shared with the forward. */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -91,6 +93,7 @@ typedef struct {
   float z_near, t_eps, alpha_min, alpha_max;
   float bg[3];
   int32_t persistent;
+  int32_t px_per_lane_bwd;
 } snp_config;
 
 typedef struct {

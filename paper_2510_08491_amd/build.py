@@ -25,6 +25,9 @@ ARCH = "gfx950"
 # packed FP32 instructions are disabled on purpose (the compiler would form
 # them from ordinary float code)
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
+          # atomics here are issued on already reduced values; the compiler's
+          # atomic optimizer would wrap each one in a loop over the lanes
+          "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 PER_FILE = {
     # float64 key path: one fixed operation order, no contraction

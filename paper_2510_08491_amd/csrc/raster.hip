@@ -142,9 +142,11 @@ __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, co
     const double x = g.dx, y = g.dy;
     disc = (float)(dq[0] + x * (dq[1] + dq[3] * x + dq[4] * y) + y * (dq[2] + dq[5] * y));
   }
-  if (!(disc > 0.f)) return false;
+  const bool hit = disc > 0.f;
+  // every field stays finite for a miss (H = 0, e' = 0), so loops over the
+  // hidden units can run without per-pixel branches and be masked afterwards
   g.rA = fast_rcp(g.A);
-  g.sq = fast_sqrt(disc);
+  g.sq = fast_sqrt(hit ? disc : 0.f);
   g.H = g.sq * g.rA;
   g.p0 = (g.d1 * g.m2 - g.d2 * g.m1) * g.rA;
   g.p1 = (g.d2 * g.m0 - g.d0 * g.m2) * g.rA;
@@ -152,7 +154,7 @@ __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, co
   g.e0 = g.d0 * g.H;
   g.e1 = g.d1 * g.H;
   g.e2 = g.d2 * g.H;
-  return true;
+  return hit;
 }
 
 __device__ __forceinline__ float alpha_of(float ahat, float alpha_max) {
@@ -211,21 +213,20 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
           Q[q] = 0.f;
           if (COUNT) npairs += hit[q] ? 1 : 0;
         }
-        if (!any) continue;
+        if (__ballot(any) == 0) continue;  // wave-uniform skip
         const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
+        // all lanes run the unit loop; misses are masked after it
 #pragma unroll 4
         for (int k = 0; k < N; ++k) {
           const float4 w = S.tab[j][k];
           const float w2 = tabf[4 * N + k];
 #pragma unroll
           for (int q = 0; q < PPL; ++q) {
-            if (hit[q]) {
-              const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
-              const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
-              const float c = cos_rev(ph);
-              const float sn = sinc_rev(sin_rev(hv), hv);
-              Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
-            }
+            const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
+            const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
+            const float c = cos_rev(ph);
+            const float sn = sinc_rev(sin_rev(hv), hv);
+            Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
           }
         }
         const float b2 = tabf[5 * N];
@@ -296,6 +297,30 @@ __device__ __forceinline__ void wave_accumulate(float* slot, float v, int lane) 
   if ((lane & 15) == 0) atomicAdd(slot, v);
 }
 
+// five sums at once (interleaved, so the DPP steps of one value fill the
+// hazard slots of the others): a[0..3] += (x, y, z, w), b[0] += u
+__device__ __forceinline__ void wave_accumulate5(float* a, float* b, float x, float y, float z, float w, float u,
+                                                 int lane) {
+#define SNP_DPP_STEP(CTRL)                                                                          \
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false)); \
+  y += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), CTRL, 0xF, 0xF, false)); \
+  z += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(z), CTRL, 0xF, 0xF, false)); \
+  w += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(w), CTRL, 0xF, 0xF, false)); \
+  u += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(u), CTRL, 0xF, 0xF, false));
+  SNP_DPP_STEP(0xB1)
+  SNP_DPP_STEP(0x4E)
+  SNP_DPP_STEP(0x141)
+  SNP_DPP_STEP(0x140)
+#undef SNP_DPP_STEP
+  if ((lane & 15) == 0) {
+    atomicAdd(a + 0, x);
+    atomicAdd(a + 1, y);
+    atomicAdd(a + 2, z);
+    atomicAdd(a + 3, w);
+    atomicAdd(b, u);
+  }
+}
+
 template <int N>
 struct BwdBatch {
   static constexpr int value = N >= 16 ? 32 : BATCH;
@@ -303,7 +328,7 @@ struct BwdBatch {
 
 // Per (instance, pixel) the backward needs, for every hidden unit k,
 //   cs_k = cos(ph_k) sinc(hv_k),  ss_k = sin(ph_k) sinc(hv_k),  cd_k = cos(ph_k) sinc'(hv_k)
-// (sinc in the revolution form sin(2 pi hv) / hv).  When N * PPL <= 32 they
+// (sinc in the revolution form sin(2 pi hv) / hv).  When N * PPL <= 16 they
 // are kept in registers from the first unit loop (which needs cos and sinc
 // anyway for the integral), so the second loop has no transcendentals;
 // otherwise the second loop recomputes them.
@@ -313,7 +338,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
   constexpr int TS = 5 * N + 4;
   constexpr int NB = BwdBatch<N>::value;
   constexpr int ACC = TS + kGViewFloats;  // per instance: table grads, then record grads
-  constexpr bool CACHE = N * PPL <= 32;
+  constexpr bool CACHE = N * PPL <= 16;
   __shared__ Stage<N, true, NB> S;
   __shared__ float s_acc[NB][ACC];
   __shared__ int s_item;
@@ -379,26 +404,22 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
           const float w2 = tabf[4 * N + k];
 #pragma unroll
           for (int q = 0; q < PPL; ++q) {
-            if (hit[q]) {
-              const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
-              const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
-              const float c = cos_rev(ph);
-              const float sh = sin_rev(hv);
-              const float sn = sinc_rev(sh, hv);
-              Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
-              if constexpr (CACHE) {
-                const float s = sin_rev(ph), ch = cos_rev(hv);
-                float dsn;
-                if (fabsf(hv) < 0.02f) {
-                  const float h = kTwoPi * hv, h2 = h * h;
-                  dsn = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
-                } else {
-                  dsn = (kTwoPi * ch - sn) * fast_rcp(hv);
-                }
-                cs[k][q] = c * sn;
-                ss[k][q] = s * sn;
-                cd[k][q] = c * dsn;
-              }
+            const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
+            const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
+            const float c = cos_rev(ph);
+            const float sh = sin_rev(hv);
+            const float rh = fast_rcp(hv);
+            const bool small = fabsf(hv) < 1e-4f;
+            const float sn = small ? kTwoPi : sh * rh;
+            Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
+            if constexpr (CACHE) {
+              const float s = sin_rev(ph), ch = cos_rev(hv);
+              const float h = kTwoPi * hv, h2 = h * h;
+              const float series = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
+              const float dsn = fabsf(hv) < 0.02f ? series : (kTwoPi * ch - sn) * rh;
+              cs[k][q] = c * sn;
+              ss[k][q] = s * sn;
+              cd[k][q] = c * dsn;
             }
           }
         }
@@ -454,7 +475,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
           float sW2 = 0.f, sBt = 0.f, sWx = 0.f, sWy = 0.f, sWz = 0.f;
 #pragma unroll
           for (int q = 0; q < PPL; ++q) {
-            if (wq[q] != 0.f) {
+            {
               float csq, ssq, cdq;
               if constexpr (CACHE) {
                 csq = cs[k][q];
@@ -493,11 +514,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
               ge2[q] = __builtin_fmaf(ghv, w.z, ge2[q]);
             }
           }
-          wave_accumulate(acc + 4 * k + 0, sWx, lane);
-          wave_accumulate(acc + 4 * k + 1, sWy, lane);
-          wave_accumulate(acc + 4 * k + 2, sWz, lane);
-          wave_accumulate(acc + 4 * k + 3, sBt, lane);
-          wave_accumulate(acc + 4 * N + k, sW2, lane);
+          wave_accumulate5(acc + 4 * k, acc + 4 * N + k, sWx, sWy, sWz, sBt, sW2, lane);
         }
         wave_accumulate(acc + 5 * N, gb2, lane);
         // chain p', e', H -> d', m' -> record coefficients
@@ -597,6 +614,13 @@ bool tile_supported(int tw, int th, int ppl) {
   return false;
 }
 
+// pixels per thread of the backward for a tile shape (the forward's list plus
+// one thread per pixel on 32 x 16 tiles)
+bool bwd_ppl_supported(int tw, int th, int ppl) {
+  if (tw == 32 && th == 16 && ppl == 1) return true;
+  return tile_supported(tw, th, ppl);
+}
+
 template <typename K>
 static int persistent_grid(K kernel, int threads, int total) {
   int dev = 0, cus = 0, occ = 0;
@@ -660,6 +684,7 @@ static hipError_t bwd_n(const RasterArgs& a, int tw, int th, int ppl, bool persi
   if (tw == 16 && th == 16 && ppl == 2) return bwd_shape<N, 16, 16, 2>(a, persist, st);
   if (tw == 16 && th == 16 && ppl == 4) return bwd_shape<N, 16, 16, 4>(a, persist, st);
   if (tw == 8 && th == 8 && ppl == 1) return bwd_shape<N, 8, 8, 1>(a, persist, st);
+  if (tw == 32 && th == 16 && ppl == 1) return bwd_shape<N, 32, 16, 1>(a, persist, st);
   if (tw == 32 && th == 16 && ppl == 2) return bwd_shape<N, 32, 16, 2>(a, persist, st);
   if (tw == 32 && th == 16 && ppl == 4) return bwd_shape<N, 32, 16, 4>(a, persist, st);
   return hipErrorInvalidValue;

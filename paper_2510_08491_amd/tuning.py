@@ -44,53 +44,75 @@ def _load() -> Dict:
     return {}
 
 
-def lookup(N: int, color_mode: int, cams) -> Optional[Tuple[int, int, int]]:
+def lookup(N: int, color_mode: int, cams) -> Optional[Tuple[int, int, int, int]]:
+    """(tile_w, tile_h, px_per_lane, px_per_lane_bwd) tuned for this class, or None."""
     entry = _load().get(key_of(N, color_mode, cams))
-    return tuple(entry["tile"]) if entry else None
+    if not entry:
+        return None
+    return tuple(entry["tile"]) + (int(entry.get("px_per_lane_bwd", entry["tile"][2])),)
 
 
 def autotune(base: RenderConfig, P: int, cams, params, targets: torch.Tensor, reps: int = 2,
              shapes=None, write=True, log=print):
-    """Times each tile shape (forward + backward rasterizer kernels, HIP
-    events around the launches) and returns (best shape, table)."""
-    shapes = shapes or supported_shapes()
+    """Times the rasterizer kernels for every tile shape and every pixels-per-
+    thread count of the forward and of the backward (HIP events around the
+    launches, best of `reps`), checks that each candidate renders the same
+    image as the first, and returns (best (tile_w, tile_h, ppl_fwd, ppl_bwd),
+    table)."""
+    fwd_shapes = shapes or supported_shapes()
+    tiles = sorted({(s[0], s[1]) for s in fwd_shapes})
     results = {}
     ref_img = None
     n_norm = float(targets.numel())
-    for sh in shapes:
-        cfg = RenderConfig(**{**base.__dict__, "tile_w": sh[0], "tile_h": sh[1], "px_per_lane": sh[2]})
-        rast = Rasterizer(cfg, P, cams)
-        inst = rast.prepare(params)
-        rast._alloc(int(inst * 1.1) + 4096)
-        images, T = rast.new_images()
-        loss = torch.zeros(1, dtype=torch.float64, device=images.device)
-        dL = torch.empty_like(images)
-        grads = zeros_like_params(params)
-        rast.step(params, images, T, targets, n_norm, loss, dL, grads)   # warm-up
-        kernel_timing(True)
-        best = None
-        for _ in range(reps):
-            rast.step(params, images, T, targets, n_norm, loss, dL, grads)
-            f, b = kernel_timing_read()
-            best = f + b if best is None else min(best, f + b)
-        kernel_timing(False)
-        torch.cuda.synchronize()
-        if ref_img is None:
-            ref_img = images.clone()
-            diff = 0.0
-        else:
+    best = None
+    for tw, th in tiles:
+        f_ppls = [s[2] for s in fwd_shapes if (s[0], s[1]) == (tw, th)]
+        b_ppls = sorted(set(f_ppls) | ({1} if (tw, th) == (32, 16) else set()))
+        fwd_ms, bwd_ms = {}, {}
+        for ppl in sorted(set(f_ppls) | set(b_ppls)):
+            pf = ppl if ppl in f_ppls else f_ppls[0]
+            cfg = RenderConfig(**{**base.__dict__, "tile_w": tw, "tile_h": th, "px_per_lane": pf,
+                                  "px_per_lane_bwd": ppl})
+            rast = Rasterizer(cfg, P, cams)
+            inst = rast.prepare(params)
+            rast._alloc(int(inst * 1.1) + 4096)
+            images, T = rast.new_images()
+            loss = torch.zeros(1, dtype=torch.float64, device=images.device)
+            dL = torch.empty_like(images)
+            grads = zeros_like_params(params)
+            rast.step(params, images, T, targets, n_norm, loss, dL, grads)   # warm-up
+            kernel_timing(True)
+            fb, bb = None, None
+            for _ in range(reps):
+                rast.step(params, images, T, targets, n_norm, loss, dL, grads)
+                f, b = kernel_timing_read()
+                fb = f if fb is None else min(fb, f)
+                bb = b if bb is None else min(bb, b)
+            kernel_timing(False)
+            torch.cuda.synchronize()
+            if ref_img is None:
+                ref_img = images.clone()
             diff = float((images - ref_img).abs().max())
-        results[sh] = dict(ms=best, img_diff=diff)
-        log(f"[tune] tile {sh}: raster fwd+bwd {best:.3f} ms, image diff vs first {diff:.2e}")
-        del rast, images, T, dL, grads
-        torch.cuda.empty_cache()
-    ok = {sh: r for sh, r in results.items() if r["img_diff"] <= 1e-5}
-    best_shape = min(ok, key=lambda s: ok[s]["ms"])
+            if pf == ppl:
+                fwd_ms[ppl] = fb
+            bwd_ms[ppl] = bb
+            results[f"{tw}x{th} fwd{pf} bwd{ppl}"] = dict(fwd_ms=fb, bwd_ms=bb, img_diff=diff)
+            log(f"[tune] tile {tw}x{th} ppl fwd {pf} bwd {ppl}: forward {fb:.3f} ms, backward {bb:.3f} ms, "
+                f"image diff {diff:.2e}")
+            if diff > 1e-5:
+                raise RuntimeError(f"tile {tw}x{th}/{ppl} renders a different image ({diff})")
+            del rast, images, T, dL, grads
+            torch.cuda.empty_cache()
+        pf = min(fwd_ms, key=fwd_ms.get)
+        pb = min(bwd_ms, key=bwd_ms.get)
+        total = fwd_ms[pf] + bwd_ms[pb]
+        if best is None or total < best[0]:
+            best = (total, (tw, th, pf, pb))
+    best_shape = best[1]
     if write:
         cache = _load()
         cache[key_of(base.n_hidden, base.color_mode, cams)] = {
-            "tile": list(best_shape), "ms": ok[best_shape]["ms"],
-            "candidates": {f"{s[0]}x{s[1]}x{s[2]}": r for s, r in results.items()}}
+            "tile": list(best_shape[:3]), "px_per_lane_bwd": best_shape[3], "ms": best[0], "candidates": results}
         with open(CACHE, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return best_shape, results

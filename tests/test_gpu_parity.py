@@ -92,12 +92,16 @@ def test_tile_shapes_ragged_image(tile):
 
 
 @pytest.mark.parametrize("N", [4, 8, 32])
-def test_hidden_widths(N):
+def test_hidden_widths_with_gradients(N):
     scene = S.custom_scene(800, N, seed=60 + N, omega0=30.0 if N == 32 else 10.0)
     cams = S.make_cameras([(96, 80)], seed=61)
     cfg = config_for(scene, tile=(16, 16, 2))
     fw = run_forward(scene, cams, cfg)
     _check_images(fw, scene, cams, cfg)
+    small = S.subset_scene(scene, np.arange(200))
+    small["N"], small["omega0"] = scene["N"], scene["omega0"]
+    _grad_parity(small, cams, S.make_targets(cams, seed=62), config_for(small, tile=(16, 16, 1)),
+                 ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
 def test_multiview_batched_and_persistent():
@@ -162,7 +166,7 @@ def test_c1_gradients():
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 4), (32, 16, 2)])
+@pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 4), (32, 16, 2), (32, 16, 2, 1), (32, 16, 4, 2), (8, 8, 1)])
 def test_gradients_multiview_tiles(tile):
     scene = S.custom_scene(400, 8, seed=101)
     cams = S.make_cameras([(72, 56), (48, 64)], seed=102)
@@ -171,11 +175,12 @@ def test_gradients_multiview_tiles(tile):
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
-def test_colour_mlp_gradients():
+@pytest.mark.parametrize("tile", [(16, 16, 2), (32, 16, 2, 1)])
+def test_colour_mlp_gradients(tile):
     scene = S.custom_scene(300, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=111)
     cams = S.make_cameras([(64, 48), (48, 40), (56, 56)], seed=112)
     targets = S.make_targets(cams, seed=113)
-    cfg = config_for(scene, tile=(16, 16, 2))
+    cfg = config_for(scene, tile=tile)
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
 
 
