@@ -244,6 +244,7 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   a.records = wsp<float>(ws, L.records);
   a.values = wsp<uint32_t>(ws, L.values);
   a.ranges = wsp<uint32_t>(ws, L.ranges);
+  a.rects = wsp<int32_t>(ws, L.rects);
   a.gview = wsp<float>(ws, L.gview);
   a.gtable = wsp<float>(ws, L.gtable);
   a.disc_coef = wsp<double>(ws, L.disc_coef);

@@ -52,12 +52,19 @@ __device__ __forceinline__ float sinc_rev(float s, float hv) {
   return fabsf(hv) < 1e-4f ? kTwoPi : s * fast_rcp(hv);
 }
 
-// per-thread pixel block of a tile
+// per-thread pixel block of a tile (a wave covers 64 / TW thread rows)
 template <int TW, int TH, int PPL>
 struct PixelBlock {
+  static_assert(64 % TW == 0, "a wave must cover whole tile rows");
   float pxc[PPL], pyc[PPL], L[PPL];
   int pix[PPL];   // index into the packed image, -1 if outside
+  int wx0, wx1, wy0, wy1;  // pixel block of this thread's wave
   __device__ void init(const CamDev& cam, int tx, int ty) {
+    constexpr int ROWS = (64 / TW) * PPL;  // pixel rows covered by one wave
+    wx0 = tx * TW;
+    wx1 = wx0 + TW - 1;
+    wy0 = ty * TH + (int)(threadIdx.x / 64) * ROWS;
+    wy1 = wy0 + ROWS - 1;
     const int lx = threadIdx.x % TW;
     const int ly0 = (threadIdx.x / TW) * PPL;
 #pragma unroll
@@ -88,12 +95,17 @@ struct Stage {
   float4 rec[B][6];
   float4 tab[B][TS / 4];
   float4 dq[BWD ? B : 1][3];
+  int4 rect[B];  // the primitive's inclusive pixel rectangle in this view
   uint32_t id[B];
 };
 
 template <int N, bool BWD, int NT, int B>
 __device__ __forceinline__ void stage_batch(Stage<N, BWD, B>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
-  for (int t = threadIdx.x; t < nb; t += NT) S.id[t] = a.values[b0 + t];
+  for (int t = threadIdx.x; t < nb; t += NT) {
+    const uint32_t p = a.values[b0 + t];
+    S.id[t] = p;
+    S.rect[t] = reinterpret_cast<const int4*>(a.rects)[(int64_t)v * a.P + p];
+  }
   __syncthreads();
   const float4* rec4 = reinterpret_cast<const float4*>(a.records);
   const float4* tab4 = reinterpret_cast<const float4*>(a.table);
@@ -200,6 +212,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
       __syncthreads();
       stage_batch<N, decltype(S)::DQ4 != 0, NT, decltype(S)::NB>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
+        const int4 rc = S.rect[j];
+        if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
         PairGeom g[PPL];
@@ -380,6 +394,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
       __syncthreads();
       stage_batch<N, true, NT, NB>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
+        const int4 rc = S.rect[j];
+        if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
         const float* tabf = reinterpret_cast<const float*>(S.tab[j]);

@@ -174,6 +174,7 @@ struct RasterArgs {
   const float* records;
   const uint32_t* values;
   const uint32_t* ranges;
+  const int32_t* rects;   // per (view, primitive) pixel rectangle x0, x1, y0, y1
   float* images;          // forward output
   float* final_T;         // forward output
   const float* images_in; // backward: forward's images
