@@ -222,7 +222,9 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
         float Q[PPL];
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-          hit[q] = !done[q] && pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q]);
+          // geometry for every lane (finite for misses), so the unit loops can run unmasked
+          const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q]);
+          hit[q] = !done[q] && gh;
           any |= hit[q];
           Q[q] = 0.f;
           if (COUNT) npairs += hit[q] ? 1 : 0;
@@ -406,8 +408,10 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
         float Q[PPL];
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-          hit[q] = !done[q] && pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q],
-                                         reinterpret_cast<const double*>(S.dq[j]));
+          // geometry for every lane (finite for misses), so the unit loops can run unmasked
+          const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q],
+                                    reinterpret_cast<const double*>(S.dq[j]));
+          hit[q] = !done[q] && gh;
           any |= hit[q];
           Q[q] = 0.f;
         }
