@@ -62,6 +62,8 @@ def main(argv=None):
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--eager-only", action="store_true",
+                    help="profiling aid: only run --steps eager steps (no graph, no per-view, no CPU leg) and print timings")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -100,6 +102,16 @@ def main(argv=None):
     cnt = rast.counters()
     hit_pairs, live_pairs = cnt["hit_pairs"], cnt["live_pairs"]
     log(f"[bench] instances {inst}, hit pairs {hit_pairs}, live pairs {live_pairs}")
+    if a.eager_only:
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dL = torch.empty_like(images)
+        grads = snp.zeros_like_params(params)
+        for s in range(a.steps):
+            t0 = time.perf_counter()
+            rast.step(params, images, final_T, tg, n_norm, loss, dL, grads)
+            torch.cuda.synchronize()
+            log(f"[bench] eager step {s}: {1e3 * (time.perf_counter() - t0):.1f} ms")
+        return
 
     # ---- batched: one graph per step -------------------------------------------------
     step = snp.GraphStep(rast, params, tg, n_norm)
