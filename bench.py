@@ -58,7 +58,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5"])
-    ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,px_per_lane_bwd] (default: tuned)")
+    ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,bwd_batch] (default: tuned)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -83,10 +83,10 @@ def main(argv=None):
     else:
         tile = tuning.lookup(N, scene["color_mode"], cams) or (16, 16, 2)
     if len(tile) == 3:
-        tile = tile + (tile[2],)
+        tile = tile + (0,)
     cfg = snp.RenderConfig(n_hidden=N, omega0=scene["omega0"], color_mode=scene["color_mode"],
                            cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], tile_w=tile[0],
-                           tile_h=tile[1], px_per_lane=tile[2], px_per_lane_bwd=tile[3], persistent=1)
+                           tile_h=tile[1], px_per_lane=tile[2], bwd_batch=tile[3], persistent=1)
     log(f"[bench] workload {a.workload}: P={scene['P']} V={len(cams)} N={N} tile={tile}")
     params = snp.params_to_device(scene)
     tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()

@@ -82,8 +82,9 @@ typedef struct {
  *  bg         background colour added as T_final * bg.
  *  persistent 1 = one persistent launch over all (view, tile) work items
  *             with a device work queue; 0 = one workgroup per tile.
- *  px_per_lane_bwd  pixels per thread of the backward rasterizer (0 = same
- *             as px_per_lane); the tile shape is shared with the forward. */
+ *  bwd_batch  instances per batch of the backward rasterizer (0 = the
+ *             default for the tile shape); the tile shape is shared with the
+ *             forward, and the backward runs one pixel per thread. */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -93,7 +94,7 @@ typedef struct {
   float z_near, t_eps, alpha_min, alpha_max;
   float bg[3];
   int32_t persistent;
-  int32_t px_per_lane_bwd;
+  int32_t bwd_batch;
 } snp_config;
 
 typedef struct {

@@ -22,7 +22,7 @@ class SnpConfig(C.Structure):
                 ("cmlp_width", C.c_int32), ("cmlp_depth", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("px_per_lane", C.c_int32), ("z_near", C.c_float),
                 ("t_eps", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
-                ("bg", C.c_float * 3), ("persistent", C.c_int32), ("px_per_lane_bwd", C.c_int32)]
+                ("bg", C.c_float * 3), ("persistent", C.c_int32), ("bwd_batch", C.c_int32)]
 
 
 class SnpPrims(C.Structure):

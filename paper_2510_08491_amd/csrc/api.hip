@@ -34,7 +34,7 @@ static snp_status check_cfg(const snp_config* cfg) {
   if (!(cfg->t_eps >= 0.f && cfg->t_eps < 1.f)) return SNP_ERR_INVALID;
   if (!(cfg->alpha_min >= 0.f && cfg->alpha_max > 0.f && cfg->alpha_max < 1.f)) return SNP_ERR_INVALID;
   if (cfg->persistent != 0 && cfg->persistent != 1) return SNP_ERR_INVALID;
-  if (cfg->px_per_lane_bwd != 0 && !bwd_ppl_supported(cfg->tile_w, cfg->tile_h, cfg->px_per_lane_bwd))
+  if (cfg->bwd_batch != 0 && !bwd_batch_supported(cfg->tile_w, cfg->tile_h, cfg->bwd_batch))
     return SNP_ERR_UNSUPPORTED;
   return SNP_OK;
 }
@@ -303,8 +303,8 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
   SNP_HIP(zero_f32(a.gtable, P * (int64_t)L.table_stride, st));
   if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_BWD, st));
   timer_mark(2, st);
-  const int ppl_bwd = cfg->px_per_lane_bwd ? cfg->px_per_lane_bwd : cfg->px_per_lane;
-  SNP_HIP(launch_render_bwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, ppl_bwd, cfg->persistent != 0, a, st));
+  const int nb = cfg->bwd_batch ? cfg->bwd_batch : bwd_batch_default(cfg->tile_w, cfg->tile_h);
+  SNP_HIP(launch_render_bwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, nb, cfg->persistent != 0, a, st));
   timer_mark(3, st);
   if (cfg->color_mode == 1) {
     CmlpArgs ca;

@@ -337,28 +337,46 @@ __device__ __forceinline__ void wave_accumulate5(float* a, float* b, float x, fl
   }
 }
 
-template <int N>
-struct BwdBatch {
-  static constexpr int value = N >= 16 ? 32 : BATCH;
-};
+// Length of the un-normalised camera ray R^-1 ((x+1/2-cx)/fx, (y+1/2-cy)/fy, 1).
+__device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float pyc) {
+  const float cxn = (pxc - cam.cx) / cam.fx;
+  const float cyn = (pyc - cam.cy) / cam.fy;
+  const float Dx = cam.Rinv_f[0] * cxn + cam.Rinv_f[1] * cyn + cam.Rinv_f[2];
+  const float Dy = cam.Rinv_f[3] * cxn + cam.Rinv_f[4] * cyn + cam.Rinv_f[5];
+  const float Dz = cam.Rinv_f[6] * cxn + cam.Rinv_f[7] * cyn + cam.Rinv_f[8];
+  return sqrtf(Dx * Dx + Dy * Dy + Dz * Dz);
+}
 
-// Per (instance, pixel) the backward needs, for every hidden unit k,
-//   cs_k = cos(ph_k) sinc(hv_k),  ss_k = sin(ph_k) sinc(hv_k),  cd_k = cos(ph_k) sinc'(hv_k)
-// (sinc in the revolution form sin(2 pi hv) / hv).  When N * PPL <= 16 they
-// are kept in registers from the first unit loop (which needs cos and sinc
-// anyway for the integral), so the second loop has no transcendentals;
-// otherwise the second loop recomputes them.
-template <int N, int TW, int TH, int PPL, bool PERSIST>
-__global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a) {
-  constexpr int NT = TW * TH / PPL;
+// The backward works on batches of NB instances of a tile in two phases.
+//
+// Phase 1 (one pixel per thread, the instances in depth order): the same
+// arithmetic as the forward gives alpha, T and the accumulated colour; the
+// colour gradient is summed here; every pair whose integral is positive and
+// unclamped ("live", it carries gradient) is appended to the instance's list
+// in LDS with its pixel, d loss / d Q and d loss / d H.
+//
+// Phase 2 (one live pair per lane): the waves take chunks of 64 list entries
+// (instance by instance, round robin over the waves), recompute the pair's
+// geometry -- with the float64 discriminant near the silhouette -- and the
+// per-unit terms, and sum the gradients of the table entries and of the
+// record coefficients over the wave into LDS accumulators, flushed to HBM
+// once per batch.  Every lane of phase 2 carries gradient, and each wave
+// reduction covers 64 live pairs.
+template <int N, int TW, int TH, int NB, bool PERSIST>
+__global__ void __launch_bounds__(TW * TH) render_bwd_kernel(RasterArgs a) {
+  constexpr int NT = TW * TH;
+  constexpr int NW = NT / 64;
   constexpr int TS = 5 * N + 4;
-  constexpr int NB = BwdBatch<N>::value;
   constexpr int ACC = TS + kGViewFloats;  // per instance: table grads, then record grads
-  constexpr bool CACHE = N * PPL <= 16;
   __shared__ Stage<N, true, NB> S;
   __shared__ float s_acc[NB][ACC];
+  __shared__ uint32_t s_cnt[NB];
+  __shared__ uint16_t s_pix[NB][NT];
+  __shared__ float s_wq[NB][NT];
+  __shared__ float s_gh[NB][NT];
   __shared__ int s_item;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int idx = threadIdx.x; idx < NB * ACC; idx += NT) (&s_acc[0][0])[idx] = 0.f;
   int item = blockIdx.x;
   while (true) {
@@ -373,238 +391,204 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_bwd_kernel(RasterArgs a)
     const CamDev& cam = a.cams[v];
     const int local = item - cam.tile_base;
     const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
-    PixelBlock<TW, TH, PPL> pb;
+    PixelBlock<TW, TH, 1> pb;
     pb.init(cam, tx, ty);
-    float T[PPL], A0[PPL], A1[PPL], A2[PPL], G0[PPL], G1[PPL], G2[PPL], F0[PPL], F1[PPL], F2[PPL];
-    bool done[PPL];
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-      T[q] = 1.f;
-      A0[q] = A1[q] = A2[q] = 0.f;
-      done[q] = pb.pix[q] < 0;
-      const int64_t px = cam.pix_base + (pb.pix[q] < 0 ? 0 : pb.pix[q]);
-      G0[q] = done[q] ? 0.f : a.dL[3 * px + 0];
-      G1[q] = done[q] ? 0.f : a.dL[3 * px + 1];
-      G2[q] = done[q] ? 0.f : a.dL[3 * px + 2];
-      F0[q] = done[q] ? 0.f : a.images_in[3 * px + 0];
-      F1[q] = done[q] ? 0.f : a.images_in[3 * px + 1];
-      F2[q] = done[q] ? 0.f : a.images_in[3 * px + 2];
-    }
+    float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f;
+    bool done = pb.pix[0] < 0;
+    const int64_t pxi = cam.pix_base + (done ? 0 : pb.pix[0]);
+    const float G0 = done ? 0.f : a.dL[3 * pxi + 0];
+    const float G1 = done ? 0.f : a.dL[3 * pxi + 1];
+    const float G2 = done ? 0.f : a.dL[3 * pxi + 2];
+    const float F0 = done ? 0.f : a.images_in[3 * pxi + 0];
+    const float F1 = done ? 0.f : a.images_in[3 * pxi + 1];
+    const float F2 = done ? 0.f : a.images_in[3 * pxi + 2];
     const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
       __syncthreads();
+      if (threadIdx.x < NB) s_cnt[threadIdx.x] = 0u;
       stage_batch<N, true, NT, NB>(S, a, v, b0, nb);
+      // ---------------- phase 1: pixels ----------------
       for (int j = 0; j < nb; ++j) {
         const int4 rc = S.rect[j];
         if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
+        PairGeom g;
+        const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[0], pb.pyc[0], g);
+        const bool hit = !done && gh;
+        if (__ballot(hit) == 0) continue;  // wave-uniform
         const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
-        float* acc = s_acc[j];
-        PairGeom g[PPL];
-        bool hit[PPL];
-        bool any = false;
-        float Q[PPL];
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-          // geometry for every lane (finite for misses), so the unit loops can run unmasked
-          const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q],
-                                    reinterpret_cast<const double*>(S.dq[j]));
-          hit[q] = !done[q] && gh;
-          any |= hit[q];
-          Q[q] = 0.f;
-        }
-        if (__ballot(any) == 0) continue;  // wave-uniform
-        float cs[CACHE ? N : 1][PPL], ss[CACHE ? N : 1][PPL], cd[CACHE ? N : 1][PPL];
-        // pass 1: the integral (same arithmetic as the forward), caching the unit terms
-#pragma unroll
+        float Q = 0.f;
+#pragma unroll 4
         for (int k = 0; k < N; ++k) {
           const float4 w = S.tab[j][k];
           const float w2 = tabf[4 * N + k];
-#pragma unroll
-          for (int q = 0; q < PPL; ++q) {
-            const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
-            const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
-            const float c = cos_rev(ph);
-            const float sh = sin_rev(hv);
-            const float rh = fast_rcp(hv);
-            const bool small = fabsf(hv) < 1e-4f;
-            const float sn = small ? kTwoPi : sh * rh;
-            Q[q] = __builtin_fmaf(w2 * c, sn, Q[q]);
-            if constexpr (CACHE) {
-              const float s = sin_rev(ph), ch = cos_rev(hv);
-              const float h = kTwoPi * hv, h2 = h * h;
-              const float series = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
-              const float dsn = fabsf(hv) < 0.02f ? series : (kTwoPi * ch - sn) * rh;
-              cs[k][q] = c * sn;
-              ss[k][q] = s * sn;
-              cd[k][q] = c * dsn;
-            }
-          }
+          const float ph = __builtin_fmaf(w.x, g.p0, __builtin_fmaf(w.y, g.p1, __builtin_fmaf(w.z, g.p2, w.w)));
+          const float hv = __builtin_fmaf(w.x, g.e0, __builtin_fmaf(w.y, g.e1, w.z * g.e2));
+          const float c = cos_rev(ph);
+          const float sn = sinc_rev(sin_rev(hv), hv);
+          Q = __builtin_fmaf(w2 * c, sn, Q);
         }
         const float b2 = tabf[5 * N];
-        // blending and d loss / d integral
-        float wq[PPL], gHq[PPL];
-        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;
+        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, wq = 0.f, gH = 0.f;
         bool live = false;
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-          wq[q] = 0.f;
-          gHq[q] = 0.f;
-          if (hit[q]) {
-            const float ahat = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
-            const float al = alpha_of(ahat, a.alpha_max);
-            if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
-              const float wt = al * T[q];
-              gc0 = __builtin_fmaf(G0[q], wt, gc0);
-              gc1 = __builtin_fmaf(G1[q], wt, gc1);
-              gc2 = __builtin_fmaf(G2[q], wt, gc2);
-              A0[q] = __builtin_fmaf(r2.w, wt, A0[q]);
-              A1[q] = __builtin_fmaf(r3.w, wt, A1[q]);
-              A2[q] = __builtin_fmaf(r4.w, wt, A2[q]);
-              if (ahat > 0.f && al < a.alpha_max) {
-                const float ta = T[q] * (1.f - al);
-                const float G = G0[q] * (r2.w * ta - (F0[q] - A0[q])) + G1[q] * (r3.w * ta - (F1[q] - A1[q])) +
-                                G2[q] * (r4.w * ta - (F2[q] - A2[q]));
-                wq[q] = G * 2.f * pb.L[q] * g[q].H;       // d loss / d Q
-                gHq[q] = G * 2.f * pb.L[q] * (Q[q] + b2);  // d loss / d H (direct)
-                live = true;
-              }
-              T[q] = T[q] * (1.f - al);
-              if (T[q] < a.t_eps) done[q] = true;
+        if (hit) {
+          const float ahat = 2.f * pb.L[0] * g.H * (Q + b2);
+          const float al = alpha_of(ahat, a.alpha_max);
+          if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
+            const float wt = al * T;
+            gc0 = G0 * wt;
+            gc1 = G1 * wt;
+            gc2 = G2 * wt;
+            A0 = __builtin_fmaf(r2.w, wt, A0);
+            A1 = __builtin_fmaf(r3.w, wt, A1);
+            A2 = __builtin_fmaf(r4.w, wt, A2);
+            if (ahat > 0.f && al < a.alpha_max) {
+              const float ta = T * (1.f - al);
+              const float G = G0 * (r2.w * ta - (F0 - A0)) + G1 * (r3.w * ta - (F1 - A1)) + G2 * (r4.w * ta - (F2 - A2));
+              wq = G * 2.f * pb.L[0] * g.H;       // d loss / d Q
+              gH = G * 2.f * pb.L[0] * (Q + b2);  // d loss / d H (direct)
+              live = wq != 0.f || gH != 0.f;
             }
+            T = T * (1.f - al);
+            if (T < a.t_eps) done = true;
           }
         }
-        // colour gradient (also when the integral's gradient is clamped)
+        float* acc = s_acc[j];
         wave_accumulate(acc + TS + 18, gc0, lane);
         wave_accumulate(acc + TS + 19, gc1, lane);
         wave_accumulate(acc + TS + 20, gc2, lane);
-        if (__ballot(live) == 0) continue;
-        // pass 2: per hidden unit
-        float gp0[PPL], gp1[PPL], gp2[PPL], ge0[PPL], ge1[PPL], ge2[PPL];
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) gp0[q] = gp1[q] = gp2[q] = ge0[q] = ge1[q] = ge2[q] = 0.f;
-        float gb2 = 0.f;
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) gb2 += wq[q];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-          const float4 w = S.tab[j][k];
-          const float w2 = tabf[4 * N + k];
-          float sW2 = 0.f, sBt = 0.f, sWx = 0.f, sWy = 0.f, sWz = 0.f;
-#pragma unroll
-          for (int q = 0; q < PPL; ++q) {
-            {
-              float csq, ssq, cdq;
-              if constexpr (CACHE) {
-                csq = cs[k][q];
-                ssq = ss[k][q];
-                cdq = cd[k][q];
-              } else {
-                const float ph = __builtin_fmaf(w.x, g[q].p0, __builtin_fmaf(w.y, g[q].p1, __builtin_fmaf(w.z, g[q].p2, w.w)));
-                const float hv = __builtin_fmaf(w.x, g[q].e0, __builtin_fmaf(w.y, g[q].e1, w.z * g[q].e2));
-                const float c = cos_rev(ph), s = sin_rev(ph);
-                const float sh = sin_rev(hv), ch = cos_rev(hv);
-                const float sn = sinc_rev(sh, hv);
-                float dsn;
-                if (fabsf(hv) < 0.02f) {
-                  const float h = kTwoPi * hv, h2 = h * h;
-                  dsn = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
-                } else {
-                  dsn = (kTwoPi * ch - sn) * fast_rcp(hv);
-                }
-                csq = c * sn;
-                ssq = s * sn;
-                cdq = c * dsn;
-              }
-              const float ww = wq[q] * w2;
-              const float gph = -kTwoPi * ww * ssq;  // d loss / d ph
-              const float ghv = ww * cdq;            // d loss / d hv
-              sW2 = __builtin_fmaf(wq[q], csq, sW2);
-              sBt += gph;
-              sWx = __builtin_fmaf(gph, g[q].p0, __builtin_fmaf(ghv, g[q].e0, sWx));
-              sWy = __builtin_fmaf(gph, g[q].p1, __builtin_fmaf(ghv, g[q].e1, sWy));
-              sWz = __builtin_fmaf(gph, g[q].p2, __builtin_fmaf(ghv, g[q].e2, sWz));
-              gp0[q] = __builtin_fmaf(gph, w.x, gp0[q]);
-              gp1[q] = __builtin_fmaf(gph, w.y, gp1[q]);
-              gp2[q] = __builtin_fmaf(gph, w.z, gp2[q]);
-              ge0[q] = __builtin_fmaf(ghv, w.x, ge0[q]);
-              ge1[q] = __builtin_fmaf(ghv, w.y, ge1[q]);
-              ge2[q] = __builtin_fmaf(ghv, w.z, ge2[q]);
-            }
+        const unsigned long long lm = __ballot(live);
+        if (lm) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&s_cnt[j], (uint32_t)__popcll(lm));
+          base = __builtin_amdgcn_readfirstlane(base);
+          if (live) {
+            const uint32_t pos = base + (uint32_t)__popcll(lm & lt_mask);
+            s_pix[j][pos] = (uint16_t)threadIdx.x;
+            s_wq[j][pos] = wq;
+            s_gh[j][pos] = gH;
           }
-          wave_accumulate5(acc + 4 * k, acc + 4 * N + k, sWx, sWy, sWz, sBt, sW2, lane);
         }
-        wave_accumulate(acc + 5 * N, gb2, lane);
-        // chain p', e', H -> d', m' -> record coefficients
-        float R[18];
+      }
+      __syncthreads();
+      // ---------------- phase 2: live pairs ----------------
+      int it = 0;
+      for (int j = 0; j < nb; ++j) {
+        const uint32_t cnt = s_cnt[j];
+        for (uint32_t c0 = 0; c0 < cnt; c0 += 64, ++it) {
+          if (it % NW != wave) continue;  // wave-uniform
+          const uint32_t e = c0 + lane;
+          const bool act = e < cnt;
+          const int pix = act ? s_pix[j][e] : 0;
+          float wq = act ? s_wq[j][e] : 0.f;
+          float gHd = act ? s_gh[j][e] : 0.f;
+          const float pxc = (float)(tx * TW + pix % TW) + 0.5f;
+          const float pyc = (float)(ty * TH + pix / TW) + 0.5f;
+          const float L = ray_length(cam, pxc, pyc);
+          (void)L;
+          const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
+          const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
+          PairGeom G;
+          const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pxc, pyc, G, reinterpret_cast<const double*>(S.dq[j]));
+          if (!gh) {  // float64 discriminant says the ray misses: no gradient
+            wq = 0.f;
+            gHd = 0.f;
+          }
+          const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
+          float* acc = s_acc[j];
+          float gp0 = 0.f, gp1 = 0.f, gp2 = 0.f, ge0 = 0.f, ge1 = 0.f, ge2 = 0.f;
+#pragma unroll 2
+          for (int k = 0; k < N; ++k) {
+            const float4 w = S.tab[j][k];
+            const float w2 = tabf[4 * N + k];
+            const float ph = __builtin_fmaf(w.x, G.p0, __builtin_fmaf(w.y, G.p1, __builtin_fmaf(w.z, G.p2, w.w)));
+            const float hv = __builtin_fmaf(w.x, G.e0, __builtin_fmaf(w.y, G.e1, w.z * G.e2));
+            const float c = cos_rev(ph), s = sin_rev(ph);
+            const float sh = sin_rev(hv), ch = cos_rev(hv);
+            const float rh = fast_rcp(hv);
+            const float sn = fabsf(hv) < 1e-4f ? kTwoPi : sh * rh;
+            const float h = kTwoPi * hv, h2 = h * h;
+            const float series = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
+            const float dsn = fabsf(hv) < 0.02f ? series : (kTwoPi * ch - sn) * rh;
+            const float ww = wq * w2;
+            const float gph = -kTwoPi * ww * s * sn;  // d loss / d ph
+            const float ghv = ww * c * dsn;           // d loss / d hv
+            const float sW2 = wq * c * sn;
+            const float sWx = __builtin_fmaf(gph, G.p0, ghv * G.e0);
+            const float sWy = __builtin_fmaf(gph, G.p1, ghv * G.e1);
+            const float sWz = __builtin_fmaf(gph, G.p2, ghv * G.e2);
+            gp0 = __builtin_fmaf(gph, w.x, gp0);
+            gp1 = __builtin_fmaf(gph, w.y, gp1);
+            gp2 = __builtin_fmaf(gph, w.z, gp2);
+            ge0 = __builtin_fmaf(ghv, w.x, ge0);
+            ge1 = __builtin_fmaf(ghv, w.y, ge1);
+            ge2 = __builtin_fmaf(ghv, w.z, ge2);
+            wave_accumulate5(acc + 4 * k, acc + 4 * N + k, sWx, sWy, sWz, gph, sW2, lane);
+          }
+          wave_accumulate(acc + 5 * N, wq, lane);
+          // chain p', e', H -> d', m' -> record coefficients
+          float R[18];
 #pragma unroll
-        for (int r = 0; r < 18; ++r) R[r] = 0.f;
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-          if (wq[q] != 0.f) {
-            const PairGeom& G = g[q];
-            // e' = d' H
-            const float gH = gHq[q] + ge0[q] * G.d0 + ge1[q] * G.d1 + ge2[q] * G.d2;
-            float gd0 = ge0[q] * G.H, gd1 = ge1[q] * G.H, gd2 = ge2[q] * G.H;
-            // p' = X rA, X = d' x m'
-            const float gX0 = gp0[q] * G.rA, gX1 = gp1[q] * G.rA, gX2 = gp2[q] * G.rA;
-            const float gA_p = -(gp0[q] * G.p0 + gp1[q] * G.p1 + gp2[q] * G.p2) * G.rA;
-            // H = sq rA, sq = sqrt(A - M)
-            const float gdisc = gH * G.rA * 0.5f * fast_rcp(G.sq);
-            const float gA = gdisc - gH * G.H * G.rA + gA_p;
+          for (int r = 0; r < 18; ++r) R[r] = 0.f;
+          if (wq != 0.f || gHd != 0.f) {
+            const float gHt = gHd + ge0 * G.d0 + ge1 * G.d1 + ge2 * G.d2;
+            float gd0 = ge0 * G.H, gd1 = ge1 * G.H, gd2 = ge2 * G.H;
+            const float gX0 = gp0 * G.rA, gX1 = gp1 * G.rA, gX2 = gp2 * G.rA;
+            const float gA_p = -(gp0 * G.p0 + gp1 * G.p1 + gp2 * G.p2) * G.rA;
+            const float gdisc = gHt * G.rA * 0.5f * fast_rcp(G.sq);
+            const float gA = gdisc - gHt * G.H * G.rA + gA_p;
             const float gM = -gdisc;
-            // d' (A = d'.d', X = d' x m'),  m' (M = m'.m', X)
             gd0 += 2.f * gA * G.d0 + (G.m1 * gX2 - G.m2 * gX1);
             gd1 += 2.f * gA * G.d1 + (G.m2 * gX0 - G.m0 * gX2);
             gd2 += 2.f * gA * G.d2 + (G.m0 * gX1 - G.m1 * gX0);
             const float gm0 = 2.f * gM * G.m0 + (gX1 * G.d2 - gX2 * G.d1);
             const float gm1 = 2.f * gM * G.m1 + (gX2 * G.d0 - gX0 * G.d2);
             const float gm2 = 2.f * gM * G.m2 + (gX0 * G.d1 - gX1 * G.d0);
-            R[0] += gd0;
-            R[1] += gd1;
-            R[2] += gd2;
-            R[3] = __builtin_fmaf(gd0, G.dx, R[3]);
-            R[4] = __builtin_fmaf(gd1, G.dx, R[4]);
-            R[5] = __builtin_fmaf(gd2, G.dx, R[5]);
-            R[6] = __builtin_fmaf(gd0, G.dy, R[6]);
-            R[7] = __builtin_fmaf(gd1, G.dy, R[7]);
-            R[8] = __builtin_fmaf(gd2, G.dy, R[8]);
-            R[9] += gm0;
-            R[10] += gm1;
-            R[11] += gm2;
-            R[12] = __builtin_fmaf(gm0, G.dx, R[12]);
-            R[13] = __builtin_fmaf(gm1, G.dx, R[13]);
-            R[14] = __builtin_fmaf(gm2, G.dx, R[14]);
-            R[15] = __builtin_fmaf(gm0, G.dy, R[15]);
-            R[16] = __builtin_fmaf(gm1, G.dy, R[16]);
-            R[17] = __builtin_fmaf(gm2, G.dy, R[17]);
+            R[0] = gd0;
+            R[1] = gd1;
+            R[2] = gd2;
+            R[3] = gd0 * G.dx;
+            R[4] = gd1 * G.dx;
+            R[5] = gd2 * G.dx;
+            R[6] = gd0 * G.dy;
+            R[7] = gd1 * G.dy;
+            R[8] = gd2 * G.dy;
+            R[9] = gm0;
+            R[10] = gm1;
+            R[11] = gm2;
+            R[12] = gm0 * G.dx;
+            R[13] = gm1 * G.dx;
+            R[14] = gm2 * G.dx;
+            R[15] = gm0 * G.dy;
+            R[16] = gm1 * G.dy;
+            R[17] = gm2 * G.dy;
+          }
+#pragma unroll
+          for (int r = 0; r < 18; r += 6) {
+            wave_accumulate5(acc + TS + r, acc + TS + r + 4, R[r], R[r + 1], R[r + 2], R[r + 3], R[r + 4], lane);
+            wave_accumulate(acc + TS + r + 5, R[r + 5], lane);
           }
         }
-#pragma unroll
-        for (int r = 0; r < 18; ++r) wave_accumulate(acc + TS + r, R[r], lane);
       }
       // flush the batch's accumulators to HBM (one float atomic per nonzero
       // value, spread over the workgroup) and clear them
       __syncthreads();
       for (int idx = threadIdx.x; idx < nb * ACC; idx += NT) {
-        const int jj = idx / ACC, c = idx - jj * ACC;
-        float* slot = &s_acc[jj][c];
+        const int jj = idx / ACC, cc = idx - jj * ACC;
+        float* slot = &s_acc[jj][cc];
         const float val = *slot;
         if (val != 0.f) {
           const uint32_t p = S.id[jj];
-          if (c < TS)
-            atomic_add_f32(a.gtable + (int64_t)p * TS + c, val);
+          if (cc < TS)
+            atomic_add_f32(a.gtable + (int64_t)p * TS + cc, val);
           else
-            atomic_add_f32(a.gview + ((int64_t)v * a.P + p) * kGViewFloats + (c - TS), val);
+            atomic_add_f32(a.gview + ((int64_t)v * a.P + p) * kGViewFloats + (cc - TS), val);
           *slot = 0.f;
         }
       }
-      bool mine = true;
-#pragma unroll
-      for (int q = 0; q < PPL; ++q) mine = mine && done[q];
-      if (__syncthreads_and(mine)) break;
+      if (__syncthreads_and(done)) break;
     }
     if (!PERSIST) break;
   }
@@ -634,11 +618,14 @@ bool tile_supported(int tw, int th, int ppl) {
   return false;
 }
 
-// pixels per thread of the backward for a tile shape (the forward's list plus
-// one thread per pixel on 32 x 16 tiles)
-bool bwd_ppl_supported(int tw, int th, int ppl) {
-  if (tw == 32 && th == 16 && ppl == 1) return true;
-  return tile_supported(tw, th, ppl);
+// instances per backward batch for a tile shape; 0 picks the default
+int bwd_batch_default(int tw, int th) { return tw * th >= 512 ? 4 : (tw * th >= 256 ? 8 : 16); }
+
+bool bwd_batch_supported(int tw, int th, int nb) {
+  if (tw == 16 && th == 16) return nb == 4 || nb == 8 || nb == 16;
+  if (tw == 8 && th == 8) return nb == 16 || nb == 32;
+  if (tw == 32 && th == 16) return nb == 4 || nb == 8;
+  return false;
 }
 
 template <typename K>
@@ -674,15 +661,15 @@ static hipError_t fwd_shape(const RasterArgs& a, bool persist, bool count, hipSt
   return hipGetLastError();
 }
 
-template <int N, int TW, int TH, int PPL>
+template <int N, int TW, int TH, int NB>
 static hipError_t bwd_shape(const RasterArgs& a, bool persist, hipStream_t st) {
-  constexpr int NT = TW * TH / PPL;
+  constexpr int NT = TW * TH;
   if (a.total_tiles <= 0) return hipSuccess;
   if (persist) {
-    auto k = render_bwd_kernel<N, TW, TH, PPL, true>;
+    auto k = render_bwd_kernel<N, TW, TH, NB, true>;
     hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
   } else {
-    hipLaunchKernelGGL((render_bwd_kernel<N, TW, TH, PPL, false>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((render_bwd_kernel<N, TW, TH, NB, false>), dim3(a.total_tiles), dim3(NT), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -699,14 +686,14 @@ static hipError_t fwd_n(const RasterArgs& a, int tw, int th, int ppl, bool persi
 }
 
 template <int N>
-static hipError_t bwd_n(const RasterArgs& a, int tw, int th, int ppl, bool persist, hipStream_t st) {
-  if (tw == 16 && th == 16 && ppl == 1) return bwd_shape<N, 16, 16, 1>(a, persist, st);
-  if (tw == 16 && th == 16 && ppl == 2) return bwd_shape<N, 16, 16, 2>(a, persist, st);
-  if (tw == 16 && th == 16 && ppl == 4) return bwd_shape<N, 16, 16, 4>(a, persist, st);
-  if (tw == 8 && th == 8 && ppl == 1) return bwd_shape<N, 8, 8, 1>(a, persist, st);
-  if (tw == 32 && th == 16 && ppl == 1) return bwd_shape<N, 32, 16, 1>(a, persist, st);
-  if (tw == 32 && th == 16 && ppl == 2) return bwd_shape<N, 32, 16, 2>(a, persist, st);
-  if (tw == 32 && th == 16 && ppl == 4) return bwd_shape<N, 32, 16, 4>(a, persist, st);
+static hipError_t bwd_n(const RasterArgs& a, int tw, int th, int nb, bool persist, hipStream_t st) {
+  if (tw == 16 && th == 16 && nb == 4) return bwd_shape<N, 16, 16, 4>(a, persist, st);
+  if (tw == 16 && th == 16 && nb == 8) return bwd_shape<N, 16, 16, 8>(a, persist, st);
+  if (tw == 16 && th == 16 && nb == 16) return bwd_shape<N, 16, 16, 16>(a, persist, st);
+  if (tw == 8 && th == 8 && nb == 16) return bwd_shape<N, 8, 8, 16>(a, persist, st);
+  if (tw == 8 && th == 8 && nb == 32) return bwd_shape<N, 8, 8, 32>(a, persist, st);
+  if (tw == 32 && th == 16 && nb == 4) return bwd_shape<N, 32, 16, 4>(a, persist, st);
+  if (tw == 32 && th == 16 && nb == 8) return bwd_shape<N, 32, 16, 8>(a, persist, st);
   return hipErrorInvalidValue;
 }
 

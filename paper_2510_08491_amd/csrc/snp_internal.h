@@ -212,10 +212,11 @@ hipError_t launch_ranges(const unsigned long long* keys, const unsigned long lon
 // raster.hip
 int supported_tiles(int32_t* triples, int32_t max);
 bool tile_supported(int tw, int th, int ppl);
-bool bwd_ppl_supported(int tw, int th, int ppl);
+bool bwd_batch_supported(int tw, int th, int nb);
+int bwd_batch_default(int tw, int th);
 hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
                              hipStream_t st);
-hipError_t launch_render_bwd(int N, int tw, int th, int ppl, bool persist, const RasterArgs& a, hipStream_t st);
+hipError_t launch_render_bwd(int N, int tw, int th, int nb, bool persist, const RasterArgs& a, hipStream_t st);
 hipError_t launch_wave_sum_selftest(const float* in, float* out, int waves, hipStream_t st);
 // loss.hip
 size_t loss_scratch_bytes();

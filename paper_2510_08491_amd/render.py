@@ -33,7 +33,7 @@ class RenderConfig:
     alpha_max: float = 0.99
     bg: tuple = (0.0, 0.0, 0.0)
     persistent: int = 0
-    px_per_lane_bwd: int = 0
+    bwd_batch: int = 0
 
     def to_c(self) -> L.SnpConfig:
         c = L.SnpConfig()

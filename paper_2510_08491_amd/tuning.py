@@ -45,20 +45,38 @@ def _load() -> Dict:
 
 
 def lookup(N: int, color_mode: int, cams) -> Optional[Tuple[int, int, int, int]]:
-    """(tile_w, tile_h, px_per_lane, px_per_lane_bwd) tuned for this class, or None."""
+    """(tile_w, tile_h, px_per_lane, bwd_batch) tuned for this class, or None."""
     entry = _load().get(key_of(N, color_mode, cams))
     if not entry:
         return None
-    return tuple(entry["tile"]) + (int(entry.get("px_per_lane_bwd", entry["tile"][2])),)
+    return tuple(entry["tile"]) + (int(entry.get("bwd_batch", 0)),)
+
+
+def bwd_batches(base: RenderConfig, tw: int, th: int, cams) -> List[int]:
+    """Backward batch sizes the library accepts for a tile shape (asked by
+    validating a layout on the host)."""
+    out = []
+    for nb in (4, 8, 16, 32):
+        cfg = RenderConfig(**{**base.__dict__, "tile_w": tw, "tile_h": th, "bwd_batch": nb})
+        for ppl in (1, 2, 4):
+            cfg.px_per_lane = ppl
+            lay = L.SnpLayout()
+            from .render import camera_array
+            if L.lib().snp_workspace_layout(C.byref(cfg.to_c()), 1, len(cams), camera_array(cams), 1,
+                                            C.byref(lay)) == L.SNP_OK:
+                out.append(nb)
+                break
+    return out
 
 
 def autotune(base: RenderConfig, P: int, cams, params, targets: torch.Tensor, reps: int = 2,
              shapes=None, write=True, log=print):
-    """Times the rasterizer kernels for every tile shape and every pixels-per-
-    thread count of the forward and of the backward (HIP events around the
-    launches, best of `reps`), checks that each candidate renders the same
-    image as the first, and returns (best (tile_w, tile_h, ppl_fwd, ppl_bwd),
-    table)."""
+    """Times the rasterizer kernels for every tile shape, every forward
+    pixels-per-thread count and every backward batch size (HIP events around
+    the launches, best of `reps`); the forward time depends only on the
+    former, the backward time only on the latter.  Checks that each candidate
+    renders the same image as the first.  Returns (best (tile_w, tile_h,
+    px_per_lane, bwd_batch), table)."""
     fwd_shapes = shapes or supported_shapes()
     tiles = sorted({(s[0], s[1]) for s in fwd_shapes})
     results = {}
@@ -67,12 +85,11 @@ def autotune(base: RenderConfig, P: int, cams, params, targets: torch.Tensor, re
     best = None
     for tw, th in tiles:
         f_ppls = [s[2] for s in fwd_shapes if (s[0], s[1]) == (tw, th)]
-        b_ppls = sorted(set(f_ppls) | ({1} if (tw, th) == (32, 16) else set()))
+        nbs = bwd_batches(base, tw, th, cams)
+        runs = [(p, 0) for p in f_ppls] + [(f_ppls[0], nb) for nb in nbs]
         fwd_ms, bwd_ms = {}, {}
-        for ppl in sorted(set(f_ppls) | set(b_ppls)):
-            pf = ppl if ppl in f_ppls else f_ppls[0]
-            cfg = RenderConfig(**{**base.__dict__, "tile_w": tw, "tile_h": th, "px_per_lane": pf,
-                                  "px_per_lane_bwd": ppl})
+        for pf, nb in runs:
+            cfg = RenderConfig(**{**base.__dict__, "tile_w": tw, "tile_h": th, "px_per_lane": pf, "bwd_batch": nb})
             rast = Rasterizer(cfg, P, cams)
             inst = rast.prepare(params)
             rast._alloc(int(inst * 1.1) + 4096)
@@ -93,26 +110,27 @@ def autotune(base: RenderConfig, P: int, cams, params, targets: torch.Tensor, re
             if ref_img is None:
                 ref_img = images.clone()
             diff = float((images - ref_img).abs().max())
-            if pf == ppl:
-                fwd_ms[ppl] = fb
-            bwd_ms[ppl] = bb
-            results[f"{tw}x{th} fwd{pf} bwd{ppl}"] = dict(fwd_ms=fb, bwd_ms=bb, img_diff=diff)
-            log(f"[tune] tile {tw}x{th} ppl fwd {pf} bwd {ppl}: forward {fb:.3f} ms, backward {bb:.3f} ms, "
-                f"image diff {diff:.2e}")
+            if nb == 0:
+                fwd_ms[pf] = fb
+            else:
+                bwd_ms[nb] = bb
+            results[f"{tw}x{th} ppl{pf} batch{nb}"] = dict(fwd_ms=fb, bwd_ms=bb, img_diff=diff)
+            log(f"[tune] tile {tw}x{th} ppl {pf} bwd batch {nb or 'default'}: forward {fb:.3f} ms, "
+                f"backward {bb:.3f} ms, image diff {diff:.2e}")
             if diff > 1e-5:
-                raise RuntimeError(f"tile {tw}x{th}/{ppl} renders a different image ({diff})")
+                raise RuntimeError(f"tile {tw}x{th}/{pf} renders a different image ({diff})")
             del rast, images, T, dL, grads
             torch.cuda.empty_cache()
         pf = min(fwd_ms, key=fwd_ms.get)
-        pb = min(bwd_ms, key=bwd_ms.get)
-        total = fwd_ms[pf] + bwd_ms[pb]
+        nb = min(bwd_ms, key=bwd_ms.get)
+        total = fwd_ms[pf] + bwd_ms[nb]
         if best is None or total < best[0]:
-            best = (total, (tw, th, pf, pb))
+            best = (total, (tw, th, pf, nb))
     best_shape = best[1]
     if write:
         cache = _load()
         cache[key_of(base.n_hidden, base.color_mode, cams)] = {
-            "tile": list(best_shape[:3]), "px_per_lane_bwd": best_shape[3], "ms": best[0], "candidates": results}
+            "tile": list(best_shape[:3]), "bwd_batch": best_shape[3], "ms": best[0], "candidates": results}
         with open(CACHE, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return best_shape, results

@@ -166,7 +166,7 @@ def test_c1_gradients():
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 4), (32, 16, 2), (32, 16, 2, 1), (32, 16, 4, 2), (8, 8, 1)])
+@pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 4), (32, 16, 2), (32, 16, 2, 4), (16, 16, 4, 16), (8, 8, 1, 32)])
 def test_gradients_multiview_tiles(tile):
     scene = S.custom_scene(400, 8, seed=101)
     cams = S.make_cameras([(72, 56), (48, 64)], seed=102)
@@ -175,7 +175,7 @@ def test_gradients_multiview_tiles(tile):
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 2), (32, 16, 2, 1)])
+@pytest.mark.parametrize("tile", [(16, 16, 2), (32, 16, 2, 8)])
 def test_colour_mlp_gradients(tile):
     scene = S.custom_scene(300, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=111)
     cams = S.make_cameras([(64, 48), (48, 40), (56, 56)], seed=112)
