@@ -337,6 +337,57 @@ __device__ __forceinline__ void wave_accumulate5(float* a, float* b, float x, fl
   }
 }
 
+// Transposed butterfly over the 16 lanes of a row.  One level combines two
+// registers a, b across partner lanes: a lane whose selector bit is set keeps
+// b and sends a, its partner keeps a and sends b, and each adds what it
+// receives, so the pair of lanes ends with the pair sum of a in one lane and
+// of b in the other.  Four levels with partners lane^7 (row_half_mirror),
+// lane^1, lane^2 and lane^8 (row_ror:8) and selector bits 2, 0, 1, 3 reduce
+// 16 registers to one in which row lane r holds the row sum of value
+// 8 b3 + 4 b1 + 2 b0 + b2 (b = the bits of r): 45 VALU operations for 16
+// sums, against 64 and 16 LDS atomics for one plain butterfly per value.
+constexpr int kDppXor1 = 0xB1;        // quad_perm 1,0,3,2
+constexpr int kDppXor2 = 0x4E;        // quad_perm 2,3,0,1
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror: lane ^ 7 within 8
+constexpr int kDppRor8 = 0x128;       // row_ror:8: lane ^ 8 within the row
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_from_partner(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float tb_level(float a, float b, bool sel) {
+  const float keep = sel ? b : a, send = sel ? a : b;
+  return keep + dpp_from_partner<CTRL>(send);
+}
+
+// plain butterfly level (one value): both partners end with the pair sum
+template <int CTRL>
+__device__ __forceinline__ float nb_level(float a) {
+  return a + dpp_from_partner<CTRL>(a);
+}
+
+// Row sums of 8 registers: three transposed levels, then a plain one over
+// lane^8.  Row lane r ends with the row sum of v[4 b1 + 2 b0 + b2]; lanes
+// r and r^8 hold the same sum.
+__device__ __forceinline__ float reduce8(const float (&v)[8], bool sel1, bool sel2, bool sel3) {
+  const float w0 = tb_level<kDppHalfMirror>(v[0], v[1], sel1);
+  const float w1 = tb_level<kDppHalfMirror>(v[2], v[3], sel1);
+  const float w2 = tb_level<kDppHalfMirror>(v[4], v[5], sel1);
+  const float w3 = tb_level<kDppHalfMirror>(v[6], v[7], sel1);
+  const float x0 = tb_level<kDppXor1>(w0, w1, sel2);
+  const float x1 = tb_level<kDppXor1>(w2, w3, sel2);
+  return nb_level<kDppRor8>(tb_level<kDppXor2>(x0, x1, sel3));
+}
+
+// Row sums of 2 registers: one transposed level, then plain levels over
+// lane^1, lane^2 and lane^8.  Row lane r ends with the row sum of a if bit 2
+// of r is clear, else of b.
+__device__ __forceinline__ float reduce2(float a, float b, bool sel1) {
+  return nb_level<kDppRor8>(nb_level<kDppXor2>(nb_level<kDppXor1>(tb_level<kDppHalfMirror>(a, b, sel1))));
+}
+
 // Length of the un-normalised camera ray R^-1 ((x+1/2-cx)/fx, (y+1/2-cy)/fy, 1).
 __device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float pyc) {
   const float cxn = (pxc - cam.cx) / cam.fx;
@@ -363,7 +414,7 @@ __device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float 
 // once per batch.  Every lane of phase 2 carries gradient, and each wave
 // reduction covers 64 live pairs.
 template <int N, int TW, int TH, int NB, bool PERSIST>
-__global__ void __launch_bounds__(TW * TH) render_bwd_kernel(RasterArgs a) {
+__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5))) render_bwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
   constexpr int TS = 5 * N + 4;
@@ -377,6 +428,11 @@ __global__ void __launch_bounds__(TW * TH) render_bwd_kernel(RasterArgs a) {
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // selector bits and value index of the transposed row reductions
+  const bool sel1 = lane & 4, sel2 = lane & 1, sel3 = lane & 2, sel4 = lane & 8;
+  const int idx16 = 8 * ((lane >> 3) & 1) + 4 * ((lane >> 1) & 1) + 2 * (lane & 1) + ((lane >> 2) & 1);
+  const int idx8 = idx16 & 7;                  // value index of reduce8 (lanes with bit 3 clear write)
+  const bool lo2 = (lane & 11) == 0;           // writers of reduce2: lanes 0 and 4 of each row
   for (int idx = threadIdx.x; idx < NB * ACC; idx += NT) (&s_acc[0][0])[idx] = 0.f;
   int item = blockIdx.x;
   while (true) {
@@ -486,8 +542,6 @@ __global__ void __launch_bounds__(TW * TH) render_bwd_kernel(RasterArgs a) {
           float gHd = act ? s_gh[j][e] : 0.f;
           const float pxc = (float)(tx * TW + pix % TW) + 0.5f;
           const float pyc = (float)(ty * TH + pix / TW) + 0.5f;
-          const float L = ray_length(cam, pxc, pyc);
-          (void)L;
           const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
           const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
           PairGeom G;
@@ -496,39 +550,62 @@ __global__ void __launch_bounds__(TW * TH) render_bwd_kernel(RasterArgs a) {
             wq = 0.f;
             gHd = 0.f;
           }
+          const float4* tab = S.tab[j];
           const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
           float* acc = s_acc[j];
           float gp0 = 0.f, gp1 = 0.f, gp2 = 0.f, ge0 = 0.f, ge1 = 0.f, ge2 = 0.f;
-#pragma unroll 2
-          for (int k = 0; k < N; ++k) {
-            const float4 w = S.tab[j][k];
-            const float w2 = tabf[4 * N + k];
-            const float ph = __builtin_fmaf(w.x, G.p0, __builtin_fmaf(w.y, G.p1, __builtin_fmaf(w.z, G.p2, w.w)));
-            const float hv = __builtin_fmaf(w.x, G.e0, __builtin_fmaf(w.y, G.e1, w.z * G.e2));
-            const float c = cos_rev(ph), s = sin_rev(ph);
-            const float sh = sin_rev(hv), ch = cos_rev(hv);
-            const float rh = fast_rcp(hv);
-            const float sn = fabsf(hv) < 1e-4f ? kTwoPi : sh * rh;
-            const float h = kTwoPi * hv, h2 = h * h;
-            const float series = kTwoPi * kTwoPi * h * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
-            const float dsn = fabsf(hv) < 0.02f ? series : (kTwoPi * ch - sn) * rh;
-            const float ww = wq * w2;
-            const float gph = -kTwoPi * ww * s * sn;  // d loss / d ph
-            const float ghv = ww * c * dsn;           // d loss / d hv
-            const float sW2 = wq * c * sn;
-            const float sWx = __builtin_fmaf(gph, G.p0, ghv * G.e0);
-            const float sWy = __builtin_fmaf(gph, G.p1, ghv * G.e1);
-            const float sWz = __builtin_fmaf(gph, G.p2, ghv * G.e2);
-            gp0 = __builtin_fmaf(gph, w.x, gp0);
-            gp1 = __builtin_fmaf(gph, w.y, gp1);
-            gp2 = __builtin_fmaf(gph, w.z, gp2);
-            ge0 = __builtin_fmaf(ghv, w.x, ge0);
-            ge1 = __builtin_fmaf(ghv, w.y, ge1);
-            ge2 = __builtin_fmaf(ghv, w.z, ge2);
-            wave_accumulate5(acc + 4 * k, acc + 4 * N + k, sWx, sWy, sWz, gph, sW2, lane);
+          // units in pairs: the pair's 10 table-gradient terms are summed over
+          // the wave right away (8 by a three-level and 2 by a one-level
+          // transposed reduction) and added to LDS with two atomics
+#pragma unroll 1
+          for (int k0 = 0; k0 < N; k0 += 2) {
+            float v8[8], v2[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const int k = k0 + u;
+              const float4 w = tab[k];
+              const float w2 = tabf[4 * N + k];
+              const float ph = __builtin_fmaf(w.x, G.p0, __builtin_fmaf(w.y, G.p1, __builtin_fmaf(w.z, G.p2, w.w)));
+              const float hv = __builtin_fmaf(w.x, G.e0, __builtin_fmaf(w.y, G.e1, w.z * G.e2));
+              const float c = cos_rev(ph), s = sin_rev(ph);
+              const float sh = sin_rev(hv), ch = cos_rev(hv);
+              const float rh = fast_rcp(hv);
+              const float ahv = fabsf(hv);
+              const float sn = ahv < 1e-4f ? kTwoPi : sh * rh;
+              const float hh = kTwoPi * hv, h2 = hh * hh;
+              const float series = kTwoPi * kTwoPi * hh * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
+              const float general = (kTwoPi * ch - sn) * rh;
+              const float dsn = ahv < 0.02f ? series : general;
+              const float ww = wq * w2;
+              const float gph = -kTwoPi * ww * s * sn;  // d loss / d ph
+              const float ghv = ww * c * dsn;           // d loss / d hv
+              v8[0 + u] = __builtin_fmaf(gph, G.p0, ghv * G.e0);
+              v8[2 + u] = __builtin_fmaf(gph, G.p1, ghv * G.e1);
+              v8[4 + u] = __builtin_fmaf(gph, G.p2, ghv * G.e2);
+              v8[6 + u] = gph;
+              v2[u] = wq * c * sn;
+              gp0 = __builtin_fmaf(gph, w.x, gp0);
+              gp1 = __builtin_fmaf(gph, w.y, gp1);
+              gp2 = __builtin_fmaf(gph, w.z, gp2);
+              ge0 = __builtin_fmaf(ghv, w.x, ge0);
+              ge1 = __builtin_fmaf(ghv, w.y, ge1);
+              ge2 = __builtin_fmaf(ghv, w.z, ge2);
+            }
+            // v8[i] is component i / 2 of unit k0 + i % 2: table slot 4 (k0 + i % 2) + i / 2
+            const float z8 = reduce8(v8, sel1, sel2, sel3);
+            if (!sel4) atomicAdd(acc + 4 * (k0 + (idx8 & 1)) + (idx8 >> 1), z8);
+            const float z2 = reduce2(v2[0], v2[1], sel1);
+            if (lo2) atomicAdd(acc + 4 * N + k0 + (int)sel1, z2);
           }
-          wave_accumulate(acc + 5 * N, wq, lane);
-          // chain p', e', H -> d', m' -> record coefficients
+          // chain p', e', H -> d', m' -> record coefficients.  The geometry is
+          // recomputed from LDS here (the barrier keeps the compiler from reusing
+          // the first computation), so only p' and e' stay live through the unit loop.
+          asm volatile("" ::: "memory");
+          {
+            const float4 q0 = S.rec[j][0], q1 = S.rec[j][1], q2 = S.rec[j][2];
+            const float4 q3 = S.rec[j][3], q4 = S.rec[j][4], q5 = S.rec[j][5];
+            pair_geom(q0, q1, q2, q3, q4, q5, pxc, pyc, G, reinterpret_cast<const double*>(S.dq[j]));
+          }
           float R[18];
 #pragma unroll
           for (int r = 0; r < 18; ++r) R[r] = 0.f;
@@ -565,10 +642,22 @@ __global__ void __launch_bounds__(TW * TH) render_bwd_kernel(RasterArgs a) {
             R[16] = gm1 * G.dy;
             R[17] = gm2 * G.dy;
           }
+          {
+            // record coefficients 0..15: one full transposed reduction
+            float x4[4];
 #pragma unroll
-          for (int r = 0; r < 18; r += 6) {
-            wave_accumulate5(acc + TS + r, acc + TS + r + 4, R[r], R[r + 1], R[r + 2], R[r + 3], R[r + 4], lane);
-            wave_accumulate(acc + TS + r + 5, R[r + 5], lane);
+            for (int q = 0; q < 4; ++q)
+              x4[q] = tb_level<kDppXor1>(tb_level<kDppHalfMirror>(R[4 * q], R[4 * q + 1], sel1),
+                                         tb_level<kDppHalfMirror>(R[4 * q + 2], R[4 * q + 3], sel1), sel2);
+            const float z = tb_level<kDppRor8>(tb_level<kDppXor2>(x4[0], x4[1], sel3),
+                                               tb_level<kDppXor2>(x4[2], x4[3], sel3), sel4);
+            atomicAdd(acc + TS + idx16, z);
+            // coefficients 16, 17 and the b2 gradient (sum of d loss / d Q)
+            const float t4 = nb_level<kDppRor8>(nb_level<kDppXor2>(
+                tb_level<kDppXor1>(tb_level<kDppHalfMirror>(R[16], R[17], sel1),
+                                   tb_level<kDppHalfMirror>(wq, 0.f, sel1), sel2)));
+            const int i4 = idx16 & 3;
+            if (!sel3 && !sel4 && i4 < 3) atomicAdd(i4 == 2 ? acc + 5 * N : acc + TS + 16 + i4, t4);
           }
         }
       }
