@@ -40,8 +40,13 @@ def ops_per_pair(N):
     with a positive, unclamped integral, which carry gradient)."""
     fwd_v, fwd_t = 50 + 11 * N, 3 * N + 3
     bwd_hit_v, bwd_hit_t = fwd_v + 25, fwd_t
+    # with the forward's pair integrals at hand, a hit pair in the backward
+    # needs the chord only (ray frame, discriminant, sqrt, 1/A: 26 ops + 2),
+    # alpha (exp2) and the blending and d loss / d integral (40 ops + 1/H)
+    bwd_hit_cached_v, bwd_hit_cached_t = 66, 4
     bwd_live_v, bwd_live_t = 32 * N + 60, 6 * N + 1
-    return dict(fwd=(fwd_v, fwd_t), bwd_hit=(bwd_hit_v, bwd_hit_t), bwd_live=(bwd_live_v, bwd_live_t))
+    return dict(fwd=(fwd_v, fwd_t), bwd_hit=(bwd_hit_v, bwd_hit_t), bwd_hit_cached=(bwd_hit_cached_v, bwd_hit_cached_t),
+                bwd_live=(bwd_live_v, bwd_live_t))
 
 
 def slots(vt):
@@ -101,7 +106,8 @@ def main(argv=None):
     rast.forward(params, images, final_T, count_pairs=True)
     cnt = rast.counters()
     hit_pairs, live_pairs = cnt["hit_pairs"], cnt["live_pairs"]
-    log(f"[bench] instances {inst}, hit pairs {hit_pairs}, live pairs {live_pairs}")
+    log(f"[bench] instances {inst}, hit pairs {hit_pairs}, live pairs {live_pairs}, "
+        f"pair cache {rast.fwd_cache} ({rast.layout.ahat_cache_bytes / 2 ** 30:.1f} GiB)")
     if a.eager_only:
         loss = torch.zeros(1, dtype=torch.float64, device="cuda")
         dL = torch.empty_like(images)
@@ -146,6 +152,11 @@ def main(argv=None):
     rmod.kernel_timing(False)
     fwd_ms, bwd_ms = float(np.mean(fwd_ms)), float(np.mean(bwd_ms))
     log(f"[bench] raster kernels: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
+    pair_cache = rast.fwd_cache
+    cache_gb = rast.layout.ahat_cache_bytes / 2 ** 30
+    # the per-view rasterizers below need their own workspaces
+    del step, rast, images, final_T, dL, grads
+    torch.cuda.empty_cache()
 
     # ---- per-view plain launches ---------------------------------------------------------
     per_view_ms = None
@@ -190,7 +201,8 @@ def main(argv=None):
     # ---- roofline of the dominant kernel ----------------------------------------------------
     ops = ops_per_pair(N)
     fwd_slots = hit_pairs * slots(ops["fwd"])
-    bwd_slots = hit_pairs * slots(ops["bwd_hit"]) + live_pairs * slots(ops["bwd_live"])
+    bwd_slots = hit_pairs * slots(ops["bwd_hit_cached" if pair_cache else "bwd_hit"]) + \
+        live_pairs * slots(ops["bwd_live"])
     if bwd_ms >= fwd_ms:
         dom, dom_ms, dom_slots = "render_bwd", bwd_ms, bwd_slots
     else:
@@ -224,7 +236,8 @@ def main(argv=None):
         "data": "synthetic (seeded primitives, random-pose cameras, random targets)",
         "config": {"workload": workload_name(a.workload, cams), "primitives": scene["P"], "n_hidden": N,
                    "colour_mlp": [scene["cmlp_width"], scene["cmlp_depth"]], "tile": list(tile),
-                   "batched": "one HIP graph per step, persistent rasterizer launches"},
+                   "batched": "one HIP graph per step, persistent rasterizer launches",
+                   "pair_cache": pair_cache, "pair_cache_gib": round(cache_gb, 2)},
         "hit_pairs_per_step": hit_pairs,
         "live_pairs_per_step": live_pairs,
         "instances_per_step": inst,

@@ -84,7 +84,13 @@ typedef struct {
  *             with a device work queue; 0 = one workgroup per tile.
  *  bwd_batch  instances per batch of the backward rasterizer (0 = the
  *             default for the tile shape); the tile shape is shared with the
- *             forward, and the backward runs one pixel per thread. */
+ *             forward, and the backward runs one pixel per thread.
+ *  fwd_cache  1 = the forward stores the integral (alpha-hat, Eq. 8-9) of
+ *             every (pixel, instance) pair it evaluates, capacity x tile_w x
+ *             tile_h floats in the workspace, and the backward reads it back
+ *             instead of evaluating the density MLP again; a backward must
+ *             then follow a forward of the same step on the same workspace.
+ *             0 = the backward re-evaluates every pair (no extra memory). */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -95,6 +101,7 @@ typedef struct {
   float bg[3];
   int32_t persistent;
   int32_t bwd_batch;
+  int32_t fwd_cache;
 } snp_config;
 
 typedef struct {
@@ -134,6 +141,8 @@ typedef struct {
   int64_t capacity;       /* tile-instance capacity */
   int32_t table_stride;   /* floats per table row */
   int32_t total_tiles;    /* tiles over all views */
+  size_t ahat_cache;      /* fwd_cache = 1: float per (instance, tile pixel), else unused */
+  size_t ahat_cache_bytes; /* 0 when fwd_cache = 0 */
 } snp_layout;
 
 /* Size and layout of the workspace for P primitives seen by V cameras with

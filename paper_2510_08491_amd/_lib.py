@@ -22,7 +22,8 @@ class SnpConfig(C.Structure):
                 ("cmlp_width", C.c_int32), ("cmlp_depth", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("px_per_lane", C.c_int32), ("z_near", C.c_float),
                 ("t_eps", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
-                ("bg", C.c_float * 3), ("persistent", C.c_int32), ("bwd_batch", C.c_int32)]
+                ("bg", C.c_float * 3), ("persistent", C.c_int32), ("bwd_batch", C.c_int32),
+                ("fwd_cache", C.c_int32)]
 
 
 class SnpPrims(C.Structure):
@@ -39,7 +40,8 @@ class SnpLayout(C.Structure):
     _fields_ = [(k, C.c_size_t) for k in
                 ("bytes", "cams", "table", "records", "rects", "depth_bits", "tile_counts", "offsets", "keys",
                  "values", "ranges", "counters", "gview", "gtable", "loss", "disc_coef")] + \
-               [("capacity", C.c_int64), ("table_stride", C.c_int32), ("total_tiles", C.c_int32)]
+               [("capacity", C.c_int64), ("table_stride", C.c_int32), ("total_tiles", C.c_int32),
+                ("ahat_cache", C.c_size_t), ("ahat_cache_bytes", C.c_size_t)]
 
 
 _lib = None

@@ -28,7 +28,9 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-a
           # atomics here are issued on already reduced values; the compiler's
           # atomic optimizer would wrap each one in a loop over the lanes
           "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+          # an occupancy request that the LDS of a large batch already rules out
+          "-Wno-pass-failed"]
 PER_FILE = {
     # float64 key path: one fixed operation order, no contraction
     "preprocess.hip": ["-ffp-contract=off"],

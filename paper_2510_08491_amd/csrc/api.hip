@@ -36,6 +36,7 @@ static snp_status check_cfg(const snp_config* cfg) {
   if (cfg->persistent != 0 && cfg->persistent != 1) return SNP_ERR_INVALID;
   if (cfg->bwd_batch != 0 && !bwd_batch_supported(cfg->tile_w, cfg->tile_h, cfg->bwd_batch))
     return SNP_ERR_UNSUPPORTED;
+  if (cfg->fwd_cache != 0 && cfg->fwd_cache != 1) return SNP_ERR_INVALID;
   return SNP_OK;
 }
 
@@ -109,6 +110,10 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   L.ranges = take(sizeof(uint32_t) * 2 * (size_t)tiles);
   L.gview = take(sizeof(float) * (size_t)VP * kGViewFloats);
   L.gtable = take(sizeof(float) * (size_t)P * TS);
+  if (cfg->fwd_cache) {
+    L.ahat_cache_bytes = sizeof(float) * (size_t)cap * (size_t)(cfg->tile_w * cfg->tile_h);
+    L.ahat_cache = take(L.ahat_cache_bytes);
+  }
   L.bytes = off;
   L.capacity = cap;
   L.table_stride = TS;
@@ -248,6 +253,7 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   a.gview = wsp<float>(ws, L.gview);
   a.gtable = wsp<float>(ws, L.gtable);
   a.disc_coef = wsp<double>(ws, L.disc_coef);
+  a.ahat_cache = cfg->fwd_cache ? wsp<float>(ws, L.ahat_cache) : nullptr;
   a.counters = wsp<unsigned long long>(ws, L.counters);
   a.t_eps = cfg->t_eps;
   a.alpha_min = cfg->alpha_min;
@@ -391,7 +397,8 @@ static bool same_layout(const snp_layout& a, const snp_layout& b) {
          a.offsets == b.offsets && a.keys == b.keys && a.values == b.values && a.ranges == b.ranges &&
          a.counters == b.counters && a.gview == b.gview && a.gtable == b.gtable && a.loss == b.loss &&
          a.disc_coef == b.disc_coef &&
-         a.capacity == b.capacity && a.table_stride == b.table_stride && a.total_tiles == b.total_tiles;
+         a.capacity == b.capacity && a.table_stride == b.table_stride && a.total_tiles == b.total_tiles &&
+         a.ahat_cache == b.ahat_cache && a.ahat_cache_bytes == b.ahat_cache_bytes;
 }
 
 // Rebuilds the plan of a call from its arguments and checks it against the

@@ -246,12 +246,19 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
           }
         }
         const float b2 = tabf[5 * N];
+        float ahat[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) ahat[q] = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
+        if (a.ahat_cache) {  // every lane of an evaluated wave stores (misses store 0)
+          float* cp = a.ahat_cache + (int64_t)(b0 + j) * (TW * TH) + (threadIdx.x / TW) * PPL * TW + threadIdx.x % TW;
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) cp[q * TW] = ahat[q];
+        }
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
           if (hit[q]) {
-            const float ahat = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
-            const float al = alpha_of(ahat, a.alpha_max);
-            if (COUNT) nlive += (ahat > 0.f && al < a.alpha_max) ? 1 : 0;
+            const float al = alpha_of(ahat[q], a.alpha_max);
+            if (COUNT) nlive += (ahat[q] > 0.f && al < a.alpha_max) ? 1 : 0;
             if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
               const float w = al * T[q];
               C0[q] = __builtin_fmaf(r2.w, w, C0[q]);
@@ -465,32 +472,39 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
       if (threadIdx.x < NB) s_cnt[threadIdx.x] = 0u;
       stage_batch<N, true, NT, NB>(S, a, v, b0, nb);
       // ---------------- phase 1: pixels ----------------
-      for (int j = 0; j < nb; ++j) {
+      // One instance for this thread's pixel.  `cached`: the integral comes
+      // from the forward's store (ahc) instead of the density MLP.
+      auto pixel_step = [&](const int j, const bool cached, const float ahc) {
         const int4 rc = S.rect[j];
-        if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
+        if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) return;  // wave-uniform
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
         PairGeom g;
         const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[0], pb.pyc[0], g);
         const bool hit = !done && gh;
-        if (__ballot(hit) == 0) continue;  // wave-uniform
-        const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
-        float Q = 0.f;
+        if (__ballot(hit) == 0) return;  // wave-uniform
+        float ahat, QB = 0.f;  // QB = Q + b2 (recomputed path only)
+        if (cached) {
+          ahat = ahc;
+        } else {
+          const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
+          float Q = 0.f;
 #pragma unroll 4
-        for (int k = 0; k < N; ++k) {
-          const float4 w = S.tab[j][k];
-          const float w2 = tabf[4 * N + k];
-          const float ph = __builtin_fmaf(w.x, g.p0, __builtin_fmaf(w.y, g.p1, __builtin_fmaf(w.z, g.p2, w.w)));
-          const float hv = __builtin_fmaf(w.x, g.e0, __builtin_fmaf(w.y, g.e1, w.z * g.e2));
-          const float c = cos_rev(ph);
-          const float sn = sinc_rev(sin_rev(hv), hv);
-          Q = __builtin_fmaf(w2 * c, sn, Q);
+          for (int k = 0; k < N; ++k) {
+            const float4 w = S.tab[j][k];
+            const float w2 = tabf[4 * N + k];
+            const float ph = __builtin_fmaf(w.x, g.p0, __builtin_fmaf(w.y, g.p1, __builtin_fmaf(w.z, g.p2, w.w)));
+            const float hv = __builtin_fmaf(w.x, g.e0, __builtin_fmaf(w.y, g.e1, w.z * g.e2));
+            const float c = cos_rev(ph);
+            const float sn = sinc_rev(sin_rev(hv), hv);
+            Q = __builtin_fmaf(w2 * c, sn, Q);
+          }
+          QB = Q + tabf[5 * N];
+          ahat = 2.f * pb.L[0] * g.H * QB;
         }
-        const float b2 = tabf[5 * N];
         float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, wq = 0.f, gH = 0.f;
         bool live = false;
         if (hit) {
-          const float ahat = 2.f * pb.L[0] * g.H * (Q + b2);
           const float al = alpha_of(ahat, a.alpha_max);
           if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
             const float wt = al * T;
@@ -503,18 +517,23 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
             if (ahat > 0.f && al < a.alpha_max) {
               const float ta = T * (1.f - al);
               const float G = G0 * (r2.w * ta - (F0 - A0)) + G1 * (r3.w * ta - (F1 - A1)) + G2 * (r4.w * ta - (F2 - A2));
-              wq = G * 2.f * pb.L[0] * g.H;       // d loss / d Q
-              gH = G * 2.f * pb.L[0] * (Q + b2);  // d loss / d H (direct)
+              wq = G * 2.f * pb.L[0] * g.H;  // d loss / d Q
+              // d loss / d H (direct) = G 2 L (Q + b2); from the stored integral
+              // alpha-hat = 2 L H (Q + b2) when cached (H > 0 for a hit)
+              gH = cached ? G * ahat * fast_rcp(g.H) : G * 2.f * pb.L[0] * QB;
               live = wq != 0.f || gH != 0.f;
             }
             T = T * (1.f - al);
             if (T < a.t_eps) done = true;
           }
         }
-        float* acc = s_acc[j];
-        wave_accumulate(acc + TS + 18, gc0, lane);
-        wave_accumulate(acc + TS + 19, gc1, lane);
-        wave_accumulate(acc + TS + 20, gc2, lane);
+        // colour gradient: one transposed reduction of the three sums
+        {
+          const float z = nb_level<kDppRor8>(nb_level<kDppXor2>(
+              tb_level<kDppXor1>(tb_level<kDppHalfMirror>(gc0, gc1, sel1), tb_level<kDppHalfMirror>(gc2, 0.f, sel1), sel2)));
+          const int i4 = idx16 & 3;
+          if (!sel3 && !sel4 && i4 < 3) atomicAdd(s_acc[j] + TS + 18 + i4, z);
+        }
         const unsigned long long lm = __ballot(live);
         if (lm) {
           uint32_t base = 0;
@@ -527,6 +546,26 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
             s_gh[j][pos] = gH;
           }
         }
+      };
+      if (a.ahat_cache) {
+        // the forward's integrals of this batch, fetched together (only for
+        // instances whose rectangle meets this wave's pixels)
+        float pre[NB];
+        const float* cp = a.ahat_cache + (int64_t)b0 * NT + threadIdx.x;
+        const bool wave_live = __ballot(!done) != 0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          pre[j] = 0.f;
+          if (j < nb && wave_live) {
+            const int4 rc = S.rect[j];
+            if (!(rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1)) pre[j] = cp[(int64_t)j * NT];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j < nb) pixel_step(j, true, pre[j]);
+      } else {
+        for (int j = 0; j < nb; ++j) pixel_step(j, false, 0.f);
       }
       __syncthreads();
       // ---------------- phase 2: live pairs ----------------

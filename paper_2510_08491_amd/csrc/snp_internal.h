@@ -182,6 +182,8 @@ struct RasterArgs {
   float* gview;
   float* gtable;
   const double* disc_coef;  // backward: float64 discriminant near silhouettes
+  float* ahat_cache;        // per (instance, tile pixel) integral: the forward writes it,
+                            // the backward reads it (null: the backward re-evaluates)
   unsigned long long* counters;
   float t_eps, alpha_min, alpha_max;
   float bg0, bg1, bg2;

@@ -34,10 +34,19 @@ class RenderConfig:
     bg: tuple = (0.0, 0.0, 0.0)
     persistent: int = 0
     bwd_batch: int = 0
+    # 1: the forward keeps every evaluated pair's integral for the backward
+    # (capacity x tile pixels floats) when it fits the memory budget below;
+    # 0: the backward re-evaluates the density MLP
+    fwd_cache: int = 1
+    # device bytes the pair cache may take; None: 85% of the free memory
+    # left after the rest of the workspace
+    fwd_cache_budget: Optional[int] = None
 
     def to_c(self) -> L.SnpConfig:
         c = L.SnpConfig()
         for f in dataclasses.fields(self):
+            if f.name == "fwd_cache_budget":
+                continue
             if f.name == "bg":
                 c.bg = (C.c_float * 3)(*self.bg)
             else:
@@ -103,13 +112,24 @@ class Rasterizer:
         self._alloc(capacity if capacity is not None else max(1 << 16, 8 * self.P))
 
     # -- workspace ---------------------------------------------------------------
-    def _alloc(self, capacity: int):
+    def _layout(self, capacity: int, fwd_cache: int) -> L.SnpLayout:
+        self.ccfg.fwd_cache = int(fwd_cache)
         lay = L.SnpLayout()
         L.check(L.lib().snp_workspace_layout(C.byref(self.ccfg), self.P, self.V, self.ccams, int(capacity),
                                              C.byref(lay)), "snp_workspace_layout")
-        self.layout = lay
+        return lay
+
+    def _alloc(self, capacity: int):
         self.ws = None
-        torch.cuda.empty_cache() if False else None
+        lay = self._layout(capacity, self.cfg.fwd_cache)
+        if lay.ahat_cache_bytes:
+            budget = self.cfg.fwd_cache_budget
+            if budget is None:
+                free, _ = torch.cuda.mem_get_info(torch.device(self.device))
+                budget = int(0.85 * (free - (lay.bytes - lay.ahat_cache_bytes)))
+            if lay.ahat_cache_bytes > budget:  # does not fit: the backward re-evaluates
+                lay = self._layout(capacity, 0)
+        self.layout = lay
         self.ws = torch.empty(lay.bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.ws.data_ptr()) % 256
         self._ws_off = off
@@ -118,6 +138,11 @@ class Rasterizer:
     @property
     def capacity(self) -> int:
         return int(self.layout.capacity)
+
+    @property
+    def fwd_cache(self) -> bool:
+        """True when the forward keeps the pair integrals for the backward."""
+        return bool(self.ccfg.fwd_cache)
 
     def _view(self, field: str, dtype, count: int) -> torch.Tensor:
         start = self._ws_off + getattr(self.layout, field)

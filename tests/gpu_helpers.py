@@ -16,12 +16,14 @@ def say(msg):
     sys.stdout.flush()
 
 
-def config_for(scene, tile=(16, 16, 1), persistent=0, t_eps=1e-4, alpha_min=0.0, alpha_max=0.99, bg=(0, 0, 0)):
+def config_for(scene, tile=(16, 16, 1), persistent=0, t_eps=1e-4, alpha_min=0.0, alpha_max=0.99, bg=(0, 0, 0),
+               fwd_cache=1):
     return snp.RenderConfig(n_hidden=int(scene["N"]), omega0=float(scene["omega0"]),
                             color_mode=int(scene["color_mode"]), cmlp_width=int(scene.get("cmlp_width", 0)),
                             cmlp_depth=int(scene.get("cmlp_depth", 0)), tile_w=tile[0], tile_h=tile[1],
                             px_per_lane=tile[2], bwd_batch=tile[3] if len(tile) > 3 else 0, t_eps=t_eps,
-                            alpha_min=alpha_min, alpha_max=alpha_max, bg=tuple(bg), persistent=persistent)
+                            alpha_min=alpha_min, alpha_max=alpha_max, bg=tuple(bg), persistent=persistent,
+                            fwd_cache=fwd_cache)
 
 
 def options_for(cfg: snp.RenderConfig) -> RenderOptions:

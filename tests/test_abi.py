@@ -49,6 +49,14 @@ def test_layout_and_validation():
     offs = [lay.counters, lay.loss, lay.cams, lay.table, lay.records, lay.rects, lay.depth_bits, lay.tile_counts,
             lay.offsets, lay.keys, lay.values, lay.ranges, lay.gview, lay.gtable]
     assert all(o % 256 == 0 for o in offs) and max(offs) < lay.bytes
+    # the forward's pair cache: one float per (instance, tile pixel), or nothing
+    assert lay.ahat_cache_bytes == 4 * 5000 * 256 and lay.ahat_cache % 256 == 0
+    assert lay.ahat_cache + lay.ahat_cache_bytes <= lay.bytes
+    lay0 = L.SnpLayout()
+    assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=16, fwd_cache=0)), 1000, 2, cams, 5000,
+                                    C.byref(lay0)) == L.SNP_OK
+    assert lay0.ahat_cache_bytes == 0 and lay0.bytes < lay.bytes
+    assert lib.snp_workspace_layout(C.byref(_cfg(fwd_cache=2)), 10, 2, cams, 100, C.byref(lay0)) == L.SNP_ERR_INVALID
     # unsupported / invalid configurations are rejected before any device work
     assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
     assert lib.snp_workspace_layout(C.byref(_cfg(tile_w=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED

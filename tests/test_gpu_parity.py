@@ -160,27 +160,56 @@ def _grad_parity(scene, cams, targets, cfg, keys):
     assert not bad, bad
 
 
-def test_c1_gradients():
+@pytest.mark.parametrize("fwd_cache", [1, 0])
+def test_c1_gradients(fwd_cache):
     _, scene, cams, targets = S.make_workload("C1")
-    cfg = config_for(scene)
+    cfg = config_for(scene, fwd_cache=fwd_cache)
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 4), (32, 16, 2), (32, 16, 2, 4), (16, 16, 4, 16), (8, 8, 1, 32)])
-def test_gradients_multiview_tiles(tile):
+@pytest.mark.parametrize("tile,fwd_cache", [((16, 16, 1), 1), ((16, 16, 4), 1), ((32, 16, 2), 1), ((32, 16, 2, 4), 0),
+                                            ((16, 16, 4, 16), 1), ((8, 8, 1, 32), 1), ((16, 16, 2, 8), 0)])
+def test_gradients_multiview_tiles(tile, fwd_cache):
     scene = S.custom_scene(400, 8, seed=101)
     cams = S.make_cameras([(72, 56), (48, 64)], seed=102)
     targets = S.make_targets(cams, seed=103)
-    cfg = config_for(scene, tile=tile, persistent=1)
+    cfg = config_for(scene, tile=tile, persistent=1, fwd_cache=fwd_cache)
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 2), (32, 16, 2, 8)])
-def test_colour_mlp_gradients(tile):
+def test_cached_and_recomputed_backward_agree():
+    """The backward from the forward's stored integrals and the one that
+    re-evaluates them give the same gradients (up to the rounding of
+    d loss / d H), and a cache that does not fit the budget is dropped."""
+    import paper_2510_08491_amd as snp
+    scene = S.custom_scene(1500, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=131)
+    cams = S.make_cameras([(160, 120), (96, 128)], seed=132)
+    targets = S.make_targets(cams, seed=133)
+    out = {}
+    for cache in (1, 0):
+        cfg = config_for(scene, tile=(16, 16, 2), persistent=1, fwd_cache=cache)
+        fw = run_forward(scene, cams, cfg)
+        assert fw["rast"].fwd_cache == bool(cache)
+        out[cache] = (fw["images"], run_backward(fw, targets))
+    for a, b in zip(out[1][0], out[0][0]):
+        assert np.array_equal(a, b)
+    assert out[1][1][0] == out[0][1][0]
+    for k, g in out[1][1][1].items():
+        ok, err, erel = grad_close(g, out[0][1][1][k], rel=1e-5, elem_rel=1e-4)
+        say(f"  {k}: cached vs recomputed {err:.2e} / {erel:.2e}")
+        assert ok, (k, err, erel)
+    cfg = config_for(scene, tile=(16, 16, 2), fwd_cache=1)
+    cfg.fwd_cache_budget = 0
+    rast = snp.Rasterizer(cfg, scene["P"], cams)
+    assert not rast.fwd_cache and rast.layout.ahat_cache_bytes == 0
+
+
+@pytest.mark.parametrize("tile,fwd_cache", [((16, 16, 2), 1), ((32, 16, 2, 8), 1), ((16, 16, 1, 8), 0)])
+def test_colour_mlp_gradients(tile, fwd_cache):
     scene = S.custom_scene(300, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=111)
     cams = S.make_cameras([(64, 48), (48, 40), (56, 56)], seed=112)
     targets = S.make_targets(cams, seed=113)
-    cfg = config_for(scene, tile=tile)
+    cfg = config_for(scene, tile=tile, fwd_cache=fwd_cache)
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
 
 
