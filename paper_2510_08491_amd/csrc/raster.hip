@@ -47,10 +47,12 @@ __device__ __forceinline__ float wave_total(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dpp_sum_last(v)), 63));
 }
 
-// sinc(2 pi hv) * 2 pi = sin(2 pi hv) / hv, with its limit 2 pi at hv = 0
-__device__ __forceinline__ float sinc_rev(float s, float hv) {
-  return fabsf(hv) < 1e-4f ? kTwoPi : s * fast_rcp(hv);
-}
+// sinc(2 pi hv) * 2 pi = sin(2 pi hv) / hv.  The hardware sine keeps its
+// relative accuracy (about 5e-7) down to the smallest arguments, so the
+// product with 1/hv needs no small-argument branch; at hv = 0 it is 0 * inf
+// = NaN, and the minimum with the limit 2 pi (which returns the non-NaN
+// operand; sin(x)/x <= 2 pi everywhere) turns that into the limit.
+__device__ __forceinline__ float sinc_rev(float s, float hv) { return fminf(s * fast_rcp(hv), kTwoPi); }
 
 // per-thread pixel block of a tile (a wave covers 64 / TW thread rows)
 template <int TW, int TH, int PPL>
@@ -360,7 +362,9 @@ constexpr int kDppRor8 = 0x128;       // row_ror:8: lane ^ 8 within the row
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_from_partner(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  // every lane has a source lane in the patterns used here, so bound_ctrl
+  // changes nothing but lets the move fold into the consuming add
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 template <int CTRL>
@@ -610,7 +614,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
               const float sh = sin_rev(hv), ch = cos_rev(hv);
               const float rh = fast_rcp(hv);
               const float ahv = fabsf(hv);
-              const float sn = ahv < 1e-4f ? kTwoPi : sh * rh;
+              const float sn = fminf(sh * rh, kTwoPi);  // sinc, as in sinc_rev
               const float hh = kTwoPi * hv, h2 = hh * hh;
               const float series = kTwoPi * kTwoPi * hh * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
               const float general = (kTwoPi * ch - sn) * rh;
