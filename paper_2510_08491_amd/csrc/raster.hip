@@ -379,24 +379,24 @@ __device__ __forceinline__ float nb_level(float a) {
   return a + dpp_from_partner<CTRL>(a);
 }
 
-// Row sums of 8 registers: three transposed levels, then a plain one over
-// lane^8.  Row lane r ends with the row sum of v[4 b1 + 2 b0 + b2]; lanes
-// r and r^8 hold the same sum.
-__device__ __forceinline__ float reduce8(const float (&v)[8], bool sel1, bool sel2, bool sel3) {
-  const float w0 = tb_level<kDppHalfMirror>(v[0], v[1], sel1);
-  const float w1 = tb_level<kDppHalfMirror>(v[2], v[3], sel1);
-  const float w2 = tb_level<kDppHalfMirror>(v[4], v[5], sel1);
-  const float w3 = tb_level<kDppHalfMirror>(v[6], v[7], sel1);
-  const float x0 = tb_level<kDppXor1>(w0, w1, sel2);
-  const float x1 = tb_level<kDppXor1>(w2, w3, sel2);
-  return nb_level<kDppRor8>(tb_level<kDppXor2>(x0, x1, sel3));
+// Sums across the four rows of 16 lanes (v_permlane32_swap exchanges the
+// upper half of its first operand with the lower half of its second,
+// v_permlane16_swap the odd rows of the first with the even rows of the
+// second).  cross_rows_sum: every row ends with the sum of the four rows.
+__device__ __forceinline__ float cross_rows_sum(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  const float s = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // rows: x0+x2, x1+x3, x0+x2, x1+x3
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
-// Row sums of 2 registers: one transposed level, then plain levels over
-// lane^1, lane^2 and lane^8.  Row lane r ends with the row sum of a if bit 2
-// of r is clear, else of b.
-__device__ __forceinline__ float reduce2(float a, float b, bool sel1) {
-  return nb_level<kDppRor8>(nb_level<kDppXor2>(nb_level<kDppXor1>(tb_level<kDppHalfMirror>(a, b, sel1))));
+// Two registers of row partials: rows 0 and 1 end with the four-row sums
+// of a, rows 2 and 3 with those of b.
+__device__ __forceinline__ float cross_rows_pair(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  const float w = __uint_as_float(r[0]) + __uint_as_float(r[1]);  // rows: a0+a2, a1+a3, b0+b2, b1+b3
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(w), __float_as_uint(w), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
 // Length of the un-normalised camera ray R^-1 ((x+1/2-cx)/fx, (y+1/2-cy)/fy, 1).
@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
   constexpr int ACC = TS + kGViewFloats;  // per instance: table grads, then record grads
   __shared__ Stage<N, true, NB> S;
   __shared__ float s_acc[NB][ACC];
-  __shared__ uint32_t s_cnt[NB];
+  __shared__ uint32_t s_cnt[NB][NW];  // live pairs per (instance, wave)
   __shared__ uint16_t s_pix[NB][NT];
   __shared__ float s_wq[NB][NT];
   __shared__ float s_gh[NB][NT];
@@ -442,8 +442,6 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
   // selector bits and value index of the transposed row reductions
   const bool sel1 = lane & 4, sel2 = lane & 1, sel3 = lane & 2, sel4 = lane & 8;
   const int idx16 = 8 * ((lane >> 3) & 1) + 4 * ((lane >> 1) & 1) + 2 * (lane & 1) + ((lane >> 2) & 1);
-  const int idx8 = idx16 & 7;                  // value index of reduce8 (lanes with bit 3 clear write)
-  const bool lo2 = (lane & 11) == 0;           // writers of reduce2: lanes 0 and 4 of each row
   for (int idx = threadIdx.x; idx < NB * ACC; idx += NT) (&s_acc[0][0])[idx] = 0.f;
   int item = blockIdx.x;
   while (true) {
@@ -473,7 +471,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
       __syncthreads();
-      if (threadIdx.x < NB) s_cnt[threadIdx.x] = 0u;
+      if (threadIdx.x < NB * NW) (&s_cnt[0][0])[threadIdx.x] = 0u;
       stage_batch<N, true, NT, NB>(S, a, v, b0, nb);
       // ---------------- phase 1: pixels ----------------
       // One instance for this thread's pixel.  `cached`: the integral comes
@@ -538,17 +536,17 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           const int i4 = idx16 & 3;
           if (!sel3 && !sel4 && i4 < 3) atomicAdd(s_acc[j] + TS + 18 + i4, z);
         }
+        // each wave appends to its own 64 slots of the instance's list (a
+        // wave meets an instance once per batch), so no atomic is needed
         const unsigned long long lm = __ballot(live);
         if (lm) {
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(&s_cnt[j], (uint32_t)__popcll(lm));
-          base = __builtin_amdgcn_readfirstlane(base);
           if (live) {
-            const uint32_t pos = base + (uint32_t)__popcll(lm & lt_mask);
+            const uint32_t pos = wave * 64 + (uint32_t)__popcll(lm & lt_mask);
             s_pix[j][pos] = (uint16_t)threadIdx.x;
             s_wq[j][pos] = wq;
             s_gh[j][pos] = gH;
           }
+          if (lane == 0) s_cnt[j][wave] = (uint32_t)__popcll(lm);
         }
       };
       if (a.ahat_cache) {
@@ -575,14 +573,25 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
       // ---------------- phase 2: live pairs ----------------
       int it = 0;
       for (int j = 0; j < nb; ++j) {
-        const uint32_t cnt = s_cnt[j];
+        // the list is the waves' regions in order: entry e lies in region w
+        // with start[w] <= e < start[w + 1], at slot 64 w + e - start[w]
+        uint32_t start[NW + 1];
+        start[0] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) start[w + 1] = start[w] + s_cnt[j][w];
+        const uint32_t cnt = start[NW];
         for (uint32_t c0 = 0; c0 < cnt; c0 += 64, ++it) {
           if (it % NW != wave) continue;  // wave-uniform
           const uint32_t e = c0 + lane;
           const bool act = e < cnt;
-          const int pix = act ? s_pix[j][e] : 0;
-          float wq = act ? s_wq[j][e] : 0.f;
-          float gHd = act ? s_gh[j][e] : 0.f;
+          uint32_t slot = e;
+#pragma unroll
+          for (int w = 1; w < NW; ++w)
+            if (e >= start[w]) slot = 64 * w + (e - start[w]);
+          slot = act ? slot : 0;
+          const int pix = act ? s_pix[j][slot] : 0;
+          float wq = act ? s_wq[j][slot] : 0.f;
+          float gHd = act ? s_gh[j][slot] : 0.f;
           const float pxc = (float)(tx * TW + pix % TW) + 0.5f;
           const float pyc = (float)(ty * TH + pix / TW) + 0.5f;
           const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
@@ -597,9 +606,18 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
           float* acc = s_acc[j];
           float gp0 = 0.f, gp1 = 0.f, gp2 = 0.f, ge0 = 0.f, ge1 = 0.f, ge2 = 0.f;
-          // units in pairs: the pair's 10 table-gradient terms are summed over
-          // the wave right away (8 by a three-level and 2 by a one-level
-          // transposed reduction) and added to LDS with two atomics
+          // Units in groups of eight (four when N = 4), one unit pair per
+          // iteration.  A pair's eight terms (sWx, sWy, sWz, gph of both units)
+          // take three transposed row levels and its two sW2 terms one; the
+          // second pair of four units completes a 16-value row reduction
+          // (lane: term 2 b1 + b0 of unit 2 b3 + b2), and the last pair of a
+          // group finishes the sums across the rows with the row swaps, after
+          // which each LDS address receives exactly one lane's sum.  y_prev,
+          // s_prev carry the previous pair, z_prev, q_prev the previous four units.
+          constexpr int GU = N >= 8 ? 8 : 4;
+          const int tl = 2 * ((lane >> 1) & 1) + (lane & 1);         // term of this lane
+          const int ul = 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);  // unit in its group of four
+          float y_prev = 0.f, s_prev = 0.f, z_prev = 0.f, q_prev = 0.f;
 #pragma unroll 1
           for (int k0 = 0; k0 < N; k0 += 2) {
             float v8[8], v2[2];
@@ -634,11 +652,37 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
               ge1 = __builtin_fmaf(ghv, w.y, ge1);
               ge2 = __builtin_fmaf(ghv, w.z, ge2);
             }
-            // v8[i] is component i / 2 of unit k0 + i % 2: table slot 4 (k0 + i % 2) + i / 2
-            const float z8 = reduce8(v8, sel1, sel2, sel3);
-            if (!sel4) atomicAdd(acc + 4 * (k0 + (idx8 & 1)) + (idx8 >> 1), z8);
-            const float z2 = reduce2(v2[0], v2[1], sel1);
-            if (lo2) atomicAdd(acc + 4 * N + k0 + (int)sel1, z2);
+            const float x0 = tb_level<kDppXor1>(tb_level<kDppHalfMirror>(v8[0], v8[1], sel1),
+                                                tb_level<kDppHalfMirror>(v8[2], v8[3], sel1), sel2);
+            const float x1 = tb_level<kDppXor1>(tb_level<kDppHalfMirror>(v8[4], v8[5], sel1),
+                                                tb_level<kDppHalfMirror>(v8[6], v8[7], sel1), sel2);
+            const float y = tb_level<kDppXor2>(x0, x1, sel3);
+            const float s2 = tb_level<kDppHalfMirror>(v2[0], v2[1], sel1);
+            const int pi = (k0 >> 1) & (GU / 2 - 1);  // pair within the group (wave-uniform)
+            if ((pi & 1) == 0) {
+              y_prev = y;
+              s_prev = s2;
+              continue;
+            }
+            const float z = tb_level<kDppRor8>(y_prev, y, sel4);
+            const float q = tb_level<kDppXor1>(s_prev, s2, sel2);  // unit 2 b0 + b2 of the four
+            const int g = k0 & ~(GU - 1);
+            if (GU == 8 && pi == 1) {
+              z_prev = z;
+              q_prev = q;
+              continue;
+            }
+            if (GU == 8) {
+              const float zz = cross_rows_pair(z_prev, z);  // rows 0, 1: first four units; rows 2, 3: second
+              if ((lane & 16) == 0) atomicAdd(acc + 4 * (g + 4 * (lane >> 5) + ul) + tl, zz);
+              const float q8 = cross_rows_sum(nb_level<kDppRor8>(tb_level<kDppXor2>(q_prev, q, sel3)));
+              if (lane < 8) atomicAdd(acc + 4 * N + g + (idx16 & 7), q8);
+            } else {
+              const float zz = cross_rows_sum(z);
+              if (lane < 16) atomicAdd(acc + 4 * (g + ul) + tl, zz);
+              const float q4 = cross_rows_sum(nb_level<kDppRor8>(nb_level<kDppXor2>(q)));
+              if (lane < 8 && !sel3) atomicAdd(acc + 4 * N + g + (idx16 & 3), q4);
+            }
           }
           // chain p', e', H -> d', m' -> record coefficients.  The geometry is
           // recomputed from LDS here (the barrier keeps the compiler from reusing
@@ -692,15 +736,15 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
             for (int q = 0; q < 4; ++q)
               x4[q] = tb_level<kDppXor1>(tb_level<kDppHalfMirror>(R[4 * q], R[4 * q + 1], sel1),
                                          tb_level<kDppHalfMirror>(R[4 * q + 2], R[4 * q + 3], sel1), sel2);
-            const float z = tb_level<kDppRor8>(tb_level<kDppXor2>(x4[0], x4[1], sel3),
-                                               tb_level<kDppXor2>(x4[2], x4[3], sel3), sel4);
-            atomicAdd(acc + TS + idx16, z);
+            const float z = cross_rows_sum(tb_level<kDppRor8>(tb_level<kDppXor2>(x4[0], x4[1], sel3),
+                                                              tb_level<kDppXor2>(x4[2], x4[3], sel3), sel4));
+            if (lane < 16) atomicAdd(acc + TS + idx16, z);
             // coefficients 16, 17 and the b2 gradient (sum of d loss / d Q)
-            const float t4 = nb_level<kDppRor8>(nb_level<kDppXor2>(
+            const float t4 = cross_rows_sum(nb_level<kDppRor8>(nb_level<kDppXor2>(
                 tb_level<kDppXor1>(tb_level<kDppHalfMirror>(R[16], R[17], sel1),
-                                   tb_level<kDppHalfMirror>(wq, 0.f, sel1), sel2)));
+                                   tb_level<kDppHalfMirror>(wq, 0.f, sel1), sel2))));
             const int i4 = idx16 & 3;
-            if (!sel3 && !sel4 && i4 < 3) atomicAdd(i4 == 2 ? acc + 5 * N : acc + TS + 16 + i4, t4);
+            if (lane < 8 && !sel3 && i4 < 3) atomicAdd(i4 == 2 ? acc + 5 * N : acc + TS + 16 + i4, t4);
           }
         }
       }
