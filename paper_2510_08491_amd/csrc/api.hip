@@ -326,7 +326,8 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
     ca.gview = a.gview;
     ca.g_cmlp = g->cmlp;
     ca.g_xi = g->xi;
-    if (g->cmlp) SNP_HIP(launch_cmlp_bwd(cfg->cmlp_width, cfg->cmlp_depth, ca, st));
+    // also without g->cmlp: the view-direction gradient feeds the centres
+    if (g->cmlp || g->xi || g->centers) SNP_HIP(launch_cmlp_bwd(cfg->cmlp_width, cfg->cmlp_depth, ca, st));
   }
   PreBwdArgs pa;
   pa.P = P;

@@ -360,151 +360,187 @@ __global__ void __launch_bounds__(256) cmlp_fwd_kernel(CmlpArgs a) {
   }
 }
 
-// Sum over the GS lanes of a group (GS a power of two <= 64); all lanes get it.
-__device__ __forceinline__ float group_sum(float v, int GS) {
-  for (int off = 1; off < GS; off <<= 1) v += __shfl_xor(v, off);
-  return v;
-}
-
-// Backward of one hidden layer L (input activations hs[L-1], output deltas
-// in s_delta), then recursion to layer L-1.  The loop over output units is
-// a runtime loop reading the delta from LDS, so that no register array is
-// indexed dynamically.
-template <int WIDTH, int DEPTH, int Lyr>
-__device__ __forceinline__ void cmlp_bwd_hidden(const CmlpArgs& a, const float* Wp, float* gW, bool writer,
-                                                float (&hs)[DEPTH][WIDTH], float* s_delta) {
-  if constexpr (Lyr >= 1) {
-    const int off = kCmlpIn * WIDTH + WIDTH + (Lyr - 1) * (WIDTH * WIDTH + WIDTH);
-    float dprev[WIDTH];
-#pragma unroll
-    for (int k = 0; k < WIDTH; ++k) dprev[k] = 0.f;
-    for (int o = 0; o < WIDTH; ++o) {
-      const float dl = s_delta[o];
-#pragma unroll
-      for (int k = 0; k < WIDTH; ++k) {
-        const float gw = group_sum(dl * hs[Lyr - 1][k], a.GS);
-        if (writer) gW[off + o * WIDTH + k] += gw;
-        dprev[k] = __builtin_fmaf(Wp[off + o * WIDTH + k], dl, dprev[k]);
-      }
-      const float gb = group_sum(dl, a.GS);
-      if (writer) gW[off + WIDTH * WIDTH + o] += gb;
-    }
-#pragma unroll
-    for (int k = 0; k < WIDTH; ++k) s_delta[k] = hs[Lyr - 1][k] > 0.f ? dprev[k] : 0.f;
-    cmlp_bwd_hidden<WIDTH, DEPTH, Lyr - 1>(a, Wp, gW, writer, hs, s_delta);
-  }
-}
-
+// Backward of the colour MLP, one wave per primitive.  The primitive's
+// weights are staged in LDS.  Its views are taken 16 at a time; four lanes
+// serve each view (lane = 16 q + view), each computing a quarter of every
+// layer's units, so the per-view forward pass and deltas run on all 64 lanes
+// with activations exchanged through LDS.  Then every weight gradient
+// sum_v delta_v[o] a_v[i] is owned by one lane (entries lane, lane + 64, ...)
+// and summed over the views from LDS, so no cross-lane reduction or atomic
+// is needed; the sums are added to the gradient in HBM with coalesced
+// read-add-writes.  Views culled for the primitive carry zero deltas.
 template <int WIDTH, int DEPTH>
-__global__ void __launch_bounds__(256) cmlp_bwd_kernel(CmlpArgs a) {
-  __shared__ float s_delta_all[256 * (WIDTH + 1)];
-  float* s_delta = s_delta_all + threadIdx.x * (WIDTH + 1);
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // every lane of a group must reach the shuffles: no early return
-  const int64_t p = gid / a.GS;
-  const int lane_v = (int)(gid - p * a.GS);
-  const bool valid_p = p < a.P;
+__global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
   constexpr int K = CmlpShape<WIDTH, DEPTH>::K;
-  const float* Wp = a.cmlp + (valid_p ? p : 0) * K;
-  float* gW = a.g_cmlp + (valid_p ? p : 0) * K;
-  const bool writer = valid_p && lane_v == 0;
-  const int rounds = (a.V + a.GS - 1) / a.GS;
-  for (int r = 0; r < rounds; ++r) {
-    const int v = lane_v + r * a.GS;
+  constexpr int IN = kCmlpIn;
+  constexpr int VC = 16;            // views per chunk
+  constexpr int QW = WIDTH / 4;     // units per lane and layer
+  constexpr int LAST = IN * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH);  // output layer offset
+  __shared__ float sW[K];
+  __shared__ float sX[VC][IN + 1];
+  __shared__ float sH[DEPTH][VC][WIDTH + 1];  // post-ReLU activations
+  __shared__ float sD[DEPTH][VC][WIDTH + 1];  // deltas of the hidden pre-activations
+  __shared__ float sDo[VC][4];                // deltas of the output pre-activations
+  __shared__ float sGx[VC][IN + 1];           // d loss / d input
+  const int64_t p = blockIdx.x;
+  const int lane = threadIdx.x, vi = lane & (VC - 1), q = lane >> 4;
+  const float* Wg = a.cmlp + p * K;
+  for (int i = lane; i < K; i += 64) sW[i] = Wg[i];
+  float xi_acc = 0.f;  // lanes 0..7: sum over views of d loss / d xi[lane]
+  __syncthreads();
+  for (int v0 = 0; v0 < a.V; v0 += VC) {
+    const int v = v0 + vi;
     const int64_t i = (int64_t)v * a.P + p;
-    const bool act = valid_p && v < a.V && a.tile_counts[i] != 0;
-    float x[kCmlpIn], dir[3], il = 0.f;
-    float hs[DEPTH][WIDTH];  // post-ReLU activations
-    float gout[3] = {0.f, 0.f, 0.f};
+    const bool act = v < a.V && a.tile_counts[i] != 0;
+    // ---- inputs
+    if (q == 0) {
+      float x[IN], dir[3], il = 0.f;
 #pragma unroll
-    for (int k = 0; k < kCmlpIn; ++k) x[k] = 0.f;
+      for (int k = 0; k < IN; ++k) x[k] = 0.f;
+      if (act) cmlp_input(a, p, v, x, dir, &il);
 #pragma unroll
-    for (int l = 0; l < DEPTH; ++l)
-#pragma unroll
-      for (int o = 0; o < WIDTH; ++o) hs[l][o] = 0.f;
-    if (act) {
-      cmlp_input(a, p, v, x, dir, &il);
-      int off = 0;
-#pragma unroll
-      for (int o = 0; o < WIDTH; ++o) {
-        float acc = Wp[off + kCmlpIn * WIDTH + o];
-#pragma unroll
-        for (int k = 0; k < kCmlpIn; ++k) acc = __builtin_fmaf(Wp[off + o * kCmlpIn + k], x[k], acc);
-        hs[0][o] = fmaxf(acc, 0.f);
-      }
-      off += kCmlpIn * WIDTH + WIDTH;
-#pragma unroll
-      for (int l = 1; l < DEPTH; ++l) {
-#pragma unroll
-        for (int o = 0; o < WIDTH; ++o) {
-          float acc = Wp[off + WIDTH * WIDTH + o];
-#pragma unroll
-          for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], hs[l - 1][k], acc);
-          hs[l][o] = fmaxf(acc, 0.f);
-        }
-        off += WIDTH * WIDTH + WIDTH;
-      }
-      const float* gv = a.gview + i * kGViewFloats;
-#pragma unroll
-      for (int o = 0; o < 3; ++o) {
-        float acc = Wp[off + 3 * WIDTH + o];
-#pragma unroll
-        for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], hs[DEPTH - 1][k], acc);
-        const float sg = 1.0f / (1.0f + expf(-acc));
-        gout[o] = gv[18 + o] * sg * (1.0f - sg);  // d loss / d pre-sigmoid
-      }
+      for (int k = 0; k < IN; ++k) sX[vi][k] = x[k];
     }
-    // output layer: W (3 x WIDTH), b (3)
-    const int off_last = kCmlpIn * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH);
+    __syncthreads();
+    // ---- forward, a quarter of each layer per lane (the view's input row in
+    // registers, the weight rows read from LDS)
     {
-      float delta[WIDTH];
+      float xin[IN];
 #pragma unroll
-      for (int k = 0; k < WIDTH; ++k) delta[k] = 0.f;
+      for (int k = 0; k < IN; ++k) xin[k] = sX[vi][k];
+#pragma unroll 1
+      for (int t = 0; t < QW; ++t) {
+        const int o = q * QW + t;
+        float s0 = sW[IN * WIDTH + o];
 #pragma unroll
-      for (int o = 0; o < 3; ++o) {
-#pragma unroll
-        for (int k = 0; k < WIDTH; ++k) {
-          const float gw = group_sum(gout[o] * hs[DEPTH - 1][k], a.GS);
-          if (writer) gW[off_last + o * WIDTH + k] += gw;
-          delta[k] = __builtin_fmaf(Wp[off_last + o * WIDTH + k], gout[o], delta[k]);
-        }
-        const float gb = group_sum(gout[o], a.GS);
-        if (writer) gW[off_last + 3 * WIDTH + o] += gb;
+        for (int k = 0; k < IN; ++k) s0 = __builtin_fmaf(sW[o * IN + k], xin[k], s0);
+        sH[0][vi][o] = fmaxf(s0, 0.f);
       }
-#pragma unroll
-      for (int k = 0; k < WIDTH; ++k) s_delta[k] = hs[DEPTH - 1][k] > 0.f ? delta[k] : 0.f;
     }
-    // hidden layers DEPTH-1 .. 1
-    cmlp_bwd_hidden<WIDTH, DEPTH, DEPTH - 1>(a, Wp, gW, writer, hs, s_delta);
-    // first layer: W (WIDTH x 11)
-    float gx[kCmlpIn];
+    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kCmlpIn; ++k) gx[k] = 0.f;
-    for (int o = 0; o < WIDTH; ++o) {
-      const float dl = s_delta[o];
+    for (int l = 1; l < DEPTH; ++l) {
+      const int off = IN * WIDTH + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH);
+      float hin[WIDTH];
 #pragma unroll
-      for (int k = 0; k < kCmlpIn; ++k) {
-        const float gw = group_sum(dl * x[k], a.GS);
-        if (writer) gW[o * kCmlpIn + k] += gw;
-        gx[k] = __builtin_fmaf(Wp[o * kCmlpIn + k], dl, gx[k]);
+      for (int k = 0; k < WIDTH; ++k) hin[k] = sH[l - 1][vi][k];
+#pragma unroll 1
+      for (int t = 0; t < QW; ++t) {
+        const int o = q * QW + t;
+        float s0 = sW[off + WIDTH * WIDTH + o];
+#pragma unroll
+        for (int k = 0; k < WIDTH; ++k) s0 = __builtin_fmaf(sW[off + o * WIDTH + k], hin[k], s0);
+        sH[l][vi][o] = fmaxf(s0, 0.f);
       }
-      const float gb = group_sum(dl, a.GS);
-      if (writer) gW[kCmlpIn * WIDTH + o] += gb;
+      __syncthreads();
     }
-    if (act) {
+    if (q < 3) {  // output unit q: sigmoid, then d loss / d pre-sigmoid
+      float s0 = sW[LAST + 3 * WIDTH + q];
+#pragma unroll 8
+      for (int k = 0; k < WIDTH; ++k) s0 = __builtin_fmaf(sW[LAST + q * WIDTH + k], sH[DEPTH - 1][vi][k], s0);
+      const float sg = 1.0f / (1.0f + expf(-s0));
+      sDo[vi][q] = act ? a.gview[i * kGViewFloats + 18 + q] * sg * (1.0f - sg) : 0.f;
+    }
+    __syncthreads();
+    // ---- deltas, last hidden layer down to the first
+    {
+      const float d0 = sDo[vi][0], d1 = sDo[vi][1], d2 = sDo[vi][2];
+#pragma unroll 1
+      for (int t = 0; t < QW; ++t) {
+        const int k = q * QW + t;
+        float d = sW[LAST + k] * d0;
+        d = __builtin_fmaf(sW[LAST + WIDTH + k], d1, d);
+        d = __builtin_fmaf(sW[LAST + 2 * WIDTH + k], d2, d);
+        sD[DEPTH - 1][vi][k] = sH[DEPTH - 1][vi][k] > 0.f ? d : 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = DEPTH - 1; l >= 1; --l) {
+      const int off = IN * WIDTH + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH);
+      float din[WIDTH];
+#pragma unroll
+      for (int o = 0; o < WIDTH; ++o) din[o] = sD[l][vi][o];
+#pragma unroll 1
+      for (int t = 0; t < QW; ++t) {
+        const int k = q * QW + t;
+        float d = 0.f;
+#pragma unroll
+        for (int o = 0; o < WIDTH; ++o) d = __builtin_fmaf(sW[off + o * WIDTH + k], din[o], d);
+        sD[l - 1][vi][k] = sH[l - 1][vi][k] > 0.f ? d : 0.f;
+      }
+      __syncthreads();
+    }
+    // d loss / d input: inputs q, q + 4, q + 8
+    {
+      float din[WIDTH];
+#pragma unroll
+      for (int o = 0; o < WIDTH; ++o) din[o] = sD[0][vi][o];
+#pragma unroll 1
+      for (int k = q; k < IN; k += 4) {
+        float gx = 0.f;
+#pragma unroll
+        for (int o = 0; o < WIDTH; ++o) gx = __builtin_fmaf(sW[o * IN + k], din[o], gx);
+        sGx[vi][k] = gx;
+      }
+    }
+    __syncthreads();
+    if (q == 0 && act) {  // direction gradient for the chain to the centre
       float* gv = a.gview + i * kGViewFloats;
-      gv[21] = gx[0];
-      gv[22] = gx[1];
-      gv[23] = gx[2];
+      gv[21] = sGx[vi][0];
+      gv[22] = sGx[vi][1];
+      gv[23] = sGx[vi][2];
     }
-    if (a.g_xi) {
+    if (lane < kXiDim) {
 #pragma unroll
-      for (int k = 0; k < kXiDim; ++k) {
-        const float g = group_sum(act ? gx[3 + k] : 0.f, a.GS);
-        if (writer) a.g_xi[p * kXiDim + k] += g;
-      }
+      for (int w = 0; w < VC; ++w) xi_acc += sGx[w][3 + lane];
     }
+    // ---- weight gradients: entries idx = lane, lane + 64, ..., summed over
+    // the chunk's views and added to the gradient in HBM
+    float* G = a.g_cmlp ? a.g_cmlp + p * K : nullptr;
+#pragma unroll 1
+    for (int idx = lane; idx < K && G; idx += 64) {
+      float sum = 0.f;
+      if (idx < IN * WIDTH + WIDTH) {  // first layer
+        if (idx < IN * WIDTH) {
+          const int o = idx / IN, k = idx - o * IN;
+#pragma unroll
+          for (int w = 0; w < VC; ++w) sum = __builtin_fmaf(sD[0][w][o], sX[w][k], sum);
+        } else {
+          const int o = idx - IN * WIDTH;
+#pragma unroll
+          for (int w = 0; w < VC; ++w) sum += sD[0][w][o];
+        }
+      } else if (idx < LAST) {  // hidden layer l >= 1
+        const int r = idx - (IN * WIDTH + WIDTH);
+        const int l = 1 + r / (WIDTH * WIDTH + WIDTH);
+        const int rr = r - (l - 1) * (WIDTH * WIDTH + WIDTH);
+        if (rr < WIDTH * WIDTH) {
+          const int o = rr / WIDTH, k = rr - o * WIDTH;
+#pragma unroll
+          for (int w = 0; w < VC; ++w) sum = __builtin_fmaf(sD[l][w][o], sH[l - 1][w][k], sum);
+        } else {
+          const int o = rr - WIDTH * WIDTH;
+#pragma unroll
+          for (int w = 0; w < VC; ++w) sum += sD[l][w][o];
+        }
+      } else {  // output layer
+        const int rr = idx - LAST;
+        if (rr < 3 * WIDTH) {
+          const int o = rr / WIDTH, k = rr - o * WIDTH;
+#pragma unroll
+          for (int w = 0; w < VC; ++w) sum = __builtin_fmaf(sDo[w][o], sH[DEPTH - 1][w][k], sum);
+        } else {
+          const int o = rr - 3 * WIDTH;
+#pragma unroll
+          for (int w = 0; w < VC; ++w) sum += sDo[w][o];
+        }
+      }
+      G[idx] += sum;
+    }
+    __syncthreads();
   }
+  if (a.g_xi && lane < kXiDim) a.g_xi[p * kXiDim + lane] += xi_acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -711,9 +747,8 @@ hipError_t launch_cmlp_fwd(int width, int depth, CmlpArgs a, hipStream_t st) {
 }
 
 hipError_t launch_cmlp_bwd(int width, int depth, CmlpArgs a, hipStream_t st) {
-  a.GS = group_size(a.V);
-  const int64_t n = a.P * a.GS;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  if (a.P <= 0) return hipSuccess;
+  const dim3 grid((unsigned)a.P), block(64);
   SNP_CMLP_DISPATCH(cmlp_bwd_kernel, width, depth, grid, block, st, a);
   return hipGetLastError();
 }

@@ -257,6 +257,18 @@ def test_capacity_overflow_is_reported_then_grown():
     _check_images(fw, scene, cams, cfg)
 
 
+@pytest.mark.parametrize("width,depth,n_views", [(32, 2, 3), (32, 3, 18), (16, 1, 17)])
+def test_colour_mlp_gradients_widths_and_view_chunks(width, depth, n_views):
+    """Colour-MLP shapes of the workloads and view counts beyond one chunk
+    of 16 views in the colour backward."""
+    scene = S.custom_scene(200, 8, color_mode=1, cmlp_width=width, cmlp_depth=depth, seed=141 + depth)
+    sizes = [(40, 32), (32, 40), (36, 36)] * 6
+    cams = S.make_cameras(sizes[:n_views], seed=142)
+    targets = S.make_targets(cams, seed=143)
+    cfg = config_for(scene, tile=(16, 16, 1), persistent=1)
+    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
+
+
 def test_graph_replay_matches_eager():
     import paper_2510_08491_amd as snp
     scene = S.custom_scene(600, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=121)
