@@ -54,25 +54,44 @@ __device__ __forceinline__ float wave_total(float v) {
 // operand; sin(x)/x <= 2 pi everywhere) turns that into the limit.
 __device__ __forceinline__ float sinc_rev(float s, float hv) { return fminf(s * fast_rcp(hv), kTwoPi); }
 
-// per-thread pixel block of a tile (a wave covers 64 / TW thread rows)
+// Per-thread pixels of a tile.  With one pixel per thread and a tile of whole
+// 8 x 8 blocks, each wave covers one 8 x 8 block (a compact footprint, so
+// fewer waves are only partly covered by a primitive); otherwise a wave covers
+// 64 / TW thread rows of TW pixels, PPL pixel rows per thread.  loc is the
+// pixel's index in the tile (row-major), independent of the thread mapping.
 template <int TW, int TH, int PPL>
 struct PixelBlock {
-  static_assert(64 % TW == 0, "a wave must cover whole tile rows");
+  static_assert(64 % TW == 0 || (PPL == 1 && TW % 8 == 0), "a wave must cover whole tile rows or 8 x 8 blocks");
+  static constexpr bool kBlocks = PPL == 1 && TW % 8 == 0 && TH % 8 == 0;
   float pxc[PPL], pyc[PPL], L[PPL];
-  int pix[PPL];   // index into the packed image, -1 if outside
+  int pix[PPL];  // index into the packed image, -1 if outside
+  int loc[PPL];  // index in the tile
   int wx0, wx1, wy0, wy1;  // pixel block of this thread's wave
   __device__ void init(const CamDev& cam, int tx, int ty) {
-    constexpr int ROWS = (64 / TW) * PPL;  // pixel rows covered by one wave
-    wx0 = tx * TW;
-    wx1 = wx0 + TW - 1;
-    wy0 = ty * TH + (int)(threadIdx.x / 64) * ROWS;
-    wy1 = wy0 + ROWS - 1;
-    const int lx = threadIdx.x % TW;
-    const int ly0 = (threadIdx.x / TW) * PPL;
+    int lx, ly0;
+    if constexpr (kBlocks) {
+      const int w = (int)(threadIdx.x / 64), l = (int)(threadIdx.x % 64);
+      const int bx = w % (TW / 8), by = w / (TW / 8);
+      lx = bx * 8 + l % 8;
+      ly0 = by * 8 + l / 8;
+      wx0 = tx * TW + bx * 8;
+      wx1 = wx0 + 7;
+      wy0 = ty * TH + by * 8;
+      wy1 = wy0 + 7;
+    } else {
+      constexpr int ROWS = (64 / TW) * PPL;  // pixel rows covered by one wave
+      wx0 = tx * TW;
+      wx1 = wx0 + TW - 1;
+      wy0 = ty * TH + (int)(threadIdx.x / 64) * ROWS;
+      wy1 = wy0 + ROWS - 1;
+      lx = threadIdx.x % TW;
+      ly0 = (threadIdx.x / TW) * PPL;
+    }
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
       const int x = tx * TW + lx, y = ty * TH + ly0 + q;
       const bool in = x < cam.width && y < cam.height;
+      loc[q] = (ly0 + q) * TW + lx;
       pix[q] = in ? (int)(y * cam.width + x) : -1;
       pxc[q] = (float)x + 0.5f;
       pyc[q] = (float)y + 0.5f;
@@ -252,9 +271,9 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
 #pragma unroll
         for (int q = 0; q < PPL; ++q) ahat[q] = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
         if (a.ahat_cache) {  // every lane of an evaluated wave stores (misses store 0)
-          float* cp = a.ahat_cache + (int64_t)(b0 + j) * (TW * TH) + (threadIdx.x / TW) * PPL * TW + threadIdx.x % TW;
+          float* cp = a.ahat_cache + (int64_t)(b0 + j) * (TW * TH);
 #pragma unroll
-          for (int q = 0; q < PPL; ++q) cp[q * TW] = ahat[q];
+          for (int q = 0; q < PPL; ++q) cp[pb.loc[q]] = ahat[q];
         }
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
@@ -542,7 +561,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
         if (lm) {
           if (live) {
             const uint32_t pos = wave * 64 + (uint32_t)__popcll(lm & lt_mask);
-            s_pix[j][pos] = (uint16_t)threadIdx.x;
+            s_pix[j][pos] = (uint16_t)pb.loc[0];
             s_wq[j][pos] = wq;
             s_gh[j][pos] = gH;
           }
@@ -553,7 +572,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
         // the forward's integrals of this batch, fetched together (only for
         // instances whose rectangle meets this wave's pixels)
         float pre[NB];
-        const float* cp = a.ahat_cache + (int64_t)b0 * NT + threadIdx.x;
+        const float* cp = a.ahat_cache + (int64_t)b0 * NT + pb.loc[0];
         const bool wave_live = __ballot(!done) != 0;
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
