@@ -209,7 +209,8 @@ def main(argv=None):
         dom, dom_ms, dom_slots = "render_fwd", fwd_ms, fwd_slots
     achieved = dom_slots / (dom_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_SLOTS / 1e12, 3),
-                "unit": "Tslot/s", "frac": round(achieved / (PEAK_SLOTS / 1e12), 4), "traffic": None,
+                "unit": "Tslot/s", "frac": round(achieved / (PEAK_SLOTS / 1e12), 4),
+                "traffic": measured_traffic(a.workload, dom),
                 "kernel_ms": round(dom_ms, 4),
                 "fwd_frac": round(fwd_slots / (fwd_ms * 1e-3) / PEAK_SLOTS, 4),
                 "bwd_frac": round(bwd_slots / (bwd_ms * 1e-3) / PEAK_SLOTS, 4)}
@@ -251,6 +252,28 @@ def main(argv=None):
         "paper_context": "218.87 FPS forward-only full pipeline, 100k random primitives, RTX 4090 (App. A)",
     }
     print(json.dumps(out))
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary in profiles/ (scaled by a copy kernel of known size),
+    or None when there is none for this workload or the rasterizer source
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload.lower()}_render_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 2 and parts[0] in ("source_sha256", "render_bwd_bytes", "render_fwd_bytes"):
+            vals[parts[0]] = parts[1]
+    csrc = os.path.join(ROOT, "paper_2510_08491_amd", "csrc")
+    src = open(os.path.join(csrc, "raster.hip"), "rb").read() + open(os.path.join(csrc, "snp_internal.h"), "rb").read()
+    if vals.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    key = {"render_bwd": "render_bwd_bytes", "render_fwd": "render_fwd_bytes"}[kernel]
+    return float(vals[key]) if key in vals else None
 
 
 def workload_name(w, cams):

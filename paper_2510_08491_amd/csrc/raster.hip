@@ -1,8 +1,8 @@
 // Tile rasterizer of neural primitives: forward (Eq. 3-4, 7-9) and adjoint.
 //
 // A workgroup renders one tile (TW x TH pixels, PPL pixels per thread, rows
-// stacked).  It walks the tile's depth-sorted instance list in batches of
-// BATCH primitives; each batch's records (24 floats per (view, primitive))
+// stacked, or 8 x 8 blocks per wave).  It walks the tile's depth-sorted
+// instance list in batches of primitives; each batch's records (24 floats per (view, primitive))
 // and density tables (5N + 4 floats per primitive) are staged in LDS by the
 // whole workgroup and then read as broadcasts.  Per pixel and primitive:
 //
@@ -29,7 +29,10 @@
 
 namespace snp {
 
-constexpr int BATCH = 64;
+// instances per forward batch: 64, or 32 for N = 32 (whose tables would take
+// most of the LDS at 64 and cut the occupancy)
+template <int N>
+constexpr int fwd_batch() { return N >= 32 ? 32 : 64; }
 
 
 // sum over the 64 lanes; the total ends in lane 63 (other lanes hold partials)
@@ -107,7 +110,7 @@ struct PixelBlock {
 
 // LDS stage of one batch; the backward also stages the float64
 // discriminant coefficients (3 float4 = 6 doubles per instance).
-template <int N, bool BWD, int B = BATCH>
+template <int N, bool BWD, int B>
 struct Stage {
   static constexpr int NB = B;
   static constexpr int TS = 5 * N + 4;
@@ -201,7 +204,8 @@ __device__ __forceinline__ float alpha_of(float ahat, float alpha_max) {
 template <int N, int TW, int TH, int PPL, bool PERSIST, bool COUNT>
 __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH / PPL;
-  __shared__ Stage<N, false> S;
+  constexpr int FB = fwd_batch<N>();
+  __shared__ Stage<N, false, FB> S;
   __shared__ int s_item;
   unsigned long long npairs = 0, nlive = 0;
   int item = blockIdx.x;
@@ -228,8 +232,8 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
       done[q] = pb.pix[q] < 0;
     }
     const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
-    for (uint32_t b0 = start; b0 < end; b0 += BATCH) {
-      const int nb = (int)min((uint32_t)BATCH, end - b0);
+    for (uint32_t b0 = start; b0 < end; b0 += FB) {
+      const int nb = (int)min((uint32_t)FB, end - b0);
       __syncthreads();
       stage_batch<N, decltype(S)::DQ4 != 0, NT, decltype(S)::NB>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
