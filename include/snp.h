@@ -90,7 +90,12 @@ typedef struct {
  *             tile_h floats in the workspace, and the backward reads it back
  *             instead of evaluating the density MLP again; a backward must
  *             then follow a forward of the same step on the same workspace.
- *             0 = the backward re-evaluates every pair (no extra memory). */
+ *             0 = the backward re-evaluates every pair (no extra memory).
+ *  fwd_cache_instances  with fwd_cache = 1: how many leading tile instances
+ *             (in sorted order) have their pairs kept, 0 = all of them
+ *             (the workspace capacity); batches of the backward that reach
+ *             past them re-evaluate.  Lets the cache use whatever memory is
+ *             free when the whole of it does not fit. */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -102,6 +107,7 @@ typedef struct {
   int32_t persistent;
   int32_t bwd_batch;
   int32_t fwd_cache;
+  int64_t fwd_cache_instances;
 } snp_config;
 
 typedef struct {
@@ -142,7 +148,7 @@ typedef struct {
   int32_t table_stride;   /* floats per table row */
   int32_t total_tiles;    /* tiles over all views */
   size_t ahat_cache;      /* fwd_cache = 1: float per (instance, tile pixel), else unused */
-  size_t ahat_cache_bytes; /* 0 when fwd_cache = 0 */
+  size_t ahat_cache_bytes; /* 0 when fwd_cache = 0; cached instances x tile pixels x 4 */
 } snp_layout;
 
 /* Size and layout of the workspace for P primitives seen by V cameras with

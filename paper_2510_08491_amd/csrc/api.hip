@@ -37,6 +37,7 @@ static snp_status check_cfg(const snp_config* cfg) {
   if (cfg->bwd_batch != 0 && !bwd_batch_supported(cfg->tile_w, cfg->tile_h, cfg->bwd_batch))
     return SNP_ERR_UNSUPPORTED;
   if (cfg->fwd_cache != 0 && cfg->fwd_cache != 1) return SNP_ERR_INVALID;
+  if (cfg->fwd_cache_instances < 0) return SNP_ERR_INVALID;
   return SNP_OK;
 }
 
@@ -111,7 +112,8 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   L.gview = take(sizeof(float) * (size_t)VP * kGViewFloats);
   L.gtable = take(sizeof(float) * (size_t)P * TS);
   if (cfg->fwd_cache) {
-    L.ahat_cache_bytes = sizeof(float) * (size_t)cap * (size_t)(cfg->tile_w * cfg->tile_h);
+    const int64_t n = cfg->fwd_cache_instances > 0 && cfg->fwd_cache_instances < cap ? cfg->fwd_cache_instances : cap;
+    L.ahat_cache_bytes = sizeof(float) * (size_t)n * (size_t)(cfg->tile_w * cfg->tile_h);
     L.ahat_cache = take(L.ahat_cache_bytes);
   }
   L.bytes = off;
@@ -254,6 +256,7 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   a.gtable = wsp<float>(ws, L.gtable);
   a.disc_coef = wsp<double>(ws, L.disc_coef);
   a.ahat_cache = cfg->fwd_cache ? wsp<float>(ws, L.ahat_cache) : nullptr;
+  a.cache_instances = cfg->fwd_cache ? (int64_t)(L.ahat_cache_bytes / (sizeof(float) * cfg->tile_w * cfg->tile_h)) : 0;
   a.counters = wsp<unsigned long long>(ws, L.counters);
   a.t_eps = cfg->t_eps;
   a.alpha_min = cfg->alpha_min;

@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
         float ahat[PPL];
 #pragma unroll
         for (int q = 0; q < PPL; ++q) ahat[q] = 2.f * pb.L[q] * g[q].H * (Q[q] + b2);
-        if (a.ahat_cache) {  // every lane of an evaluated wave stores (misses store 0)
+        if (a.ahat_cache && (int64_t)(b0 + j) < a.cache_instances) {  // every lane of an evaluated wave stores (misses store 0)
           float* cp = a.ahat_cache + (int64_t)(b0 + j) * (TW * TH);
 #pragma unroll
           for (int q = 0; q < PPL; ++q) cp[pb.loc[q]] = ahat[q];
@@ -572,7 +572,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           if (lane == 0) s_cnt[j][wave] = (uint32_t)__popcll(lm);
         }
       };
-      if (a.ahat_cache) {
+      if (a.ahat_cache && (int64_t)(b0 + nb) <= a.cache_instances) {
         // the forward's integrals of this batch, fetched together (only for
         // instances whose rectangle meets this wave's pixels)
         float pre[NB];

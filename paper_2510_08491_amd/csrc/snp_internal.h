@@ -182,6 +182,7 @@ struct RasterArgs {
   float* gview;
   float* gtable;
   const double* disc_coef;  // backward: float64 discriminant near silhouettes
+  int64_t cache_instances;  // leading instances covered by ahat_cache
   float* ahat_cache;        // per (instance, tile pixel) integral: the forward writes it,
                             // the backward reads it (null: the backward re-evaluates)
   unsigned long long* counters;

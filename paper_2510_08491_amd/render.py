@@ -35,8 +35,9 @@ class RenderConfig:
     persistent: int = 0
     bwd_batch: int = 0
     # 1: the forward keeps every evaluated pair's integral for the backward
-    # (capacity x tile pixels floats) when it fits the memory budget below;
-    # 0: the backward re-evaluates the density MLP
+    # (tile pixels floats per instance) for as many leading instances as the
+    # memory budget below holds, the backward re-evaluates the rest;
+    # 0: the backward re-evaluates every pair
     fwd_cache: int = 1
     # device bytes the pair cache may take; None: 85% of the free memory
     # left after the rest of the workspace
@@ -112,8 +113,9 @@ class Rasterizer:
         self._alloc(capacity if capacity is not None else max(1 << 16, 8 * self.P))
 
     # -- workspace ---------------------------------------------------------------
-    def _layout(self, capacity: int, fwd_cache: int) -> L.SnpLayout:
+    def _layout(self, capacity: int, fwd_cache: int, cache_instances: int = 0) -> L.SnpLayout:
         self.ccfg.fwd_cache = int(fwd_cache)
+        self.ccfg.fwd_cache_instances = int(cache_instances)
         lay = L.SnpLayout()
         L.check(L.lib().snp_workspace_layout(C.byref(self.ccfg), self.P, self.V, self.ccams, int(capacity),
                                              C.byref(lay)), "snp_workspace_layout")
@@ -125,10 +127,14 @@ class Rasterizer:
         if lay.ahat_cache_bytes:
             budget = self.cfg.fwd_cache_budget
             if budget is None:
+                torch.cuda.empty_cache()  # the previous workspace is still held by the allocator's cache
                 free, _ = torch.cuda.mem_get_info(torch.device(self.device))
                 budget = int(0.85 * (free - (lay.bytes - lay.ahat_cache_bytes)))
-            if lay.ahat_cache_bytes > budget:  # does not fit: the backward re-evaluates
-                lay = self._layout(capacity, 0)
+            if lay.ahat_cache_bytes > budget:
+                # cache the leading instances that fit; the backward re-evaluates the rest
+                per_instance = lay.ahat_cache_bytes // int(capacity)
+                n = max(0, budget) // per_instance
+                lay = self._layout(capacity, 1, n) if n >= max(1, int(capacity) // 50) else self._layout(capacity, 0)
         self.layout = lay
         self.ws = torch.empty(lay.bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.ws.data_ptr()) % 256
@@ -141,8 +147,15 @@ class Rasterizer:
 
     @property
     def fwd_cache(self) -> bool:
-        """True when the forward keeps the pair integrals for the backward."""
+        """True when the forward keeps pair integrals for the backward."""
         return bool(self.ccfg.fwd_cache)
+
+    @property
+    def cached_instances(self) -> int:
+        """How many leading tile instances have their pair integrals kept."""
+        if not self.ccfg.fwd_cache:
+            return 0
+        return int(self.layout.ahat_cache_bytes // (4 * self.cfg.tile_w * self.cfg.tile_h))
 
     def _view(self, field: str, dtype, count: int) -> torch.Tensor:
         start = self._ws_off + getattr(self.layout, field)

@@ -57,6 +57,13 @@ def test_layout_and_validation():
                                     C.byref(lay0)) == L.SNP_OK
     assert lay0.ahat_cache_bytes == 0 and lay0.bytes < lay.bytes
     assert lib.snp_workspace_layout(C.byref(_cfg(fwd_cache=2)), 10, 2, cams, 100, C.byref(lay0)) == L.SNP_ERR_INVALID
+    # only the leading instances cached
+    c = _cfg(n_hidden=16)
+    c.fwd_cache_instances = 1200
+    assert lib.snp_workspace_layout(C.byref(c), 1000, 2, cams, 5000, C.byref(lay0)) == L.SNP_OK
+    assert lay0.ahat_cache_bytes == 4 * 1200 * 256 and lay0.bytes < lay.bytes
+    c.fwd_cache_instances = -1
+    assert lib.snp_workspace_layout(C.byref(c), 1000, 2, cams, 5000, C.byref(lay0)) == L.SNP_ERR_INVALID
     # unsupported / invalid configurations are rejected before any device work
     assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
     assert lib.snp_workspace_layout(C.byref(_cfg(tile_w=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED

@@ -178,26 +178,38 @@ def test_gradients_multiview_tiles(tile, fwd_cache):
 
 
 def test_cached_and_recomputed_backward_agree():
-    """The backward from the forward's stored integrals and the one that
-    re-evaluates them give the same gradients (up to the rounding of
-    d loss / d H), and a cache that does not fit the budget is dropped."""
+    """The backward from the forward's stored integrals, the one that
+    re-evaluates them, and one with only the leading instances cached give
+    the same gradients (up to the rounding of d loss / d H); a cache budget
+    of nothing drops the cache."""
     import paper_2510_08491_amd as snp
     scene = S.custom_scene(1500, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=131)
     cams = S.make_cameras([(160, 120), (96, 128)], seed=132)
     targets = S.make_targets(cams, seed=133)
     out = {}
-    for cache in (1, 0):
-        cfg = config_for(scene, tile=(16, 16, 2), persistent=1, fwd_cache=cache)
+    n_inst = None
+    for mode in ("full", "none", "part"):
+        cfg = config_for(scene, tile=(16, 16, 2), persistent=1, fwd_cache=0 if mode == "none" else 1)
+        if mode == "part":  # the leading ~40% of the instances only
+            cfg.fwd_cache_budget = int(0.4 * n_inst) * 4 * 16 * 16
         fw = run_forward(scene, cams, cfg)
-        assert fw["rast"].fwd_cache == bool(cache)
-        out[cache] = (fw["images"], run_backward(fw, targets))
-    for a, b in zip(out[1][0], out[0][0]):
-        assert np.array_equal(a, b)
-    assert out[1][1][0] == out[0][1][0]
-    for k, g in out[1][1][1].items():
-        ok, err, erel = grad_close(g, out[0][1][1][k], rel=1e-5, elem_rel=1e-4)
-        say(f"  {k}: cached vs recomputed {err:.2e} / {erel:.2e}")
-        assert ok, (k, err, erel)
+        rast = fw["rast"]
+        if mode == "full":
+            n_inst = fw["instances"]
+            assert rast.cached_instances == rast.capacity
+        elif mode == "none":
+            assert not rast.fwd_cache and rast.cached_instances == 0
+        else:
+            assert 0 < rast.cached_instances < fw["instances"], (rast.cached_instances, fw["instances"])
+        out[mode] = (fw["images"], run_backward(fw, targets))
+    for mode in ("none", "part"):
+        for a, b in zip(out["full"][0], out[mode][0]):
+            assert np.array_equal(a, b)
+        assert out["full"][1][0] == out[mode][1][0]
+        for k, g in out["full"][1][1].items():
+            ok, err, erel = grad_close(g, out[mode][1][1][k], rel=1e-5, elem_rel=1e-4)
+            say(f"  {k}: cached vs {mode} {err:.2e} / {erel:.2e}")
+            assert ok, (mode, k, err, erel)
     cfg = config_for(scene, tile=(16, 16, 2), fwd_cache=1)
     cfg.fwd_cache_budget = 0
     rast = snp.Rasterizer(cfg, scene["P"], cams)
