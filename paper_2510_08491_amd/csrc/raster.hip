@@ -123,23 +123,28 @@ struct Stage {
   uint32_t id[B];
 };
 
+// Stages one batch: instance ids and rectangles, records, tables (and the
+// discriminant coefficients), gathered by primitive id as float4.  The
+// threads that gather read the id from global memory themselves, so one
+// barrier (at the end) suffices.  The caller's previous barrier (the end of
+// the previous batch, or the work-queue fetch) guarantees nobody still
+// reads the stage.
 template <int N, bool BWD, int NT, int B>
 __device__ __forceinline__ void stage_batch(Stage<N, BWD, B>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
+  const int64_t vbase = (int64_t)v * a.P;
   for (int t = threadIdx.x; t < nb; t += NT) {
     const uint32_t p = a.values[b0 + t];
     S.id[t] = p;
-    S.rect[t] = reinterpret_cast<const int4*>(a.rects)[(int64_t)v * a.P + p];
+    S.rect[t] = reinterpret_cast<const int4*>(a.rects)[vbase + p];
   }
-  __syncthreads();
   const float4* rec4 = reinterpret_cast<const float4*>(a.records);
   const float4* tab4 = reinterpret_cast<const float4*>(a.table);
   const float4* dq4 = reinterpret_cast<const float4*>(a.disc_coef);
   constexpr int F = Stage<N, BWD, B>::F;
   constexpr int T4 = Stage<N, BWD, B>::TS / 4;
-  const int64_t vbase = (int64_t)v * a.P;
   for (int idx = threadIdx.x; idx < nb * F; idx += NT) {
     const int j = idx / F, c = idx - j * F;
-    const uint32_t p = S.id[j];
+    const uint32_t p = a.values[b0 + j];
     if (c < 6)
       S.rec[j][c] = rec4[(vbase + p) * 6 + c];
     else if (c < 6 + T4)
@@ -234,7 +239,6 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
     const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
     for (uint32_t b0 = start; b0 < end; b0 += FB) {
       const int nb = (int)min((uint32_t)FB, end - b0);
-      __syncthreads();
       stage_batch<N, decltype(S)::DQ4 != 0, NT, decltype(S)::NB>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
         const int4 rc = S.rect[j];
@@ -493,7 +497,6 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
     const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
-      __syncthreads();
       if (threadIdx.x < NB * NW) (&s_cnt[0][0])[threadIdx.x] = 0u;
       stage_batch<N, true, NT, NB>(S, a, v, b0, nb);
       // ---------------- phase 1: pixels ----------------
