@@ -2,11 +2,23 @@
 
 Test infrastructure only (see the package docstring).
 
-The paper's novel-view-synthesis colour is spherical harmonics (Sec. 3.1);
-its relighting application uses a per-primitive colour network (App. D.2,
+The paper's novel-view-synthesis colour is spherical harmonics of four
+bands, as in 3DGS (Sec. 3.1 and Sec. 4, implementation details); its
+relighting application uses a per-primitive colour network (App. D.2,
 Eq. 14) whose inputs include the view direction relative to the primitive.
-The workloads here use either a constant RGB per primitive or such a
-per-primitive colour MLP, evaluated once per (primitive, view):
+The workloads here use a constant RGB per primitive, degree-3 spherical
+harmonics, or such a per-primitive colour MLP, evaluated once per
+(primitive, view).
+
+Spherical harmonics: with d = normalize(x_B - o_v) and the 16 real
+orthonormal harmonics Y_k(d) of degrees 0..3 (order (l, m) = (0,0),
+(1,-1), (1,0), (1,1), (2,-2), ..., (3,3); real forms sqrt(2) (-1)^m Re/Im of
+the complex harmonics, which cancels the Condon-Shortley phase),
+
+    colour_c = max(0, 1/2 + sum_k Y_k(d) sh[k, c])
+
+(the offset of one half and the clamp at zero are the 3DGS convention the
+paper says it follows).  Colour MLP:
 
     input  = [normalize(x_B - o_v) (3), xi_p (8)]
     hidden = ReLU(W h + b), `depth` layers of `width` units
@@ -47,13 +59,49 @@ def mlp_forward(x, layers):
     return 1.0 / (1.0 + np.exp(-h))
 
 
+def sh_basis(d):
+    """The 16 real spherical harmonics of degrees 0..3 at unit vectors d
+    (..., 3), as polynomials in (x, y, z) -> (..., 16)."""
+    d = np.asarray(d, dtype=np.float64)
+    x, y, z = d[..., 0], d[..., 1], d[..., 2]
+    pi = np.pi
+    one = np.ones_like(x)
+    return np.stack([
+        0.5 * np.sqrt(1 / pi) * one,
+        np.sqrt(3 / (4 * pi)) * y,
+        np.sqrt(3 / (4 * pi)) * z,
+        np.sqrt(3 / (4 * pi)) * x,
+        0.5 * np.sqrt(15 / pi) * x * y,
+        0.5 * np.sqrt(15 / pi) * y * z,
+        0.25 * np.sqrt(5 / pi) * (3 * z * z - 1),
+        0.5 * np.sqrt(15 / pi) * x * z,
+        0.25 * np.sqrt(15 / pi) * (x * x - y * y),
+        0.25 * np.sqrt(35 / (2 * pi)) * y * (3 * x * x - y * y),
+        0.5 * np.sqrt(105 / pi) * x * y * z,
+        0.25 * np.sqrt(21 / (2 * pi)) * y * (5 * z * z - 1),
+        0.25 * np.sqrt(7 / pi) * (5 * z ** 3 - 3 * z),
+        0.25 * np.sqrt(21 / (2 * pi)) * x * (5 * z * z - 1),
+        0.25 * np.sqrt(105 / pi) * z * (x * x - y * y),
+        0.25 * np.sqrt(35 / (2 * pi)) * x * (x * x - 3 * y * y),
+    ], axis=-1)
+
+
+def view_directions(scene, cam):
+    """normalize(x_B - o_v) for every primitive, (P, 3)."""
+    o = camera_center(cam)
+    dirv = np.asarray(scene["centers"], dtype=np.float64) - o
+    return dirv / np.linalg.norm(dirv, axis=1, keepdims=True)
+
+
 def primitive_colors(scene, cam):
     """Colour (P, 3) of every primitive as seen from camera `cam`."""
     if scene["color_mode"] == 0:
         return np.asarray(scene["colors"], dtype=np.float64)
-    o = camera_center(cam)
-    dirv = np.asarray(scene["centers"], dtype=np.float64) - o
-    dirv /= np.linalg.norm(dirv, axis=1, keepdims=True)
+    dirv = view_directions(scene, cam)
+    if scene["color_mode"] == 2:
+        Y = sh_basis(dirv)                                        # (P, 16)
+        sh = np.asarray(scene["sh"], dtype=np.float64)            # (P, 16, 3)
+        return np.maximum(0.0, 0.5 + np.einsum("pk,pkc->pc", Y, sh))
     x = np.concatenate([dirv, np.asarray(scene["xi"], dtype=np.float64)], axis=1)
     layers = unpack_cmlp(scene["cmlp"], scene["cmlp_width"], scene["cmlp_depth"], x.shape[1])
     return mlp_forward(x, layers)

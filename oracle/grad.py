@@ -25,7 +25,7 @@ import torch
 from .keys import project_all
 from .render import RenderOptions, depth_order, l1_loss, render_views
 
-PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi")
+PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh")
 
 
 def _rotmat_t(q):
@@ -38,11 +38,30 @@ def _rotmat_t(q):
     ], -2)
 
 
+def _sh_basis_t(d):
+    """Real spherical harmonics of degrees 0..3 (the 16 of oracle.color.sh_basis),
+    written again for autograd."""
+    x, y, z = d.unbind(-1)
+    pi = np.pi
+    c0 = 0.5 * np.sqrt(1 / pi)
+    c1 = np.sqrt(3 / (4 * pi))
+    c2a, c2b, c2c = 0.5 * np.sqrt(15 / pi), 0.25 * np.sqrt(5 / pi), 0.25 * np.sqrt(15 / pi)
+    c3a, c3b = 0.25 * np.sqrt(35 / (2 * pi)), 0.5 * np.sqrt(105 / pi)
+    c3c, c3d, c3e = 0.25 * np.sqrt(21 / (2 * pi)), 0.25 * np.sqrt(7 / pi), 0.25 * np.sqrt(105 / pi)
+    return torch.stack([
+        torch.full_like(x, c0), c1 * y, c1 * z, c1 * x,
+        c2a * x * y, c2a * y * z, c2b * (3 * z * z - 1), c2a * x * z, c2c * (x * x - y * y),
+        c3a * y * (3 * x * x - y * y), c3b * x * y * z, c3c * y * (5 * z * z - 1), c3d * (5 * z ** 3 - 3 * z),
+        c3c * x * (5 * z * z - 1), c3e * z * (x * x - y * y), c3a * x * (x * x - 3 * y * y)], -1)
+
+
 def _colors_t(params, meta, o):
     if meta["color_mode"] == 0:
         return params["colors"]
     dirv = params["centers"] - o
     dirv = dirv / torch.linalg.norm(dirv, dim=1, keepdim=True)
+    if meta["color_mode"] == 2:
+        return torch.relu(0.5 + torch.einsum("pk,pkc->pc", _sh_basis_t(dirv), params["sh"]))
     h = torch.cat([dirv, params["xi"]], 1)
     vec = params["cmlp"]
     width, depth = meta["cmlp_width"], meta["cmlp_depth"]

@@ -62,7 +62,7 @@ class SceneConfig:
     n_prims: int
     n_hidden: int                   # N, width of the density MLP
     cams: List[tuple]               # list of (width, height)
-    color_mode: int                 # 0 constant RGB, 1 colour MLP
+    color_mode: int                 # 0 constant RGB, 1 colour MLP, 2 spherical harmonics (degree 3)
     cmlp_width: int = 0
     cmlp_depth: int = 0             # number of hidden layers
     omega0: float = 10.0
@@ -81,6 +81,10 @@ CONFIGS = {
                       1, 32, 2),
     "C5": SceneConfig("C5", 1_000_000, 32, [(1600, 900)] * 32, 1, 32, 3,
                       center_dist="normal06", scale_lo=0.005, scale_hi=0.1),
+    # stand-in for the paper's throughput protocol (App. A): 100k random
+    # primitives in a volume, N = 8, omega0 = 30, degree-3 SH colour, square
+    # 800x800 views around the volume; forward only
+    "A": SceneConfig("A", 100_000, 8, [(800, 800)] * 8, 2, omega0=30.0, backward=False),
 }
 
 
@@ -146,9 +150,13 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
     b1 = rng.uniform(-math.pi, math.pi, (P, N))
     w2 = rng.uniform(0.0, 1.0 / 8.0, (P, N))
     b2 = np.zeros(P)
-    colors = cmlp = xi = None
+    colors = cmlp = xi = sh = None
     if cfg.color_mode == 0:
         colors = rng.uniform(0.0, 1.0, (P, 3))
+    elif cfg.color_mode == 2:
+        # 16 coefficients per channel: a constant term that keeps the colour
+        # mostly inside (0, 1) and a smaller view-dependent part
+        sh = np.concatenate([rng.uniform(-1.5, 1.5, (P, 1, 3)), rng.uniform(-0.3, 0.3, (P, 15, 3))], axis=1)
     else:
         layers = []
         n_in = 3 + XI_DIM
@@ -165,14 +173,14 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
                 cmlp_width=cfg.cmlp_width, cmlp_depth=cfg.cmlp_depth,
                 centers=f32(centers), scales=f32(scales), quats=f32(quats),
                 w1=f32(w1), b1=f32(b1), w2=f32(w2), b2=f32(b2),
-                colors=f32(colors), cmlp=f32(cmlp), xi=f32(xi))
+                colors=f32(colors), cmlp=f32(cmlp), xi=f32(xi), sh=f32(sh))
 
 
 def subset_scene(scene: dict, idx) -> dict:
     """Primitives `idx` of a scene (e.g. the first 1000)."""
     out = dict(scene)
-    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi"):
-        if scene[k] is not None:
+    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh"):
+        if scene.get(k) is not None:
             out[k] = np.ascontiguousarray(scene[k][idx])
     out["P"] = int(out["centers"].shape[0])
     return out
