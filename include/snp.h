@@ -70,7 +70,10 @@ typedef struct {
  *  color_mode 0 = constant RGB per primitive; 1 = per-(primitive, view)
  *             colour MLP: input [normalize(x_B - o_v), xi_p], cmlp_depth
  *             ReLU layers of cmlp_width units, sigmoid RGB output; weights
- *             per primitive layer after layer, each W (out x in) then b.
+ *             per primitive layer after layer, each W (out x in) then b;
+ *             2 = spherical harmonics of degree 3 (Sec. 3.1, four bands as
+ *             in 3DGS): colour = max(0, 1/2 + sum_k Y_k(d) sh[k]) with the
+ *             16 real orthonormal harmonics at d = normalize(x_B - o_v).
  *  tile_w, tile_h, px_per_lane: rasterizer tile shape and pixels per thread;
  *             supported shapes are listed by snp_supported_tiles().
  *  z_near     a primitive is culled for a view unless its whole ellipsoid
@@ -116,13 +119,14 @@ typedef struct {
   const float *colors; /* color_mode 0, else NULL */
   const float *cmlp;   /* color_mode 1, else NULL */
   const float *xi;     /* color_mode 1, else NULL */
+  const float *sh;     /* color_mode 2: P x 16 x 3 (basis (l, m) in order (0,0), (1,-1), (1,0), (1,1), (2,-2) ... (3,3); channel), else NULL */
 } snp_prims;
 
 /* Gradient outputs, same shapes as the parameters.  The backward ADDS into
  * them (the caller zeroes them first); NULL skips a tensor (gradients of xi
  * are only produced when non-NULL). */
 typedef struct {
-  float *centers, *scales, *quats, *w1, *b1, *w2, *b2, *colors, *cmlp, *xi;
+  float *centers, *scales, *quats, *w1, *b1, *w2, *b2, *colors, *cmlp, *xi, *sh;
 } snp_grads;
 
 /* Byte offsets of the internal arrays inside a workspace (for inspection by

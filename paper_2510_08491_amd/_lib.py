@@ -28,12 +28,13 @@ class SnpConfig(C.Structure):
 
 class SnpPrims(C.Structure):
     _fields_ = [("P", C.c_int64)] + [(k, C.c_void_p) for k in
-                                     ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi")]
+                                     ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi",
+                                      "sh")]
 
 
 class SnpGrads(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in
-                ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi")]
+                ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh")]
 
 
 class SnpLayout(C.Structure):

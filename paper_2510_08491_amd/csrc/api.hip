@@ -27,7 +27,7 @@ static snp_status check_cfg(const snp_config* cfg) {
   if (!cfg) return SNP_ERR_INVALID;
   if (!valid_n(cfg->n_hidden)) return SNP_ERR_UNSUPPORTED;
   if (!(cfg->omega0 > 0.f) || !std::isfinite(cfg->omega0)) return SNP_ERR_INVALID;
-  if (cfg->color_mode != 0 && cfg->color_mode != 1) return SNP_ERR_INVALID;
+  if (cfg->color_mode < 0 || cfg->color_mode > 2) return SNP_ERR_INVALID;
   if (cfg->color_mode == 1 && !cmlp_supported(cfg->cmlp_width, cfg->cmlp_depth)) return SNP_ERR_UNSUPPORTED;
   if (!tile_supported(cfg->tile_w, cfg->tile_h, cfg->px_per_lane)) return SNP_ERR_UNSUPPORTED;
   if (!(cfg->z_near > 0.f)) return SNP_ERR_INVALID;
@@ -134,6 +134,7 @@ static snp_status check_prims(const snp_config* cfg, const snp_prims* pr) {
   if (!pr->centers || !pr->scales || !pr->quats || !pr->w1 || !pr->b1 || !pr->w2 || !pr->b2) return SNP_ERR_INVALID;
   if (cfg->color_mode == 0 && !pr->colors) return SNP_ERR_INVALID;
   if (cfg->color_mode == 1 && (!pr->cmlp || !pr->xi)) return SNP_ERR_INVALID;
+  if (cfg->color_mode == 2 && !pr->sh) return SNP_ERR_INVALID;
   return SNP_OK;
 }
 
@@ -196,6 +197,18 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
     ca.tile_counts = va.tile_counts;
     ca.records = va.records;
     SNP_HIP(launch_cmlp_fwd(cfg->cmlp_width, cfg->cmlp_depth, ca, st));
+  }
+  if (cfg->color_mode == 2) {
+    ShArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.P = pr->P;
+    sa.V = V;
+    sa.centers = pr->centers;
+    sa.sh = pr->sh;
+    sa.cams = cd;
+    sa.tile_counts = va.tile_counts;
+    sa.records = va.records;
+    SNP_HIP(launch_sh_fwd(sa, st));
   }
   return SNP_OK;
 }
@@ -332,6 +345,21 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
     // also without g->cmlp: the view-direction gradient feeds the centres
     if (g->cmlp || g->xi || g->centers) SNP_HIP(launch_cmlp_bwd(cfg->cmlp_width, cfg->cmlp_depth, ca, st));
   }
+  if (cfg->color_mode == 2 && (g->sh || g->centers)) {
+    // also without g->sh: the view-direction gradient feeds the centres
+    ShArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.P = P;
+    sa.V = V;
+    sa.centers = pr->centers;
+    sa.sh = pr->sh;
+    sa.cams = a.cams;
+    sa.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
+    sa.records = wsp<float>(ws, L.records);
+    sa.gview = a.gview;
+    sa.g_sh = g->sh;
+    SNP_HIP(launch_sh_bwd(sa, st));
+  }
   PreBwdArgs pa;
   pa.P = P;
   pa.V = V;
@@ -366,6 +394,7 @@ static snp_status zero_grads(const snp_config* cfg, int64_t P, const snp_grads* 
     SNP_HIP(zero_f32(g->cmlp, (int64_t)cmlp_param_count(cfg->cmlp_width, cfg->cmlp_depth) * P, st));
     SNP_HIP(zero_f32(g->xi, (int64_t)kXiDim * P, st));
   }
+  if (cfg->color_mode == 2) SNP_HIP(zero_f32(g->sh, (int64_t)kShCoeffs * P, st));
   return SNP_OK;
 }
 

@@ -17,6 +17,7 @@ constexpr int kGViewFloats = 24;       // per-(view, primitive) gradient record
 constexpr int kMaxCamsPerChunk = 16;   // cameras passed by value per launch
 constexpr int kXiDim = 8;
 constexpr int kCmlpIn = 3 + kXiDim;
+constexpr int kShCoeffs = 48;     // spherical harmonics of degree 3: 16 basis functions x RGB
 
 // Per-view constants on the device.
 struct CamDev {
@@ -139,6 +140,17 @@ struct CmlpArgs {
   float* g_xi;
 };
 
+struct ShArgs {
+  int64_t P;
+  int32_t V;
+  const float *centers, *sh;
+  const CamDev* cams;
+  const uint32_t* tile_counts;
+  float* records;
+  float* gview;
+  float* g_sh;
+};
+
 struct PreBwdArgs {
   int64_t P;
   int32_t V, N, color_mode;
@@ -197,6 +209,9 @@ hipError_t launch_prim_table(int N, int64_t P, float omega0, const snp_prims& pr
 hipError_t launch_preprocess_views(const ViewArgs& a, hipStream_t st);
 hipError_t launch_cmlp_fwd(int width, int depth, CmlpArgs a, hipStream_t st);
 hipError_t launch_cmlp_bwd(int width, int depth, CmlpArgs a, hipStream_t st);
+// sh.hip
+hipError_t launch_sh_fwd(const ShArgs& a, hipStream_t st);
+hipError_t launch_sh_bwd(const ShArgs& a, hipStream_t st);
 bool cmlp_supported(int width, int depth);
 int cmlp_param_count(int width, int depth);
 hipError_t launch_preprocess_bwd(const PreBwdArgs& a, hipStream_t st);

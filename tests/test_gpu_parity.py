@@ -281,6 +281,19 @@ def test_colour_mlp_gradients_widths_and_view_chunks(width, depth, n_views):
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
 
 
+@pytest.mark.parametrize("fwd_cache", [1, 0])
+def test_sh_colour_image_and_gradients(fwd_cache):
+    """Degree-3 spherical-harmonics colour (the paper's novel-view colour):
+    images and every gradient, SH coefficients included."""
+    scene = S.custom_scene(300, 8, omega0=30.0, color_mode=2, seed=151)
+    cams = S.make_cameras([(64, 48), (48, 56), (40, 40)], seed=152)
+    targets = S.make_targets(cams, seed=153)
+    cfg = config_for(scene, tile=(16, 16, 1), persistent=1, fwd_cache=fwd_cache)
+    fw = run_forward(scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "sh"])
+
+
 def test_graph_replay_matches_eager():
     import paper_2510_08491_amd as snp
     scene = S.custom_scene(600, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=121)
