@@ -62,7 +62,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "A"],
+                    help="C3/C4/C5: fwd+bwd step; A: forward-only frames/s of the 100k-primitive throughput workload")
     ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,bwd_batch] (default: tuned)")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -81,6 +82,8 @@ def main(argv=None):
     import synthetic as S
 
     torch.cuda.set_device(0)
+    if a.workload == "A":
+        return forward_fps(a)
     cfg0, scene, cams, targets = S.make_workload(a.workload)
     N = scene["N"]
     if a.tile:
@@ -250,6 +253,89 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": "218.87 FPS forward-only full pipeline, 100k random primitives, RTX 4090 (App. A)",
+    }
+    print(json.dumps(out))
+
+
+def forward_fps(a):
+    """Forward-only throughput on the stand-in for the paper's App. A protocol
+    (100k random primitives in a volume, N = 8, omega0 = 30, degree-3 SH
+    colour, 800x800 views): every frame runs the whole forward pipeline for
+    one view (preprocess, binning, sort, render), frames one after another
+    over the views; reports frames/s (and hit pairs/s)."""
+    import torch
+    import paper_2510_08491_amd as snp
+    import synthetic as S
+    _, scene, cams, _ = S.make_workload("A")
+    tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else (16, 16, 1)
+    cfg = snp.RenderConfig(n_hidden=scene["N"], omega0=scene["omega0"], color_mode=scene["color_mode"],
+                           tile_w=tile[0], tile_h=tile[1], px_per_lane=tile[2], persistent=1, fwd_cache=0)
+    params = snp.params_to_device(scene)
+    rasts, outs, pairs = [], [], 0
+    for c in cams:
+        r = snp.Rasterizer(cfg, scene["P"], [c])
+        r._alloc(int(r.prepare(params) * 1.1) + 4096)
+        r.prepare(params)
+        img, T = r.new_images()
+        r.forward(params, img, T, count_pairs=True)
+        pairs += r.counters()["hit_pairs"]
+        rasts.append(r)
+        outs.append((img, T))
+    log(f"[bench] workload A: P={scene['P']} views={len(cams)} {cams[0].width}x{cams[0].height} "
+        f"N={scene['N']} tile={tile}, hit pairs per frame {pairs / len(cams):.4g}")
+
+    def frame(i):
+        r = rasts[i % len(rasts)]
+        r.prepare(params)
+        r.forward(params, *outs[i % len(rasts)])
+
+    for i in range(max(a.warmup, 1) * len(rasts)):
+        frame(i)
+    torch.cuda.synchronize()
+    n = max(a.steps, 1) * len(rasts)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(n):
+        frame(i)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    fps = 1e3 / ms
+    log(f"[bench] one view per pipeline: {ms:.3f} ms/frame, {fps:.1f} frames/s")
+    # the same frames with all views in one batched pipeline (persistent launches over every view's tiles)
+    rb = snp.Rasterizer(cfg, scene["P"], cams)
+    rb._alloc(int(rb.prepare(params) * 1.1) + 4096)
+    img_b, T_b = rb.new_images()
+    for _ in range(max(a.warmup, 1)):
+        rb.prepare(params)
+        rb.forward(params, img_b, T_b)
+    torch.cuda.synchronize()
+    nb = max(a.steps, 1)
+    e0.record()
+    for _ in range(nb):
+        rb.prepare(params)
+        rb.forward(params, img_b, T_b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / (nb * len(cams))
+    same = all(torch.equal(outs[v][0], img_b[3 * sum(c.width * c.height for c in cams[:v]):
+                                               3 * sum(c.width * c.height for c in cams[:v + 1])])
+               for v in range(len(cams)))
+    log(f"[bench] all views in one pipeline: {ms_b:.3f} ms/frame, {1e3 / ms_b:.1f} frames/s, images identical: {same}")
+    out = {
+        "metric": "forward frames/s, full pipeline (preprocess, bin, sort, render) per view",
+        "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded primitives, random-pose cameras)",
+        "config": {"workload": f"{scene['P']} random primitives in [-1,1]^3, N={scene['N']}, omega0={scene['omega0']}, "
+                               f"degree-3 SH colour, {len(cams)} views of {cams[0].width}x{cams[0].height}, forward only",
+                   "tile": list(tile)},
+        "hit_pairs_per_frame": pairs / len(cams),
+        "pairs_per_s": pairs / len(cams) / (ms * 1e-3),
+        "batched_frames_per_s": 1e3 / ms_b,
+        "batched_images_identical": same,
+        "paper_context": "218.87 FPS, 100k random primitives, synthetic-NeRF cameras, RTX 4090 (App. A); "
+                         "primitive sizes and cameras there are not given, so not comparable one to one",
     }
     print(json.dumps(out))
 
