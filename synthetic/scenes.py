@@ -21,8 +21,14 @@ uniform on S^3 (normalised Gaussian, stored un-normalised), W1 ~ U(-1/3,1/3),
 b1 ~ U(-pi,pi), W2 ~ U(0,1/8), b2 = 0, omega0 = 10.  Colour-MLP weights and
 biases ~ U(+-1/sqrt(fan_in)), xi ~ N(0,1).
 
-Seeds: scene seed 0 (draw order: centres, scales, quats, W1, b1, W2, colours or
-colour-MLP weights, xi), camera seed 1, target seed 2.
+  A   8 cameras 800x800, 100k primitives, N=8, omega0=30, degree-3 SH colour
+  G   A's scene as Gaussians (standard deviations a third of A's scales)
+
+Opacity (Gaussians only) ~ U(0.2, 0.9).
+
+Seeds: scene seed 0 (draw order: centres, scales, quats, W1, b1, W2, colours,
+SH coefficients or colour-MLP weights, xi, opacity), camera seed 1, target
+seed 2.
 """
 from __future__ import annotations
 
@@ -70,6 +76,7 @@ class SceneConfig:
     scale_lo: float = 0.02
     scale_hi: float = 0.2
     backward: bool = True
+    primitive: int = 0              # 0 neural primitive, 1 Gaussian (scales are standard deviations)
 
 
 CONFIGS = {
@@ -85,6 +92,11 @@ CONFIGS = {
     # primitives in a volume, N = 8, omega0 = 30, degree-3 SH colour, square
     # 800x800 views around the volume; forward only
     "A": SceneConfig("A", 100_000, 8, [(800, 800)] * 8, 2, omega0=30.0, backward=False),
+    # the same scene as Gaussians (the paper's 3DGS comparison): the same
+    # uniform draws with a third of the scales, so that the 3-sigma ellipsoid
+    # of each Gaussian is the bound of the neural primitive it replaces
+    "G": SceneConfig("G", 100_000, 8, [(800, 800)] * 8, 2, omega0=30.0, backward=False,
+                     scale_lo=0.02 / 3.0, scale_hi=0.2 / 3.0, primitive=1),
 }
 
 
@@ -168,8 +180,12 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
         cmlp = np.concatenate(layers, axis=1)
         assert cmlp.shape[1] == cmlp_param_count(cfg.cmlp_width, cfg.cmlp_depth)
         xi = rng.standard_normal((P, XI_DIM))
+    # opacity (used by Gaussians) is drawn last so the other arrays do not
+    # depend on it
+    opacity = rng.uniform(0.2, 0.9, P)
     f32 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
-    return dict(P=P, N=N, omega0=cfg.omega0, color_mode=cfg.color_mode,
+    return dict(P=P, N=N, omega0=cfg.omega0, color_mode=cfg.color_mode, primitive=cfg.primitive,
+                opacity=f32(opacity),
                 cmlp_width=cfg.cmlp_width, cmlp_depth=cfg.cmlp_depth,
                 centers=f32(centers), scales=f32(scales), quats=f32(quats),
                 w1=f32(w1), b1=f32(b1), w2=f32(w2), b2=f32(b2),
@@ -179,7 +195,7 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
 def subset_scene(scene: dict, idx) -> dict:
     """Primitives `idx` of a scene (e.g. the first 1000)."""
     out = dict(scene)
-    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh"):
+    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity"):
         if scene.get(k) is not None:
             out[k] = np.ascontiguousarray(scene[k][idx])
     out["P"] = int(out["centers"].shape[0])
@@ -202,8 +218,8 @@ def make_workload(name: str, n_prims: Optional[int] = None, sizes=None):
 
 
 def custom_scene(P, N, omega0=10.0, color_mode=0, cmlp_width=0, cmlp_depth=0,
-                 seed=SCENE_SEED, center_dist="uniform", scale_lo=0.02, scale_hi=0.2):
+                 seed=SCENE_SEED, center_dist="uniform", scale_lo=0.02, scale_hi=0.2, primitive=0):
     """A scene with the C1-C5 distributions but free sizes."""
     cfg = SceneConfig("custom", P, N, [], color_mode, cmlp_width, cmlp_depth, omega0,
-                      center_dist, scale_lo, scale_hi)
+                      center_dist, scale_lo, scale_hi, primitive=primitive)
     return make_scene(cfg, seed=seed)
