@@ -31,9 +31,11 @@ that the HIP path can follow them bit for bit on the key path):
     image; rows alike.  The primitive contributes only inside this
     rectangle, so the image does not depend on the tile shape.
   * Per pixel: d = pixel centre - (u, v); power = -(a' dx^2 + c' dy^2)/2 -
-    b' dx dy with conic (a', b', c'); no contribution if power > 0;
-    alpha = min(alpha_max, o exp(power)); skipped below alpha_min (3DGS uses
-    1/255).  Blending and early termination are the framework's (a pixel
+    b' dx dy with conic (a', b', c'); alpha = min(alpha_max, o exp(min(power,
+    0))); skipped below alpha_min (3DGS uses 1/255).  A kept Gaussian's conic
+    is positive definite (det > 0, a' > 0), so power <= 0 exactly; the clamp
+    only keeps a rounding error near the centre from lifting alpha above o
+    (3DGS drops such a pixel instead, which rounding could then decide).  Blending and early termination are the framework's (a pixel
     stops after the primitive that takes T below t_eps).
   * A hit pair is a (pixel, primitive) pair with the pixel inside the
     primitive's rectangle and not yet terminated.
@@ -177,13 +179,13 @@ def project_gaussians(scene, cam, tile_w=16, tile_h=16, z_near=0.2):
 
 def gaussian_alpha(proj, p, cols, rows, opacity, alpha_max):
     """power and alpha of Gaussian p at pixels (cols, rows) (centres at
-    +0.5).  Returns (power, alpha); alpha is 0 where power > 0."""
+    +0.5).  Returns (power, alpha)."""
     u, v = proj["mean2d"][p]
     ia, ib, ic = proj["conic"][p]
     dx = (np.asarray(cols, dtype=np.float64) + 0.5) - u
     dy = (np.asarray(rows, dtype=np.float64) + 0.5) - v
     power = -0.5 * (ia * dx * dx + ic * dy * dy) - ib * dx * dy
-    alpha = np.where(power > 0.0, 0.0, np.minimum(alpha_max, float(opacity) * np.exp(np.minimum(power, 0.0))))
+    alpha = np.minimum(alpha_max, float(opacity) * np.exp(np.minimum(power, 0.0)))
     return power, alpha
 
 
@@ -207,10 +209,10 @@ def render_view_gaussian(scene, cam, opts: RenderOptions = RenderOptions(), proj
     for p in depth_order(proj):
         x0, x1, y0, y1 = proj["rect"][p]
         rows, cols = np.mgrid[y0:y1 + 1, x0:x1 + 1]
-        power, alpha = gaussian_alpha(proj, p, cols, rows, opac[p], opts.alpha_max)
+        _, alpha = gaussian_alpha(proj, p, cols, rows, opac[p], opts.alpha_max)
         live = ~done[y0:y1 + 1, x0:x1 + 1]
         hit_pairs += int(live.sum())
-        use = live & (power <= 0.0)
+        use = live.copy()
         if opts.alpha_min > 0:
             use &= alpha >= opts.alpha_min
         a = np.where(use, alpha, 0.0)
@@ -243,9 +245,7 @@ def render_pixels_gaussian(scene, cam, cols, rows, opts: RenderOptions = RenderO
         T = 1.0
         for p in sel:
             out_h[n] += 1
-            power, alpha = gaussian_alpha(proj, p, np.array([i]), np.array([j]), opac[p], opts.alpha_max)
-            if power[0] > 0.0:
-                continue
+            _, alpha = gaussian_alpha(proj, p, np.array([i]), np.array([j]), opac[p], opts.alpha_max)
             a = float(alpha[0])
             if opts.alpha_min > 0 and a < opts.alpha_min:
                 continue
