@@ -30,6 +30,11 @@
  *    scales P x 3 (semi-axis lengths, > 0), quats P x 4 (w, x, y, z; need not
  *    be normalised), w1 P x N x 3, b1 P x N, w2 P x N, b2 P, and either
  *    colors P x 3 (color_mode 0) or cmlp P x K with xi P x 8 (color_mode 1).
+ *  - A second primitive kind (snp_config.primitive = 1) renders 3D Gaussians
+ *    through the same tiling, sorting and blending, as the 3DGS splatting
+ *    kernel the paper measures against (App. A, integration-cost table):
+ *    scales are then standard deviations, opacity P floats, and w1..b2 are
+ *    not read.  It has a forward pass only.
  */
 #ifndef SNP_H_
 #define SNP_H_
@@ -98,7 +103,17 @@ typedef struct {
  *             (in sorted order) have their pairs kept, 0 = all of them
  *             (the workspace capacity); batches of the backward that reach
  *             past them re-evaluate.  Lets the cache use whatever memory is
- *             free when the whole of it does not fit. */
+ *             free when the whole of it does not fit.
+ *  primitive  0 = neural primitives (everything above); 1 = 3D Gaussians
+ *             splatted as in 3DGS (EWA): covariance R diag(s^2) R^T pushed
+ *             through the Jacobian of the projection at the centre (x/z and
+ *             y/z clamped to 1.3 times the view), plus 0.3 px^2 on the
+ *             diagonal; kept iff the centre is in front of z_near; screen
+ *             bound the square of radius ceil(3 sqrt(lambda_max)) around the
+ *             projected centre; per pixel inside it alpha = min(alpha_max,
+ *             opacity exp(-d^T Sigma2d^-1 d / 2)).  n_hidden, omega0 and
+ *             fwd_cache are ignored; forward only (the backward, snp_step
+ *             and snp_graph_create return SNP_ERR_UNSUPPORTED). */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -111,6 +126,7 @@ typedef struct {
   int32_t bwd_batch;
   int32_t fwd_cache;
   int64_t fwd_cache_instances;
+  int32_t primitive;
 } snp_config;
 
 typedef struct {
@@ -120,6 +136,7 @@ typedef struct {
   const float *cmlp;   /* color_mode 1, else NULL */
   const float *xi;     /* color_mode 1, else NULL */
   const float *sh;     /* color_mode 2: P x 16 x 3 (basis (l, m) in order (0,0), (1,-1), (1,0), (1,1), (2,-2) ... (3,3); channel), else NULL */
+  const float *opacity; /* primitive 1: P opacities in (0, 1], used as given; else NULL */
 } snp_prims;
 
 /* Gradient outputs, same shapes as the parameters.  The backward ADDS into

@@ -23,10 +23,15 @@ struct Plan {
 
 static bool valid_n(int n) { return n == 4 || n == 8 || n == 16 || n == 32; }
 
+static bool gaussian(const snp_config* cfg) { return cfg->primitive == 1; }
+
 static snp_status check_cfg(const snp_config* cfg) {
   if (!cfg) return SNP_ERR_INVALID;
-  if (!valid_n(cfg->n_hidden)) return SNP_ERR_UNSUPPORTED;
-  if (!(cfg->omega0 > 0.f) || !std::isfinite(cfg->omega0)) return SNP_ERR_INVALID;
+  if (cfg->primitive != 0 && cfg->primitive != 1) return SNP_ERR_INVALID;
+  if (!gaussian(cfg)) {
+    if (!valid_n(cfg->n_hidden)) return SNP_ERR_UNSUPPORTED;
+    if (!(cfg->omega0 > 0.f) || !std::isfinite(cfg->omega0)) return SNP_ERR_INVALID;
+  }
   if (cfg->color_mode < 0 || cfg->color_mode > 2) return SNP_ERR_INVALID;
   if (cfg->color_mode == 1 && !cmlp_supported(cfg->cmlp_width, cfg->cmlp_depth)) return SNP_ERR_UNSUPPORTED;
   if (!tile_supported(cfg->tile_w, cfg->tile_h, cfg->px_per_lane)) return SNP_ERR_UNSUPPORTED;
@@ -80,8 +85,10 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   int tb = 1;
   while (((int64_t)1 << tb) < tiles) ++tb;
   pl->key_bits = 31 + tb;
-  const int N = cfg->n_hidden;
-  const int TS = table_stride(N);
+  // Gaussians have no density table, float64 discriminants, backward arrays
+  // or pair cache
+  const bool gs = gaussian(cfg);
+  const int TS = gs ? 0 : table_stride(cfg->n_hidden);
   const int64_t VP = (int64_t)V * P;
   snp_layout& L = pl->L;
   std::memset(&L, 0, sizeof(L));
@@ -97,7 +104,7 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   L.cams = take(sizeof(CamDev) * (size_t)V);
   L.table = take(sizeof(float) * (size_t)P * TS);
   L.records = take(sizeof(float) * (size_t)VP * kRecFloats);
-  L.disc_coef = take(sizeof(double) * 6 * (size_t)VP);
+  L.disc_coef = take(gs ? 0 : sizeof(double) * 6 * (size_t)VP);
   L.rects = take(sizeof(int32_t) * 4 * (size_t)VP);
   L.depth_bits = take(sizeof(uint32_t) * (size_t)VP);
   L.tile_counts = take(sizeof(uint32_t) * (size_t)VP);
@@ -109,9 +116,9 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   pl->values_alt = take(sizeof(uint32_t) * (size_t)cap);
   pl->sort_scratch = take(sort_scratch_bytes(cap));
   L.ranges = take(sizeof(uint32_t) * 2 * (size_t)tiles);
-  L.gview = take(sizeof(float) * (size_t)VP * kGViewFloats);
+  L.gview = take(gs ? 0 : sizeof(float) * (size_t)VP * kGViewFloats);
   L.gtable = take(sizeof(float) * (size_t)P * TS);
-  if (cfg->fwd_cache) {
+  if (cfg->fwd_cache && !gs) {
     const int64_t n = cfg->fwd_cache_instances > 0 && cfg->fwd_cache_instances < cap ? cfg->fwd_cache_instances : cap;
     L.ahat_cache_bytes = sizeof(float) * (size_t)n * (size_t)(cfg->tile_w * cfg->tile_h);
     L.ahat_cache = take(L.ahat_cache_bytes);
@@ -131,7 +138,8 @@ static snp_status check_ws(const Plan& pl, void* ws, size_t ws_bytes) {
 
 static snp_status check_prims(const snp_config* cfg, const snp_prims* pr) {
   if (!pr || pr->P <= 0) return SNP_ERR_INVALID;
-  if (!pr->centers || !pr->scales || !pr->quats || !pr->w1 || !pr->b1 || !pr->w2 || !pr->b2) return SNP_ERR_INVALID;
+  if (!pr->centers || !pr->scales || !pr->quats) return SNP_ERR_INVALID;
+  if (gaussian(cfg) ? !pr->opacity : (!pr->w1 || !pr->b1 || !pr->w2 || !pr->b2)) return SNP_ERR_INVALID;
   if (cfg->color_mode == 0 && !pr->colors) return SNP_ERR_INVALID;
   if (cfg->color_mode == 1 && (!pr->cmlp || !pr->xi)) return SNP_ERR_INVALID;
   if (cfg->color_mode == 2 && !pr->sh) return SNP_ERR_INVALID;
@@ -168,12 +176,15 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
     }
     SNP_HIP(launch_setup_cams(ch, cd, st));
   }
-  SNP_HIP(launch_prim_table(cfg->n_hidden, pr->P, cfg->omega0, *pr, wsp<float>(ws, L.table), counters, st));
+  if (!gaussian(cfg))
+    SNP_HIP(launch_prim_table(cfg->n_hidden, pr->P, cfg->omega0, *pr, wsp<float>(ws, L.table), counters, st));
   ViewArgs va;
   va.P = pr->P;
   va.V = V;
   va.z_near = cfg->z_near;
   va.color_mode = cfg->color_mode;
+  va.primitive = cfg->primitive;
+  va.opacity = pr->opacity;
   va.centers = pr->centers;
   va.scales = pr->scales;
   va.quats = pr->quats;
@@ -308,8 +319,12 @@ static snp_status do_forward(const snp_config* cfg, int64_t P, int32_t V, const 
   a.final_T = final_T;
   if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_FWD, st));
   timer_mark(0, st);
-  SNP_HIP(launch_render_fwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0,
-                            count != 0, a, st));
+  if (gaussian(cfg))
+    SNP_HIP(launch_render_fwd_gauss(cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0, count != 0, a,
+                                    st));
+  else
+    SNP_HIP(launch_render_fwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0,
+                              count != 0, a, st));
   timer_mark(1, st);
   return SNP_OK;
 }
@@ -502,6 +517,7 @@ snp_status snp_render_backward(const snp_config* cfg, const snp_prims* prims, in
                                void* ws, const snp_layout* layout, const float* images, const float* dL_dimages,
                                const snp_grads* grads, hipStream_t stream) {
   if (!cfg || !prims || !images || !dL_dimages || !grads) return SNP_ERR_INVALID;
+  if (gaussian(cfg)) return SNP_ERR_UNSUPPORTED;
   Plan pl;
   SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
   SNP_TRY(check_prims(cfg, prims));
@@ -526,6 +542,7 @@ static snp_status check_step_args(const snp_config* cfg, const snp_prims* prims,
                                   const snp_grads* grads) {
   if (!cfg || !prims || !images || !final_T || !targets || !loss_out || !dL || !grads || !(n_norm > 0.0))
     return SNP_ERR_INVALID;
+  if (gaussian(cfg)) return SNP_ERR_UNSUPPORTED;
   return check_prims(cfg, prims);
 }
 

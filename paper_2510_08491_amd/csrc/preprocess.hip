@@ -166,12 +166,120 @@ __device__ __forceinline__ void outline_extent(double Ma, double Mb, double M22,
   *hi = h;
 }
 
+// ---------------------------------------------------------------------------
+// Gaussian splats (the 3DGS kernel the paper compares against, App. A):
+// key path and record of one (view, primitive) pair.  Steps in one fixed
+// float64 order (contraction off):
+//   Sigma = Rc diag(s^2) Rc^T in camera space, mu = C x_B + t;
+//   kept iff mu_z > z_near and det > 0 below;
+//   J = [[fx/z, 0, -fx xc/z^2], [0, fy/z, -fy yc/z^2]] with x/z, y/z clamped
+//   to 1.3 times the view for xc, yc;
+//   (a, b; b, c) = J Sigma J^T + 0.3 I, computed as (J Sigma) J^T;
+//   r = ceil(3 sqrt(mid + sqrt(max(0.1, mid^2 - det)))), mid = (a + c)/2;
+//   pixel columns [ceil(u - r - 1/2), floor(u + r - 1/2)], u = fx x/z + cx.
+// ---------------------------------------------------------------------------
+constexpr double kLowPass = 0.3;     // px^2 on the diagonal of the 2D covariance
+constexpr double kViewClamp = 1.3;   // Jacobian evaluated within 1.3x the view
+constexpr double kEigFloor = 0.1;    // floor of the eigenvalue discriminant
+
+__device__ void gaussian_view(const ViewArgs& a, int64_t i, int64_t p, const CamDev& cam) {
+  double Rp[3][3];
+  quat_rot_f64(a.quats + 4 * p, Rp, nullptr, nullptr);
+  const double xb[3] = {a.centers[3 * p], a.centers[3 * p + 1], a.centers[3 * p + 2]};
+  const double ss[3] = {(double)a.scales[3 * p] * a.scales[3 * p], (double)a.scales[3 * p + 1] * a.scales[3 * p + 1],
+                        (double)a.scales[3 * p + 2] * a.scales[3 * p + 2]};
+  double C[3][3], t[3];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) C[r][c] = cam.R[3 * r + c];
+    t[r] = cam.t[r];
+  }
+  double Rc[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Rc[r][c] = (C[r][0] * Rp[0][c] + C[r][1] * Rp[1][c]) + C[r][2] * Rp[2][c];
+  double mu[3];
+  for (int r = 0; r < 3; ++r) mu[r] = ((C[r][0] * xb[0] + C[r][1] * xb[1]) + C[r][2] * xb[2]) + t[r];
+  double S[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      S[r][c] = ((Rc[r][0] * ss[0]) * Rc[c][0] + (Rc[r][1] * ss[1]) * Rc[c][1]) + (Rc[r][2] * ss[2]) * Rc[c][2];
+  const double mz = mu[2];
+  const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+  const double xzr = mu[0] / mz, yzr = mu[1] / mz;
+  const double lxl = -kViewClamp * (cx / fx), lxh = kViewClamp * (((double)cam.width - cx) / fx);
+  const double lyl = -kViewClamp * (cy / fy), lyh = kViewClamp * (((double)cam.height - cy) / fy);
+  const double xc = fmin(fmax(xzr, lxl), lxh) * mz;
+  const double yc = fmin(fmax(yzr, lyl), lyh) * mz;
+  const double zz2 = mz * mz;
+  const double j00 = fx / mz, j02 = -(fx * xc) / zz2;
+  const double j11 = fy / mz, j12 = -(fy * yc) / zz2;
+  double T0[3], T1[3];
+  for (int k = 0; k < 3; ++k) {
+    T0[k] = j00 * S[0][k] + j02 * S[2][k];
+    T1[k] = j11 * S[1][k] + j12 * S[2][k];
+  }
+  const double ca = (T0[0] * j00 + T0[2] * j02) + kLowPass;
+  const double cb = T0[1] * j11 + T0[2] * j12;
+  const double cc = (T1[1] * j11 + T1[2] * j12) + kLowPass;
+  const double det = ca * cc - cb * cb;
+  const bool keep = mz > (double)a.z_near && det > 0.0;
+
+  uint32_t count = 0;
+  int32_t rect[4] = {0, 0, 0, 0};
+  uint32_t dbits = 0;
+  if (keep) {
+    const double mid = 0.5 * (ca + cc);
+    const double lam = mid + sqrt(fmax(kEigFloor, mid * mid - det));
+    const double r = ceil(3.0 * sqrt(lam));
+    const double u = fx * xzr + cx, v = fy * yzr + cy;
+    double x0 = ceil((u - r) - 0.5), x1 = floor((u + r) - 0.5);
+    double y0 = ceil((v - r) - 0.5), y1 = floor((v + r) - 0.5);
+    x0 = x0 > 0.0 ? x0 : 0.0;
+    x1 = x1 < (double)cam.width - 1.0 ? x1 : (double)cam.width - 1.0;
+    y0 = y0 > 0.0 ? y0 : 0.0;
+    y1 = y1 < (double)cam.height - 1.0 ? y1 : (double)cam.height - 1.0;
+    if (x0 <= x1 && y0 <= y1) {
+      rect[0] = (int32_t)x0;
+      rect[1] = (int32_t)x1;
+      rect[2] = (int32_t)y0;
+      rect[3] = (int32_t)y1;
+      const int tx0 = rect[0] / cam.tile_w, tx1 = rect[1] / cam.tile_w;
+      const int ty0 = rect[2] / cam.tile_h, ty1 = rect[3] / cam.tile_h;
+      count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+      dbits = __float_as_uint((float)mz);
+      // conic (the inverse covariance) scaled to log2 of the Gaussian factor
+      const double L2 = 1.4426950408889634074;
+      const double ka = -0.5 * L2 * (cc / det), kb = L2 * (cb / det), kc = -0.5 * L2 * (ca / det);
+      float* rec = a.records + i * kRecFloats;
+      float4* r4 = reinterpret_cast<float4*>(rec);
+      const float cr = a.color_mode == 0 ? a.colors[3 * p] : 0.f;
+      const float cg = a.color_mode == 0 ? a.colors[3 * p + 1] : 0.f;
+      const float cbl = a.color_mode == 0 ? a.colors[3 * p + 2] : 0.f;
+      r4[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      r4[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      r4[2] = make_float4((float)u, (float)v, (float)ka, cr);
+      r4[3] = make_float4((float)kb, (float)kc, a.opacity[p], cg);
+      r4[4] = make_float4(0.f, 0.f, 0.f, cbl);
+      r4[5] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  a.rects[4 * i + 0] = rect[0];
+  a.rects[4 * i + 1] = rect[1];
+  a.rects[4 * i + 2] = rect[2];
+  a.rects[4 * i + 3] = rect[3];
+  a.depth_bits[i] = dbits;
+  a.tile_counts[i] = count;
+}
+
 __global__ void __launch_bounds__(256) preprocess_views_kernel(ViewArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.P * a.V) return;
   const int v = (int)(i / a.P);
   const int64_t p = i - (int64_t)v * a.P;
   const CamDev& cam = a.cams[v];
+  if (a.primitive == 1) {
+    gaussian_view(a, i, p, cam);
+    return;
+  }
 
   double Rp[3][3];
   quat_rot_f64(a.quats + 4 * p, Rp, nullptr, nullptr);

@@ -331,6 +331,121 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// forward of Gaussian splats (the 3DGS kernel of the paper's comparison,
+// App. A): per pixel inside the primitive's rectangle,
+//   alpha = min(alpha_max, opacity 2^(ka dx^2 + kb dx dy + kc dy^2)),
+// blended like the neural primitives.  A batch is one instance per thread
+// (up to the workgroup size), staged as two float4, the blue channel and
+// the rectangle.
+// ---------------------------------------------------------------------------
+template <int NT>
+struct GaussStage {
+  float4 g0[NT];  // u, v, ka, red
+  float4 g1[NT];  // kb, kc, opacity, green
+  float cb[NT];   // blue
+  int4 rect[NT];
+};
+
+template <int TW, int TH, int PPL, bool PERSIST, bool COUNT>
+__global__ void __launch_bounds__(TW * TH / PPL) render_fwd_gauss_kernel(RasterArgs a) {
+  constexpr int NT = TW * TH / PPL;
+  __shared__ GaussStage<NT> S;
+  __shared__ int s_item;
+  unsigned long long npairs = 0, nlive = 0;
+  int item = blockIdx.x;
+  while (true) {
+    if (PERSIST) {
+      if (threadIdx.x == 0) s_item = (int)atomicAdd(&a.counters[CNT_QUEUE_FWD], 1ull);
+      __syncthreads();
+      item = s_item;
+      __syncthreads();
+    }
+    if (item >= a.total_tiles) break;
+    const int v = view_of_tile(a.cams, a.V, item);
+    const CamDev& cam = a.cams[v];
+    const int local = item - cam.tile_base;
+    const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
+    PixelBlock<TW, TH, PPL> pb;
+    pb.init(cam, tx, ty);
+    int px[PPL], py[PPL];
+    float T[PPL], C0[PPL], C1[PPL], C2[PPL];
+    bool done[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      px[q] = (int)pb.pxc[q];
+      py[q] = (int)pb.pyc[q];
+      T[q] = 1.f;
+      C0[q] = C1[q] = C2[q] = 0.f;
+      done[q] = pb.pix[q] < 0;
+    }
+    const int64_t vbase = (int64_t)v * a.P;
+    const float4* rec4 = reinterpret_cast<const float4*>(a.records);
+    const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
+    for (uint32_t b0 = start; b0 < end; b0 += NT) {
+      const int nb = (int)min((uint32_t)NT, end - b0);
+      if ((int)threadIdx.x < nb) {
+        const int64_t r = vbase + a.values[b0 + threadIdx.x];
+        S.rect[threadIdx.x] = reinterpret_cast<const int4*>(a.rects)[r];
+        S.g0[threadIdx.x] = rec4[r * 6 + 2];
+        S.g1[threadIdx.x] = rec4[r * 6 + 3];
+        S.cb[threadIdx.x] = a.records[r * kRecFloats + 19];
+      }
+      __syncthreads();
+      for (int j = 0; j < nb; ++j) {
+        const int4 rc = S.rect[j];
+        if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
+        const float4 g0 = S.g0[j], g1 = S.g1[j];
+        const float blue = S.cb[j];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          const bool hit = !done[q] && px[q] >= rc.x && px[q] <= rc.y && py[q] >= rc.z && py[q] <= rc.w;
+          if (COUNT) npairs += hit ? 1 : 0;
+          const float dx = pb.pxc[q] - g0.x, dy = pb.pyc[q] - g0.y;
+          // log2 of the Gaussian factor; <= 0 for the positive definite conic
+          const float pw = fminf(__builtin_fmaf(dx, __builtin_fmaf(g1.x, dy, g0.z * dx), g1.y * dy * dy), 0.f);
+          const float al = fminf(g1.z * exp2_fast(pw), a.alpha_max);
+          if (hit && !(a.alpha_min > 0.f && al < a.alpha_min)) {
+            if (COUNT) nlive += 1;
+            const float w = al * T[q];
+            C0[q] = __builtin_fmaf(g0.w, w, C0[q]);
+            C1[q] = __builtin_fmaf(g1.w, w, C1[q]);
+            C2[q] = __builtin_fmaf(blue, w, C2[q]);
+            T[q] = T[q] * (1.f - al);
+            if (T[q] < a.t_eps) done[q] = true;
+          }
+        }
+      }
+      bool mine = true;
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) mine = mine && done[q];
+      if (__syncthreads_and(mine)) break;
+    }
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      if (pb.pix[q] >= 0) {
+        const int64_t pxi = cam.pix_base + pb.pix[q];
+        a.images[3 * pxi + 0] = C0[q] + T[q] * a.bg0;
+        a.images[3 * pxi + 1] = C1[q] + T[q] * a.bg1;
+        a.images[3 * pxi + 2] = C2[q] + T[q] * a.bg2;
+        a.final_T[pxi] = T[q];
+      }
+    }
+    if (!PERSIST) break;
+  }
+  if (COUNT) {
+    unsigned long long tot = npairs, live = nlive;
+    for (int o = 1; o < 64; o <<= 1) {
+      tot += __shfl_xor(tot, o);
+      live += __shfl_xor(live, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&a.counters[CNT_HIT_PAIRS], tot);
+      atomicAdd(&a.counters[CNT_LIVE_PAIRS], live);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
 // sum over each row of 16 lanes; every lane of the row ends with its row's sum
@@ -863,6 +978,28 @@ static hipError_t fwd_shape(const RasterArgs& a, bool persist, bool count, hipSt
   return hipGetLastError();
 }
 
+template <int TW, int TH, int PPL>
+static hipError_t fwd_gauss_shape(const RasterArgs& a, bool persist, bool count, hipStream_t st) {
+  constexpr int NT = TW * TH / PPL;
+  if (a.total_tiles <= 0) return hipSuccess;
+  if (persist) {
+    if (count) {
+      auto k = render_fwd_gauss_kernel<TW, TH, PPL, true, true>;
+      hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
+    } else {
+      auto k = render_fwd_gauss_kernel<TW, TH, PPL, true, false>;
+      hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
+    }
+  } else {
+    if (count)
+      hipLaunchKernelGGL((render_fwd_gauss_kernel<TW, TH, PPL, false, true>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+    else
+      hipLaunchKernelGGL((render_fwd_gauss_kernel<TW, TH, PPL, false, false>), dim3(a.total_tiles), dim3(NT), 0, st,
+                         a);
+  }
+  return hipGetLastError();
+}
+
 template <int N, int TW, int TH, int NB>
 static hipError_t bwd_shape(const RasterArgs& a, bool persist, hipStream_t st) {
   constexpr int NT = TW * TH;
@@ -907,6 +1044,17 @@ hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool 
     case 16: return fwd_n<16>(a, tw, th, ppl, persist, count, st);
     case 32: return fwd_n<32>(a, tw, th, ppl, persist, count, st);
   }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_render_fwd_gauss(int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
+                                   hipStream_t st) {
+  if (tw == 16 && th == 16 && ppl == 1) return fwd_gauss_shape<16, 16, 1>(a, persist, count, st);
+  if (tw == 16 && th == 16 && ppl == 2) return fwd_gauss_shape<16, 16, 2>(a, persist, count, st);
+  if (tw == 16 && th == 16 && ppl == 4) return fwd_gauss_shape<16, 16, 4>(a, persist, count, st);
+  if (tw == 8 && th == 8 && ppl == 1) return fwd_gauss_shape<8, 8, 1>(a, persist, count, st);
+  if (tw == 32 && th == 16 && ppl == 2) return fwd_gauss_shape<32, 16, 2>(a, persist, count, st);
+  if (tw == 32 && th == 16 && ppl == 4) return fwd_gauss_shape<32, 16, 4>(a, persist, count, st);
   return hipErrorInvalidValue;
 }
 

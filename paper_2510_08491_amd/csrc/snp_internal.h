@@ -59,6 +59,13 @@ enum Counter {
 //   [5N]           b2
 inline __host__ __device__ int table_stride(int N) { return 5 * N + 4; }
 
+// Record of a Gaussian (view, primitive) pair uses q2..q4 only (the colour
+// stays where the colour kernels write it):
+//   q2 (u, v, ka, col.r)  q3 (kb, kc, opacity, col.g)  q4 (0, 0, 0, col.b)
+// with (u, v) the projected centre in pixels and, for the pixel offset
+// (dx, dy) = pixel centre - (u, v), log2 of the Gaussian factor
+//   ka dx^2 + kb dx dy + kc dy^2   (<= 0)
+//
 // Record of a (view, primitive) pair, 6 float4:
 //   q0 (dc.xyz, rx)  q1 (gx.xyz, ry)  q2 (gy.xyz, col.r)
 //   q3 (mc.xyz, col.g)  q4 (hx.xyz, col.b)  q5 (hy.xyz, 0)
@@ -119,7 +126,9 @@ struct ViewArgs {
   int32_t V;
   float z_near;
   int32_t color_mode;
+  int32_t primitive;  // 0 neural, 1 Gaussian
   const float *centers, *scales, *quats, *colors;
+  const float* opacity;
   const CamDev* cams;
   float* records;
   int32_t* rects;
@@ -235,6 +244,8 @@ int bwd_batch_default(int tw, int th);
 hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
                              hipStream_t st);
 hipError_t launch_render_bwd(int N, int tw, int th, int nb, bool persist, const RasterArgs& a, hipStream_t st);
+hipError_t launch_render_fwd_gauss(int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
+                                   hipStream_t st);
 hipError_t launch_wave_sum_selftest(const float* in, float* out, int waves, hipStream_t st);
 // loss.hip
 size_t loss_scratch_bytes();

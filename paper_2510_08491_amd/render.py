@@ -13,7 +13,7 @@ import torch
 
 from . import _lib as L
 
-PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh")
+PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity")
 XI_DIM = 8
 
 
@@ -42,6 +42,8 @@ class RenderConfig:
     # device bytes the pair cache may take; None: 85% of the free memory
     # left after the rest of the workspace
     fwd_cache_budget: Optional[int] = None
+    # 0 neural primitives; 1 Gaussian splats (forward only)
+    primitive: int = 0
 
     def to_c(self) -> L.SnpConfig:
         c = L.SnpConfig()
@@ -250,7 +252,7 @@ class Rasterizer:
 
     def grads_struct(self, grads: Dict[str, torch.Tensor]) -> L.SnpGrads:
         g = L.SnpGrads()
-        for k in PARAM_KEYS:
+        for k, _ in L.SnpGrads._fields_:
             setattr(g, k, _ptr(grads.get(k)))
         return g
 
@@ -287,7 +289,10 @@ def kernel_timing_read():
 
 
 def zeros_like_params(params: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
-    return {k: torch.zeros_like(v) for k, v in params.items()}
+    """Zeroed gradient tensors for the parameters the backward differentiates
+    (every one but the Gaussians' opacity)."""
+    keys = {k for k, _ in L.SnpGrads._fields_}
+    return {k: torch.zeros_like(v) for k, v in params.items() if k in keys}
 
 
 class GraphStep:

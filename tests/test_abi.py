@@ -90,3 +90,30 @@ def test_supported_tiles():
     n = lib.snp_supported_tiles(arr, 21)
     triples = [tuple(arr[3 * i:3 * i + 3]) for i in range(n)]
     assert (16, 16, 1) in triples and all(tw * th % (64 * ppl) == 0 for tw, th, ppl in triples)
+
+
+def test_gaussian_layout_and_forward_only():
+    """Gaussian splats (primitive 1): no density table, float64
+    discriminants, gradient records or pair cache in the workspace; the
+    density-MLP options are not checked; the backward entry points refuse
+    before touching any pointer."""
+    L = _lib()
+    lib = L.lib()
+    from paper_2510_08491_amd.render import camera_array
+    cams = camera_array(S.make_cameras([(64, 64), (100, 40)], seed=1))
+    lay, lay_n = L.SnpLayout(), L.SnpLayout()
+    assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=3, omega0=-1.0, primitive=1)), 1000, 2, cams, 5000,
+                                    C.byref(lay)) == L.SNP_OK
+    assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=16)), 1000, 2, cams, 5000, C.byref(lay_n)) == L.SNP_OK
+    assert lay.table_stride == 0 and lay.ahat_cache_bytes == 0 and lay.bytes < lay_n.bytes
+    assert lay.total_tiles == lay_n.total_tiles and lay.capacity == 5000
+    assert lib.snp_workspace_layout(C.byref(_cfg(primitive=2)), 1000, 2, cams, 5000, C.byref(lay)) == L.SNP_ERR_INVALID
+    # backward and whole steps are not built for Gaussians
+    fake = C.c_void_p(256)
+    pr, g = L.SnpPrims(), L.SnpGrads()
+    pr.P = 1000
+    assert lib.snp_render_backward(C.byref(_cfg(primitive=1)), C.byref(pr), 2, cams, fake, C.byref(lay), fake, fake,
+                                   C.byref(g), None) == L.SNP_ERR_UNSUPPORTED
+    loss = C.c_double(0)
+    assert lib.snp_step(C.byref(_cfg(primitive=1)), C.byref(pr), 2, cams, fake, C.byref(lay), fake, fake, fake, 1.0,
+                        C.byref(loss), fake, C.byref(g), None) == L.SNP_ERR_UNSUPPORTED

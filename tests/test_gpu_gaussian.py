@@ -1,0 +1,116 @@
+"""Parity of the Gaussian splats (primitive 1, the paper's 3DGS comparison
+kernel) through the C ABI with the FP64 oracle.
+
+Bars as for the neural primitives: tile lists, sort order, rectangles, depth
+keys and tile counts bit-exact; images and transmittance within 1e-4 max
+abs; hit-pair counts equal up to pixels whose early termination (T < t_eps)
+is decided differently in float32 and float64."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic as S
+from oracle.gaussian import project_gaussians, render_pixels_gaussian, render_view_gaussian
+from oracle.keys import sorted_instances, tile_lists, tile_ranges
+from tests.gpu_helpers import config_for, options_for, run_forward, say
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    say(f"[gpu-test] {request.node.name}")
+    yield
+    torch.cuda.synchronize()
+
+
+def _check(fw, scene, cams, cfg):
+    projs = [project_gaussians(scene, c, cfg.tile_w, cfg.tile_h, cfg.z_near) for c in cams]
+    lists = tile_lists(scene, cams, cfg.tile_w, cfg.tile_h, cfg.z_near, projs=projs)
+    keys, vals = sorted_instances(lists)
+    ranges = tile_ranges(lists)
+    assert fw["instances"] == len(keys)
+    assert np.array_equal(fw["keys"], keys)
+    assert np.array_equal(fw["values"], vals)
+    nonempty = ranges[:, 1] > ranges[:, 0]
+    assert np.array_equal(fw["ranges"][nonempty], ranges[nonempty])
+    opts = options_for(cfg)
+    pairs = 0
+    for v, (cam, pr) in enumerate(zip(cams, projs)):
+        ne = pr["nonempty"]
+        assert np.array_equal(fw["tile_counts"][v], pr["n_tiles"].astype(np.int32))
+        assert np.array_equal(fw["rects"][v][ne], pr["rect"][ne].astype(np.int32))
+        assert np.array_equal(fw["depth_bits"][v][ne], pr["depth_bits"][ne])
+        ref = render_view_gaussian(scene, cam, opts, proj=pr)
+        err = np.max(np.abs(fw["images"][v] - ref["image"]))
+        terr = np.max(np.abs(fw["T"][v] - ref["T"]))
+        say(f"  view {v} {cam.width}x{cam.height}: image err {err:.2e}, T err {terr:.2e}")
+        assert err <= IMG_TOL and terr <= IMG_TOL
+        pairs += ref["hit_pairs"]
+    say(f"  instances {fw['instances']}, hit pairs gpu {fw['hit_pairs']} oracle {pairs}")
+    assert abs(fw["hit_pairs"] - pairs) <= 1e-3 * pairs + 2
+
+
+@pytest.mark.parametrize("tile,persistent", [((16, 16, 1), 0), ((16, 16, 2), 1), ((16, 16, 4), 0), ((8, 8, 1), 1),
+                                             ((32, 16, 2), 0), ((32, 16, 4), 1)])
+def test_gaussian_keys_and_images_all_tiles(tile, persistent):
+    """Two ragged views (neither a multiple of any tile size)."""
+    scene = S.custom_scene(700, 8, primitive=1, scale_lo=0.005, scale_hi=0.06, seed=201)
+    cams = S.make_cameras([(72, 56), (50, 66)], seed=202)
+    cfg = config_for(scene, tile=tile, persistent=persistent)
+    _check(run_forward(scene, cams, cfg), scene, cams, cfg)
+
+
+@pytest.mark.parametrize("color_mode", [1, 2])
+def test_gaussian_view_dependent_colour_alpha_clamps_background(color_mode):
+    """Colour MLP or SH colour, the 3DGS alpha floor of 1/255, a lower
+    alpha_max and a background."""
+    scene = S.custom_scene(500, 8, color_mode=color_mode, cmlp_width=16, cmlp_depth=2, primitive=1,
+                           scale_lo=0.01, scale_hi=0.08, seed=211)
+    cams = S.make_cameras([(64, 64), (80, 48)], seed=212)
+    cfg = config_for(scene, tile=(16, 16, 1), alpha_min=1.0 / 255.0, alpha_max=0.9, bg=(0.25, 0.5, 1.0))
+    _check(run_forward(scene, cams, cfg), scene, cams, cfg)
+
+
+def test_gaussian_dense_early_termination():
+    """Large opaque Gaussians: most pixels terminate early."""
+    scene = S.custom_scene(900, 8, primitive=1, scale_lo=0.03, scale_hi=0.15, seed=221)
+    scene["opacity"][:] = np.float32(0.95)
+    cams = S.make_cameras([(64, 48)], seed=222)
+    cfg = config_for(scene, tile=(16, 16, 2), persistent=1, t_eps=1e-3)
+    _check(run_forward(scene, cams, cfg), scene, cams, cfg)
+
+
+def test_gaussian_full_size_sampled():
+    """The 100k-Gaussian 800x800 SH workload (one view): keys of every
+    primitive bit-exact, sampled pixels against the oracle pixel by pixel,
+    and the instance lists of sampled tiles."""
+    _, scene, cams, _ = S.make_workload("G")
+    cams = cams[:1]
+    cfg = config_for(scene, tile=(16, 16, 1), alpha_min=1.0 / 255.0)
+    fw = run_forward(scene, cams, cfg)
+    cam = cams[0]
+    pr = project_gaussians(scene, cam, cfg.tile_w, cfg.tile_h, cfg.z_near)
+    ne = pr["nonempty"]
+    assert np.array_equal(fw["tile_counts"][0], pr["n_tiles"].astype(np.int32))
+    assert np.array_equal(fw["rects"][0][ne], pr["rect"][ne].astype(np.int32))
+    assert np.array_equal(fw["depth_bits"][0][ne], pr["depth_bits"][ne])
+    rng = np.random.default_rng(17)
+    cols = rng.integers(200, 600, 40)
+    rows = rng.integers(200, 600, 40)
+    c, t, h = render_pixels_gaussian(scene, cam, cols, rows, options_for(cfg), proj=pr)
+    err = np.max(np.abs(fw["images"][0][rows, cols] - c))
+    terr = np.max(np.abs(fw["T"][0][rows, cols] - t))
+    say(f"  sampled image err {err:.2e}, T err {terr:.2e}, instances {fw['instances']}, pairs {fw['hit_pairs']}")
+    assert err <= IMG_TOL and terr <= IMG_TOL
+    ntx = (cam.width + cfg.tile_w - 1) // cfg.tile_w
+    ids = np.nonzero(ne)[0]
+    tr = pr["trect"][ids]
+    for g in rng.integers(0, fw["ranges"].shape[0], 8):
+        ty, tx = divmod(int(g), ntx)
+        sel = (tr[:, 0] <= tx) & (tx <= tr[:, 1]) & (tr[:, 2] <= ty) & (ty <= tr[:, 3])
+        lst = sorted(zip(pr["depth_bits"][ids][sel].tolist(), ids[sel].tolist()))
+        s, e = fw["ranges"][g]
+        assert fw["values"][s:e].tolist() == [p for _, p in lst]
