@@ -65,6 +65,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "A"],
                     help="C3/C4/C5: fwd+bwd step; A: forward-only frames/s of the 100k-primitive throughput workload")
     ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,bwd_batch] (default: tuned)")
+    ap.add_argument("--bin-order", type=int, default=0, choices=[0, 1, 2],
+                    help="1 depth sort of the pairs then tile-bit instance sort, 2 full-key sort, 0 by size")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -92,7 +94,7 @@ def main(argv=None):
         tile = tuning.lookup(N, scene["color_mode"], cams) or (16, 16, 2)
     if len(tile) == 3:
         tile = tile + (0,)
-    cfg = snp.RenderConfig(n_hidden=N, omega0=scene["omega0"], color_mode=scene["color_mode"],
+    cfg = snp.RenderConfig(n_hidden=N, omega0=scene["omega0"], color_mode=scene["color_mode"], bin_order=a.bin_order,
                            cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], tile_w=tile[0],
                            tile_h=tile[1], px_per_lane=tile[2], bwd_batch=tile[3], persistent=1)
     log(f"[bench] workload {a.workload}: P={scene['P']} V={len(cams)} N={N} tile={tile}")
@@ -345,12 +347,14 @@ def forward_fps(a):
     _, scene, cams, _ = S.make_workload("A")
     tile = tuple(int(x) for x in a.tile.split(",")) if a.tile else (16, 16, 1)
     cfg = snp.RenderConfig(n_hidden=scene["N"], omega0=scene["omega0"], color_mode=scene["color_mode"],
+                           bin_order=a.bin_order,
                            tile_w=tile[0], tile_h=tile[1], px_per_lane=tile[2], persistent=1, fwd_cache=0)
     log(f"[bench] workload A: P={scene['P']} views={len(cams)} {cams[0].width}x{cams[0].height} "
         f"N={scene['N']} tile={tile}")
     nn = _fps(snp, torch, scene, cams, cfg, a, "neural primitives")
     _, gscene, gcams, _ = S.make_workload("G")
-    gcfg = snp.RenderConfig(color_mode=gscene["color_mode"], primitive=1, tile_w=tile[0], tile_h=tile[1],
+    gcfg = snp.RenderConfig(color_mode=gscene["color_mode"], primitive=1, bin_order=a.bin_order, tile_w=tile[0],
+                            tile_h=tile[1],
                             px_per_lane=tile[2], persistent=1, alpha_min=1.0 / 255.0)
     gs = _fps(snp, torch, gscene, gcams, gcfg, a, "Gaussians")
     ms, ms_b = nn["ms"], nn["ms_b"]

@@ -113,7 +113,14 @@ typedef struct {
  *             projected centre; per pixel inside it alpha = min(alpha_max,
  *             opacity exp(-d^T Sigma2d^-1 d / 2)).  n_hidden, omega0 and
  *             fwd_cache are ignored; forward only (the backward, snp_step
- *             and snp_graph_create return SNP_ERR_UNSUPPORTED). */
+ *             and snp_graph_create return SNP_ERR_UNSUPPORTED).
+ *  bin_order  how snp_bin / snp_sort reach the (tile, depth) order; both
+ *             give the same arrays bit for bit.  1 = the (view, primitive)
+ *             pairs are sorted by depth first, instances are emitted in that
+ *             order and sorted by their tile bits only (fewer passes over
+ *             the instances, a few more launches); 2 = instances emitted in
+ *             primitive order and sorted by the whole key; 0 = 1 when
+ *             V * P >= 2^16, else 2. */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -127,6 +134,7 @@ typedef struct {
   int32_t fwd_cache;
   int64_t fwd_cache_instances;
   int32_t primitive;
+  int32_t bin_order;
 } snp_config;
 
 typedef struct {
@@ -156,7 +164,7 @@ typedef struct {
   size_t rects;           /* per-(view, primitive) pixel rectangles, int32 x0,x1,y0,y1 */
   size_t depth_bits;      /* per-(view, primitive) uint32 depth key (0 = culled) */
   size_t tile_counts;     /* per-(view, primitive) uint32 number of tiles */
-  size_t offsets;         /* per-(view, primitive) uint32 exclusive scan of tile_counts */
+  size_t offsets;         /* uint32 exclusive scan of tile_counts over the (view, primitive) pairs (in depth order with bin_order 1) */
   size_t keys;            /* uint64 sorted keys (tile << 31 | depth bits), capacity entries */
   size_t values;          /* uint32 sorted primitive ids, capacity entries */
   size_t ranges;          /* per global tile uint32 [start, end) */
@@ -190,14 +198,19 @@ snp_status snp_workspace_layout(const snp_config* cfg, int64_t P, int32_t V, con
 snp_status snp_preprocess(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
                           void* ws, const snp_layout* layout, hipStream_t stream);
 
-/* Tile binning: exclusive scan of the tile counts and one (key, value)
+/* Tile binning: the exclusive scan of the tile counts and one (key, value)
  * instance per covered tile, key = (global tile id << 31) | depth bits,
- * value = primitive id; instance count and overflow flag on the device. */
+ * value = primitive id; instance count and overflow flag on the device.
+ * With bin_order 1 the (view, primitive) pairs are first sorted by depth
+ * bits (stably, so equal depths keep primitive order) and the scan and the
+ * instances follow that order. */
 snp_status snp_bin(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
                    const snp_layout* layout, hipStream_t stream);
 
-/* Stable device radix sort of the instances by key (so equal keys keep
- * primitive order) and the [start, end) range of every global tile. */
+/* Stable device radix sort of the instances into key order (equal keys in
+ * primitive order) and the [start, end) range of every global tile.  With
+ * bin_order 1 the instances arrive from snp_bin in depth order, so the tile
+ * bits of the key alone are sorted. */
 snp_status snp_sort(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
                     const snp_layout* layout, hipStream_t stream);
 
@@ -250,7 +263,8 @@ snp_status snp_read_status(void* ws, const snp_layout* layout, int64_t* instance
 /* Synchronises `stream` and copies the 8 device counters of the workspace:
  * [0] instances, [1] overflow flag, [2] hit pairs and [6] pairs with a
  * positive, unclamped integral (both counted by snp_render_forward with
- * count_pairs != 0), [3] phase-range flag, [4], [5] work-queue heads. */
+ * count_pairs != 0), [3] phase-range flag, [4], [5] work-queue heads,
+ * [7] the number of (view, primitive) pairs the depth sort ordered. */
 snp_status snp_read_counters(void* ws, const snp_layout* layout, int64_t* out8, hipStream_t stream);
 
 /* Kernel timing for measurement: while enabled, every eager (not captured)

@@ -23,7 +23,8 @@ class SnpConfig(C.Structure):
                 ("tile_h", C.c_int32), ("px_per_lane", C.c_int32), ("z_near", C.c_float),
                 ("t_eps", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
                 ("bg", C.c_float * 3), ("persistent", C.c_int32), ("bwd_batch", C.c_int32),
-                ("fwd_cache", C.c_int32), ("fwd_cache_instances", C.c_int64), ("primitive", C.c_int32)]
+                ("fwd_cache", C.c_int32), ("fwd_cache_instances", C.c_int64), ("primitive", C.c_int32),
+                ("bin_order", C.c_int32)]
 
 
 class SnpPrims(C.Structure):

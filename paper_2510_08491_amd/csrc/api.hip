@@ -15,10 +15,12 @@ struct Plan {
   snp_layout L;
   size_t scan_scratch, sort_scratch, loss_partials, cams_bytes;
   size_t keys_alt, values_alt;
+  size_t dkeys[2], dvals[2], counts_sorted;  // depth sort of the (view, primitive) pairs
   std::vector<int32_t> tile_base;
   std::vector<int64_t> pix_base;
   int64_t total_pixels;
-  int key_bits;
+  int tile_bits;  // significant bits of the global tile id
+  bool depth_first;  // depth sort of the pairs, then the instances by tile bits only
 };
 
 static bool valid_n(int n) { return n == 4 || n == 8 || n == 16 || n == 32; }
@@ -43,6 +45,7 @@ static snp_status check_cfg(const snp_config* cfg) {
     return SNP_ERR_UNSUPPORTED;
   if (cfg->fwd_cache != 0 && cfg->fwd_cache != 1) return SNP_ERR_INVALID;
   if (cfg->fwd_cache_instances < 0) return SNP_ERR_INVALID;
+  if (cfg->bin_order < 0 || cfg->bin_order > 2) return SNP_ERR_INVALID;
   return SNP_OK;
 }
 
@@ -69,7 +72,7 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   s = check_cams(V, cams);
   if (s != SNP_OK) return s;
   if (P <= 0 || P > ((int64_t)1 << 31) - 1) return SNP_ERR_INVALID;
-  if ((int64_t)V * P > ((int64_t)1 << 33)) return SNP_ERR_INVALID;
+  if ((int64_t)V * P >= ((int64_t)1 << 32)) return SNP_ERR_INVALID;  // pair indices are uint32
   if (cap <= 0 || cap > ((int64_t)1 << 31) - 1) return SNP_ERR_INVALID;
   pl->tile_base.resize(V);
   pl->pix_base.resize(V);
@@ -84,7 +87,8 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   pl->total_pixels = pix;
   int tb = 1;
   while (((int64_t)1 << tb) < tiles) ++tb;
-  pl->key_bits = 31 + tb;
+  pl->tile_bits = tb;
+  pl->depth_first = cfg->bin_order == 1 || (cfg->bin_order == 0 && (int64_t)V * P >= ((int64_t)1 << 16));
   // Gaussians have no density table, float64 discriminants, backward arrays
   // or pair cache
   const bool gs = gaussian(cfg);
@@ -110,11 +114,17 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   L.tile_counts = take(sizeof(uint32_t) * (size_t)VP);
   L.offsets = take(sizeof(uint32_t) * (size_t)VP);
   pl->scan_scratch = take(scan_scratch_bytes(VP));
+  const size_t dn = pl->depth_first ? (size_t)VP : 0;
+  for (int k = 0; k < 2; ++k) {
+    pl->dkeys[k] = take(sizeof(unsigned long long) * dn);
+    pl->dvals[k] = take(sizeof(uint32_t) * dn);
+  }
+  pl->counts_sorted = take(sizeof(uint32_t) * dn);
   L.keys = take(sizeof(unsigned long long) * (size_t)cap);
   pl->keys_alt = take(sizeof(unsigned long long) * (size_t)cap);
   L.values = take(sizeof(uint32_t) * (size_t)cap);
   pl->values_alt = take(sizeof(uint32_t) * (size_t)cap);
-  pl->sort_scratch = take(sort_scratch_bytes(cap));
+  pl->sort_scratch = take(sort_scratch_bytes(pl->depth_first && VP > cap ? VP : cap));
   L.ranges = take(sizeof(uint32_t) * 2 * (size_t)tiles);
   L.gview = take(gs ? 0 : sizeof(float) * (size_t)VP * kGViewFloats);
   L.gtable = take(sizeof(float) * (size_t)P * TS);
@@ -224,13 +234,37 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
   return SNP_OK;
 }
 
+constexpr int kDepthBits = 31;  // positive float32 depth: the sign bit is zero
+
+// key bits the instance sort orders: the tile bits only when the instances
+// are emitted in depth order, else depth and tile bits
+static int sort_lo(const Plan& pl) { return pl.depth_first ? kDepthBits : 0; }
+static int sort_bits(const Plan& pl) { return pl.depth_first ? pl.tile_bits : kDepthBits + pl.tile_bits; }
+
+// Instance offsets and instances, in primitive order or (depth_first) in the
+// depth order of the (view, primitive) pairs.
 static snp_status do_bin(const snp_config* cfg, int64_t P, int32_t V, const Plan& pl, void* ws, hipStream_t st) {
   const snp_layout& L = pl.L;
   unsigned long long* counters = wsp<unsigned long long>(ws, L.counters);
   const int64_t VP = (int64_t)V * P;
-  SNP_HIP(scan_exclusive_u32(wsp<uint32_t>(ws, L.tile_counts), wsp<uint32_t>(ws, L.offsets), VP,
-                             wsp<void>(ws, pl.scan_scratch), reinterpret_cast<uint64_t*>(counters + CNT_INSTANCES), st));
-  const bool odd = radix_passes(pl.key_bits) % 2 == 1;
+  const uint32_t* order = nullptr;  // identity: primitive order
+  const uint32_t* counts = wsp<uint32_t>(ws, L.tile_counts);
+  if (pl.depth_first) {
+    unsigned long long* dk0 = wsp<unsigned long long>(ws, pl.dkeys[0]);
+    unsigned long long* dk1 = wsp<unsigned long long>(ws, pl.dkeys[1]);
+    uint32_t* dv0 = wsp<uint32_t>(ws, pl.dvals[0]);
+    uint32_t* dv1 = wsp<uint32_t>(ws, pl.dvals[1]);
+    SNP_HIP(launch_depth_keys(wsp<uint32_t>(ws, L.depth_bits), VP, dk0, dv0, counters + CNT_DEPTH_SORT, st));
+    SNP_HIP(radix_sort(dk0, dv0, dk1, dv1, VP, counters + CNT_DEPTH_SORT, 0, kDepthBits,
+                       wsp<void>(ws, pl.sort_scratch), st));
+    order = radix_passes(kDepthBits) % 2 == 1 ? dv1 : dv0;
+    uint32_t* cs = wsp<uint32_t>(ws, pl.counts_sorted);
+    SNP_HIP(launch_gather_counts(order, counts, VP, cs, st));
+    counts = cs;
+  }
+  SNP_HIP(scan_exclusive_u32(counts, wsp<uint32_t>(ws, L.offsets), VP, wsp<void>(ws, pl.scan_scratch),
+                             reinterpret_cast<uint64_t*>(counters + CNT_INSTANCES), st));
+  const bool odd = radix_passes(sort_bits(pl)) % 2 == 1;
   EmitArgs ea;
   ea.P = P;
   ea.V = V;
@@ -239,6 +273,7 @@ static snp_status do_bin(const snp_config* cfg, int64_t P, int32_t V, const Plan
   ea.rects = wsp<int32_t>(ws, L.rects);
   ea.depth_bits = wsp<uint32_t>(ws, L.depth_bits);
   ea.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
+  ea.order = order;
   ea.offsets = wsp<uint32_t>(ws, L.offsets);
   ea.keys = wsp<unsigned long long>(ws, odd ? pl.keys_alt : L.keys);
   ea.values = wsp<uint32_t>(ws, odd ? pl.values_alt : L.values);
@@ -250,15 +285,19 @@ static snp_status do_bin(const snp_config* cfg, int64_t P, int32_t V, const Plan
 static snp_status do_sort(const Plan& pl, void* ws, hipStream_t st) {
   const snp_layout& L = pl.L;
   unsigned long long* counters = wsp<unsigned long long>(ws, L.counters);
-  const bool odd = radix_passes(pl.key_bits) % 2 == 1;
+  const bool odd = radix_passes(sort_bits(pl)) % 2 == 1;
   unsigned long long* k_main = wsp<unsigned long long>(ws, L.keys);
   unsigned long long* k_alt = wsp<unsigned long long>(ws, pl.keys_alt);
   uint32_t* v_main = wsp<uint32_t>(ws, L.values);
   uint32_t* v_alt = wsp<uint32_t>(ws, pl.values_alt);
+  // instances emitted in depth order need their tile bits sorted only: the
+  // passes are stable, which completes the (tile, depth) order
+  unsigned long long* n_inst = counters + CNT_INSTANCES;
+  void* scr = wsp<void>(ws, pl.sort_scratch);
   if (odd)
-    SNP_HIP(radix_sort(k_alt, v_alt, k_main, v_main, L.capacity, counters, pl.key_bits, wsp<void>(ws, pl.sort_scratch), st));
+    SNP_HIP(radix_sort(k_alt, v_alt, k_main, v_main, L.capacity, n_inst, sort_lo(pl), sort_bits(pl), scr, st));
   else
-    SNP_HIP(radix_sort(k_main, v_main, k_alt, v_alt, L.capacity, counters, pl.key_bits, wsp<void>(ws, pl.sort_scratch), st));
+    SNP_HIP(radix_sort(k_main, v_main, k_alt, v_alt, L.capacity, n_inst, sort_lo(pl), sort_bits(pl), scr, st));
   SNP_HIP(launch_ranges(k_main, counters, L.capacity, wsp<uint32_t>(ws, L.ranges), L.total_tiles, st));
   return SNP_OK;
 }

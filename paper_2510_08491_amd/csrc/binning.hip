@@ -2,11 +2,21 @@
 // App. A lists beside preprocessing; the blending of Eq. 4 needs the
 // primitives of every pixel in depth order).
 //
-//   scan   : exclusive prefix sum of the per-(view, primitive) tile counts
-//   emit   : one (key, value) instance per covered tile,
-//            key = (global tile id << 31) | float32 depth bits, value = primitive id
-//   sort   : stable LSD radix sort of the instances by key, 8-bit digits,
-//            3 kernels per pass (digit histogram per block, scan, stable scatter)
+//   depth  : (for many pairs) stable LSD radix sort of the (view, primitive)
+//            pairs by their float32 depth bits (ties keep the index order)
+//   scan   : exclusive prefix sum of the tile counts in that order
+//   emit   : one (key, value) instance per covered tile, primitives in depth
+//            order, key = (global tile id << 31) | float32 depth bits,
+//            value = primitive id
+//   sort   : stable LSD radix sort of the instances by the tile bits of the
+//            key only: the input is already in depth order and every pass
+//            is stable, so the result is ordered by the whole key (and by
+//            primitive index for equal depths), as a sort over all bits
+//            would order it, with 2-3 passes over the instances instead of
+//            6 (8-bit digits, 3 kernels per pass: digit histogram per block,
+//            scan, stable scatter).  For few pairs the extra launches of the
+//            depth sort cost more than the passes saved: the pairs stay in
+//            primitive order and the sort covers depth and tile bits.
 //   ranges : [start, end) of every global tile in the sorted array
 //
 // Sizes only known on the device (the instance count) are read from device
@@ -147,9 +157,44 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 // emit instances
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) emit_kernel(EmitArgs a) {
+// (depth bits, index) of every (view, primitive) pair, the input of the depth sort
+__global__ void __launch_bounds__(256) depth_keys_kernel(const uint32_t* __restrict__ depth_bits, int64_t n,
+                                                         unsigned long long* __restrict__ keys,
+                                                         uint32_t* __restrict__ idx, unsigned long long* n_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.P * a.V) return;
+  if (i == 0) *n_out = (unsigned long long)n;
+  if (i >= n) return;
+  keys[i] = depth_bits[i];
+  idx[i] = (uint32_t)i;
+}
+
+// tile counts in depth order
+__global__ void __launch_bounds__(256) gather_counts_kernel(const uint32_t* __restrict__ order,
+                                                            const uint32_t* __restrict__ counts, int64_t n,
+                                                            uint32_t* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[j] = counts[order[j]];
+}
+
+hipError_t launch_depth_keys(const uint32_t* depth_bits, int64_t n, unsigned long long* keys, uint32_t* idx,
+                             unsigned long long* n_out, hipStream_t st) {
+  hipLaunchKernelGGL(depth_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, depth_bits, n, keys, idx,
+                     n_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* counts, int64_t n, uint32_t* out,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(gather_counts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, order, counts, n, out);
+  return hipGetLastError();
+}
+
+// thread j emits the instances of the j-th (view, primitive) pair, in depth
+// order (or primitive order when order is null), at offsets[j]
+__global__ void __launch_bounds__(256) emit_kernel(EmitArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.P * a.V) return;
+  const int64_t i = a.order ? (int64_t)a.order[j] : j;
   const uint32_t cnt = a.tile_counts[i];
   if (cnt == 0) return;
   const int v = (int)(i / a.P);
@@ -158,7 +203,7 @@ __global__ void __launch_bounds__(256) emit_kernel(EmitArgs a) {
   const int tx0 = a.rects[4 * i] / cam.tile_w, tx1 = a.rects[4 * i + 1] / cam.tile_w;
   const int ty0 = a.rects[4 * i + 2] / cam.tile_h, ty1 = a.rects[4 * i + 3] / cam.tile_h;
   const unsigned long long dbits = a.depth_bits[i];
-  int64_t pos = a.offsets[i];
+  int64_t pos = a.offsets[j];
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
       if (pos >= a.capacity) return;
@@ -182,19 +227,20 @@ hipError_t launch_emit(const EmitArgs& a, unsigned long long* counters, hipStrea
 // ---------------------------------------------------------------------------
 // stable LSD radix sort
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t sort_count(const unsigned long long* counters, int64_t capacity) {
-  const unsigned long long n = counters[CNT_INSTANCES];
+// number of elements to sort: *count, at most the capacity of the buffers
+__device__ __forceinline__ int64_t sort_count(const unsigned long long* count, int64_t capacity) {
+  const unsigned long long n = *count;
   return n > (unsigned long long)capacity ? capacity : (int64_t)n;
 }
 
 __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const unsigned long long* __restrict__ keys,
-                                                                  const unsigned long long* counters,
+                                                                  const unsigned long long* count,
                                                                   int64_t capacity, int shift,
                                                                   uint32_t* __restrict__ hist, int64_t nblocks) {
   __shared__ uint32_t s_h[kRadix];
   s_h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t n = sort_count(counters, capacity);
+  const int64_t n = sort_count(count, capacity);
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t i = base + (int64_t)r * kSortThreads + threadIdx.x;
@@ -206,14 +252,14 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const unsigned
 
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const unsigned long long* __restrict__ kin, const uint32_t* __restrict__ vin,
-    unsigned long long* __restrict__ kout, uint32_t* __restrict__ vout, const unsigned long long* counters,
+    unsigned long long* __restrict__ kout, uint32_t* __restrict__ vout, const unsigned long long* count,
     int64_t capacity, int shift, const uint32_t* __restrict__ offs, int64_t nblocks) {
   constexpr int NW = kSortThreads / 64;
   __shared__ uint32_t s_off[kRadix];        // global offset of each digit for this block (running)
   __shared__ uint32_t s_wcnt[NW][kRadix];   // per-wave digit counts in the current round
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   s_off[t] = offs[(int64_t)t * nblocks + blockIdx.x];
-  const int64_t n = sort_count(counters, capacity);
+  const int64_t n = sort_count(count, capacity);
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kSortRounds; ++r) {
@@ -268,11 +314,12 @@ size_t sort_scratch_bytes(int64_t capacity) {
   return ((size_t)nh * 4 + 255) / 256 * 256 * 2 + scan_scratch_bytes(nh);
 }
 
-// Sorts keys/values by bits [0, key_bits).  Buffers ping-pong between (k0,v0)
-// and (k1,v1); the input is in (k0,v0) and the result ends in (k0,v0) if the
-// number of passes is even, else in (k1,v1).
+// Sorts the first min(*count, capacity) keys/values by bits [lo_bit, lo_bit +
+// key_bits), stably.  Buffers ping-pong between (k0,v0) and (k1,v1); the
+// input is in (k0,v0) and the result ends in (k0,v0) if the number of passes
+// is even, else in (k1,v1).
 hipError_t radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1, int64_t capacity,
-                      const unsigned long long* counters, int key_bits, void* scratch, hipStream_t st) {
+                      const unsigned long long* count, int lo_bit, int key_bits, void* scratch, hipStream_t st) {
   const int64_t nblocks = (capacity + kSortChunk - 1) / kSortChunk;
   if (nblocks <= 0) return hipSuccess;
   const int64_t nh = nblocks * kRadix;
@@ -284,13 +331,13 @@ hipError_t radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* 
   unsigned long long *ki = k0, *ko = k1;
   uint32_t *vi = v0, *vo = v1;
   for (int ps = 0; ps < passes; ++ps) {
-    const int shift = 8 * ps;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nblocks), dim3(kSortThreads), 0, st, ki, counters, capacity,
+    const int shift = lo_bit + 8 * ps;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nblocks), dim3(kSortThreads), 0, st, ki, count, capacity,
                        shift, hist, nblocks);
     hipError_t e = scan_exclusive_u32(hist, offs, nh, scan_scr, nullptr, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nblocks), dim3(kSortThreads), 0, st, ki, vi, ko, vo,
-                       counters, capacity, shift, offs, nblocks);
+                       count, capacity, shift, offs, nblocks);
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
@@ -305,7 +352,7 @@ int radix_passes(int key_bits) { return (key_bits + 7) / 8; }
 __global__ void __launch_bounds__(256) ranges_kernel(const unsigned long long* __restrict__ keys,
                                                      const unsigned long long* counters, int64_t capacity,
                                                      uint32_t* __restrict__ ranges) {
-  const int64_t n = sort_count(counters, capacity);
+  const int64_t n = sort_count(counters + CNT_INSTANCES, capacity);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) {

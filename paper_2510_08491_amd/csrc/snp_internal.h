@@ -50,6 +50,7 @@ enum Counter {
   CNT_QUEUE_FWD = 4,
   CNT_QUEUE_BWD = 5,
   CNT_LIVE_PAIRS = 6,
+  CNT_DEPTH_SORT = 7,  // number of (view, primitive) pairs, the length of the depth sort
   CNT_COUNT = 8
 };
 
@@ -181,7 +182,8 @@ struct EmitArgs {
   const int32_t* rects;
   const uint32_t* depth_bits;
   const uint32_t* tile_counts;
-  const uint32_t* offsets;
+  const uint32_t* order;    // (view, primitive) pair indices in depth order
+  const uint32_t* offsets;  // first instance of each pair, in depth order
   unsigned long long* keys;
   uint32_t* values;
 };
@@ -232,7 +234,11 @@ hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void
 hipError_t launch_emit(const EmitArgs& a, unsigned long long* counters, hipStream_t st);
 size_t sort_scratch_bytes(int64_t capacity);
 hipError_t radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* k1, uint32_t* v1, int64_t capacity,
-                      const unsigned long long* counters, int key_bits, void* scratch, hipStream_t st);
+                      const unsigned long long* count, int lo_bit, int key_bits, void* scratch, hipStream_t st);
+hipError_t launch_depth_keys(const uint32_t* depth_bits, int64_t n, unsigned long long* keys, uint32_t* idx,
+                             unsigned long long* n_out, hipStream_t st);
+hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* counts, int64_t n, uint32_t* out,
+                                hipStream_t st);
 int radix_passes(int key_bits);
 hipError_t launch_ranges(const unsigned long long* keys, const unsigned long long* counters, int64_t capacity,
                          uint32_t* ranges, int64_t n_tiles, hipStream_t st);

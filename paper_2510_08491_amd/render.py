@@ -44,6 +44,9 @@ class RenderConfig:
     fwd_cache_budget: Optional[int] = None
     # 0 neural primitives; 1 Gaussian splats (forward only)
     primitive: int = 0
+    # 1 depth sort of the (view, primitive) pairs then a tile-bit instance
+    # sort; 2 one sort over all key bits; 0 picks by size (same result)
+    bin_order: int = 0
 
     def to_c(self) -> L.SnpConfig:
         c = L.SnpConfig()

@@ -17,9 +17,9 @@ def say(msg):
 
 
 def config_for(scene, tile=(16, 16, 1), persistent=0, t_eps=1e-4, alpha_min=0.0, alpha_max=0.99, bg=(0, 0, 0),
-               fwd_cache=1):
+               fwd_cache=1, bin_order=0):
     return snp.RenderConfig(n_hidden=int(scene["N"]), omega0=float(scene["omega0"]),
-                            primitive=int(scene.get("primitive", 0)),
+                            primitive=int(scene.get("primitive", 0)), bin_order=bin_order,
                             color_mode=int(scene["color_mode"]), cmlp_width=int(scene.get("cmlp_width", 0)),
                             cmlp_depth=int(scene.get("cmlp_depth", 0)), tile_w=tile[0], tile_h=tile[1],
                             px_per_lane=tile[2], bwd_batch=tile[3] if len(tile) > 3 else 0, t_eps=t_eps,

@@ -117,3 +117,27 @@ def test_gaussian_layout_and_forward_only():
     loss = C.c_double(0)
     assert lib.snp_step(C.byref(_cfg(primitive=1)), C.byref(pr), 2, cams, fake, C.byref(lay), fake, fake, fake, 1.0,
                         C.byref(loss), fake, C.byref(g), None) == L.SNP_ERR_UNSUPPORTED
+
+
+def test_bin_order_option():
+    """bin_order 1 adds the depth-sort buffers of the (view, primitive)
+    pairs to the workspace, 2 does not; 0 picks 2 for few pairs (here 2000)
+    and 1 for many; others are invalid."""
+    L = _lib()
+    lib = L.lib()
+    from paper_2510_08491_amd.render import camera_array
+    cams = camera_array(S.make_cameras([(64, 64), (100, 40)], seed=1))
+    lays = {}
+    for order in (0, 1, 2):
+        lays[order] = L.SnpLayout()
+        assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=8, bin_order=order)), 1000, 2, cams, 5000,
+                                        C.byref(lays[order])) == L.SNP_OK
+    assert lays[1].bytes > lays[2].bytes == lays[0].bytes
+    big = {}
+    for order in (0, 1):
+        big[order] = L.SnpLayout()
+        assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=8, bin_order=order)), 40000, 2, cams, 5000,
+                                        C.byref(big[order])) == L.SNP_OK
+    assert big[0].bytes == big[1].bytes
+    bad = L.SnpLayout()
+    assert lib.snp_workspace_layout(C.byref(_cfg(bin_order=3)), 1000, 2, cams, 5000, C.byref(bad)) == L.SNP_ERR_INVALID

@@ -53,13 +53,13 @@ def _check(fw, scene, cams, cfg):
     assert abs(fw["hit_pairs"] - pairs) <= 1e-3 * pairs + 2
 
 
-@pytest.mark.parametrize("tile,persistent", [((16, 16, 1), 0), ((16, 16, 2), 1), ((16, 16, 4), 0), ((8, 8, 1), 1),
-                                             ((32, 16, 2), 0), ((32, 16, 4), 1)])
-def test_gaussian_keys_and_images_all_tiles(tile, persistent):
-    """Two ragged views (neither a multiple of any tile size)."""
+@pytest.mark.parametrize("tile,persistent,bin_order", [((16, 16, 1), 0, 2), ((16, 16, 2), 1, 1), ((16, 16, 4), 0, 1),
+                                                       ((8, 8, 1), 1, 2), ((32, 16, 2), 0, 1), ((32, 16, 4), 1, 2)])
+def test_gaussian_keys_and_images_all_tiles(tile, persistent, bin_order):
+    """Two ragged views (neither a multiple of any tile size), both binning orders."""
     scene = S.custom_scene(700, 8, primitive=1, scale_lo=0.005, scale_hi=0.06, seed=201)
     cams = S.make_cameras([(72, 56), (50, 66)], seed=202)
-    cfg = config_for(scene, tile=tile, persistent=persistent)
+    cfg = config_for(scene, tile=tile, persistent=persistent, bin_order=bin_order)
     _check(run_forward(scene, cams, cfg), scene, cams, cfg)
 
 
@@ -89,7 +89,7 @@ def test_gaussian_full_size_sampled():
     and the instance lists of sampled tiles."""
     _, scene, cams, _ = S.make_workload("G")
     cams = cams[:1]
-    cfg = config_for(scene, tile=(16, 16, 1), alpha_min=1.0 / 255.0)
+    cfg = config_for(scene, tile=(16, 16, 1), alpha_min=1.0 / 255.0, bin_order=1)
     fw = run_forward(scene, cams, cfg)
     cam = cams[0]
     pr = project_gaussians(scene, cam, cfg.tile_w, cfg.tile_h, cfg.z_near)

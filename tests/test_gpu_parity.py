@@ -253,6 +253,26 @@ def test_full_size_sampled(name):
         assert fw["values"][s:e].tolist() == [p for _, p in lst]
 
 
+@pytest.mark.parametrize("tile", [(16, 16, 1), (8, 8, 1), (32, 16, 2)])
+def test_both_binning_orders_give_the_oracle_lists(tile):
+    """Depth sort of the pairs then a tile-bit sort of the instances, and one
+    sort over all key bits: the same keys, values and ranges (the oracle's),
+    bit for bit, on views whose tile counts need one, two and three digits of
+    tile bits."""
+    scene = S.custom_scene(1200, 8, seed=141)
+    cams = S.make_cameras([(64, 48), (200, 120), (120, 90), (48, 40)], seed=142)
+    out = {}
+    for order in (1, 2):
+        cfg = config_for(scene, tile=tile, persistent=1, bin_order=order)
+        fw = run_forward(scene, cams, cfg)
+        _check_keys(fw, scene, cams, cfg)
+        out[order] = fw
+    for k in ("keys", "values", "ranges"):
+        assert np.array_equal(out[1][k], out[2][k])
+    for a, b in zip(out[1]["images"], out[2]["images"]):
+        assert np.array_equal(a, b)
+
+
 def test_capacity_overflow_is_reported_then_grown():
     import paper_2510_08491_amd as snp
     from paper_2510_08491_amd import _lib
