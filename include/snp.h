@@ -286,6 +286,99 @@ const char* snp_status_string(snp_status s);
  * wave of i.  Enqueues on `stream`. */
 snp_status snp_selftest_wave_sum(const float* in, float* out, int32_t waves, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Training-step extras after the backward (Sec. 4, "Training" and
+ * "Population Control"; the appendix on hyperparameters: Adam with learning
+ * rates 1.6e-4 for means, 5e-3 scales, 1e-3 quaternions, 2.5e-3 SH, 1e-3
+ * MLP; densify / prune thresholds 1e-4 / 2e-6, growing scale 1e-2, pruning
+ * scale 0.5).  Device pointers as above; nothing allocates.
+ * ------------------------------------------------------------------------- */
+
+/* One parameter tensor of an Adam step. */
+typedef struct {
+  float *param;       /* n floats, updated in place */
+  const float *grad;  /* n floats */
+  float *m, *v;       /* first and second moments, n floats each, zero before step 1 */
+  int64_t n;
+  float lr;
+  int32_t log_space;  /* 1: the moments and the update are for log(param)
+                         (param > 0), the 3DGS parameterisation of scales; the
+                         gradient is taken as d loss / d param */
+} snp_adam_group;
+
+#define SNP_MAX_ADAM_GROUPS 32
+
+/* One Adam step (Kingma & Ba) over up to SNP_MAX_ADAM_GROUPS tensors in one
+ * launch: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2, theta -= lr
+ * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  step >= 1 counts
+ * the steps taken including this one.  The betas are float64 (1 - b2 for
+ * b2 = 0.999 rounded to float32 would be off by 1.3e-5).  SNP_ERR_INVALID
+ * for null pointers of a non-empty group, n < 0, step < 1 or betas outside
+ * [0, 1). */
+snp_status snp_adam_step(const snp_adam_group* groups, int32_t n_groups, int64_t step, double beta1, double beta2,
+                         double eps, hipStream_t stream);
+
+/* Geometry regulariser: loss = weight / P * sum_p std(s_p), the population
+ * standard deviation of each primitive's three scale components; adds its
+ * gradient into grad_scales (NULL: loss only; 0 where std = 0) and writes
+ * the loss (float64, device) to loss_out.  Uses the loss scratch of a
+ * workspace (any layout from snp_workspace_layout). */
+snp_status snp_scale_regularizer(int64_t P, const float* scales, float weight, float* grad_scales, double* loss_out,
+                                 void* ws, const snp_layout* layout, hipStream_t stream);
+
+/* Population-control statistic, once per training step after the backward:
+ * grad_acc[p] += ||d loss / d (W1, b1, W2, b2) of p||_2 (from grads w1, b1,
+ * w2, b2 with N hidden units) and visible[p] += 1 if p covered a tile of any
+ * of the V views in the workspace's last preprocess. */
+snp_status snp_densify_accumulate(int64_t P, int32_t N, int32_t V, const snp_grads* grads, void* ws,
+                                  const snp_layout* layout, float* grad_acc, float* visible, hipStream_t stream);
+
+typedef struct {
+  float densify_threshold; /* statistic above it: clone or split */
+  float prune_threshold;   /* visible and statistic below it: prune */
+  float grow_scale;        /* max scale <= it: clone, else split */
+  float prune_scale;       /* max scale above it: prune */
+  float split_shrink;      /* scales of split children: s / split_shrink (1.6 in 3DGS) */
+} snp_density_control;
+
+enum { SNP_PRUNE = 0, SNP_KEEP = 1, SNP_CLONE = 2, SNP_SPLIT = 3 };
+
+/* Scratch bytes snp_densify_plan needs for P primitives. */
+size_t snp_densify_scratch_bytes(int64_t P);
+
+/* Decides per primitive, with statistic = grad_acc / visible (0 if never
+ * visible), in this order: prune if max scale > prune_scale; prune if
+ * visible and statistic < prune_threshold; clone (max scale <= grow_scale)
+ * or split if statistic > densify_threshold; else keep.  Writes action[P],
+ * offsets[P] (first output row of each primitive: primitives stay in index
+ * order, a clone's copy follows it, a split primitive is replaced by its two
+ * children) and the new primitive count (int64, device) to new_count. */
+snp_status snp_densify_plan(int64_t P, const float* scales, const float* grad_acc, const float* visible,
+                            const snp_density_control* dc, int32_t* action, uint32_t* offsets, int64_t* new_count,
+                            void* scratch, size_t scratch_bytes, hipStream_t stream);
+
+/* One per-primitive array to carry over: src P x width, dst new_count x
+ * width (the caller sizes it from snp_densify_plan's count).  kind:
+ * SNP_ROWS_PARAM copied to every output row; SNP_ROWS_CENTERS / SCALES the
+ * same but split children get x + R(q) diag(s) u_k (u_k = noise[p][k], 3
+ * standard normals each) / s / split_shrink; SNP_ROWS_STATE optimizer state,
+ * kept on the row that continues the original (a kept primitive, the first
+ * row of a clone) and zero on new rows. */
+enum { SNP_ROWS_PARAM = 0, SNP_ROWS_STATE = 1, SNP_ROWS_CENTERS = 2, SNP_ROWS_SCALES = 3 };
+typedef struct {
+  const float *src;
+  float *dst;
+  int32_t width;
+  int32_t kind;
+} snp_row_array;
+
+/* Writes every array's new rows (one launch per array).  centers, scales,
+ * quats: the primitives' current values (for split children); noise: P x 2 x
+ * 3 standard normals (may be NULL if no primitive splits). */
+snp_status snp_densify_apply(int64_t P, const int32_t* action, const uint32_t* offsets, const float* centers,
+                             const float* scales, const float* quats, const float* noise, float split_shrink,
+                             const snp_row_array* arrays, int32_t n_arrays, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,24 @@ class SnpLayout(C.Structure):
                 ("ahat_cache", C.c_size_t), ("ahat_cache_bytes", C.c_size_t)]
 
 
+class SnpAdamGroup(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("lr", C.c_float), ("log_space", C.c_int32)]
+
+
+class SnpDensityControl(C.Structure):
+    _fields_ = [(k, C.c_float) for k in
+                ("densify_threshold", "prune_threshold", "grow_scale", "prune_scale", "split_shrink")]
+
+
+class SnpRowArray(C.Structure):
+    _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("width", C.c_int32), ("kind", C.c_int32)]
+
+
+MAX_ADAM_GROUPS = 32
+PRUNE, KEEP, CLONE, SPLIT = 0, 1, 2, 3
+ROWS_PARAM, ROWS_STATE, ROWS_CENTERS, ROWS_SCALES = 0, 1, 2, 3
+
 _lib = None
 
 
@@ -78,6 +96,11 @@ def lib():
         "snp_read_counters": [VP, lay, P(I64), VP],
         "snp_kernel_timing": [I32],
         "snp_kernel_timing_read": [P(C.c_float), P(C.c_float)],
+        "snp_adam_step": [P(SnpAdamGroup), I32, I64, D, D, D, VP],
+        "snp_scale_regularizer": [I64, VP, C.c_float, VP, VP, VP, lay, VP],
+        "snp_densify_accumulate": [I64, I32, I32, grads, VP, lay, VP, VP, VP],
+        "snp_densify_plan": [I64, VP, VP, VP, P(SnpDensityControl), VP, VP, VP, VP, C.c_size_t, VP],
+        "snp_densify_apply": [I64, VP, VP, VP, VP, VP, VP, C.c_float, P(SnpRowArray), I32, VP],
     }
     for name, args in protos.items():
         f = getattr(L, name)
@@ -85,6 +108,8 @@ def lib():
         f.restype = C.c_int32
     L.snp_status_string.argtypes = [C.c_int32]
     L.snp_status_string.restype = C.c_char_p
+    L.snp_densify_scratch_bytes.argtypes = [I64]
+    L.snp_densify_scratch_bytes.restype = C.c_size_t
     _lib = L
     return L
 
@@ -92,7 +117,9 @@ def lib():
 EXPORTED = ["snp_workspace_layout", "snp_preprocess", "snp_bin", "snp_sort", "snp_render_forward", "snp_loss_l1",
             "snp_render_backward", "snp_step", "snp_graph_create", "snp_graph_launch", "snp_graph_destroy",
             "snp_read_status", "snp_supported_tiles", "snp_status_string", "snp_selftest_wave_sum",
-            "snp_read_counters", "snp_kernel_timing", "snp_kernel_timing_read"]
+            "snp_read_counters", "snp_kernel_timing", "snp_kernel_timing_read", "snp_adam_step",
+            "snp_scale_regularizer", "snp_densify_accumulate", "snp_densify_scratch_bytes", "snp_densify_plan",
+            "snp_densify_apply"]
 
 
 class SnpError(RuntimeError):

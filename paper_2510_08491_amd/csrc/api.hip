@@ -707,6 +707,71 @@ snp_status snp_kernel_timing_read(float* fwd_ms, float* bwd_ms) {
   return SNP_OK;
 }
 
+snp_status snp_adam_step(const snp_adam_group* groups, int32_t n_groups, int64_t step, double beta1, double beta2,
+                         double eps, hipStream_t stream) {
+  if (!groups || n_groups < 0 || n_groups > SNP_MAX_ADAM_GROUPS || step < 1) return SNP_ERR_INVALID;
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps >= 0.0)) return SNP_ERR_INVALID;
+  for (int k = 0; k < n_groups; ++k) {
+    const snp_adam_group& g = groups[k];
+    if (g.n < 0) return SNP_ERR_INVALID;
+    if (g.n > 0 && (!g.param || !g.grad || !g.m || !g.v)) return SNP_ERR_INVALID;
+    if (g.log_space != 0 && g.log_space != 1) return SNP_ERR_INVALID;
+  }
+  SNP_HIP(launch_adam(groups, n_groups, step, beta1, beta2, eps, stream));
+  return SNP_OK;
+}
+
+static bool loss_scratch_ok(void* ws, const snp_layout* layout) {
+  return ws && layout && (reinterpret_cast<uintptr_t>(ws) & 255) == 0 &&
+         layout->loss + loss_scratch_bytes() <= layout->bytes;
+}
+
+snp_status snp_scale_regularizer(int64_t P, const float* scales, float weight, float* grad_scales, double* loss_out,
+                                 void* ws, const snp_layout* layout, hipStream_t stream) {
+  if (P <= 0 || !scales || !loss_out || !std::isfinite(weight) || !loss_scratch_ok(ws, layout)) return SNP_ERR_INVALID;
+  SNP_HIP(launch_scale_reg(P, scales, weight, grad_scales, wsp<double>(ws, layout->loss), loss_out, stream));
+  return SNP_OK;
+}
+
+snp_status snp_densify_accumulate(int64_t P, int32_t N, int32_t V, const snp_grads* grads, void* ws,
+                                  const snp_layout* layout, float* grad_acc, float* visible, hipStream_t stream) {
+  if (P <= 0 || V <= 0 || N <= 0 || !grads || !grads->w1 || !grads->b1 || !grads->w2 || !grads->b2 || !ws ||
+      !layout || !grad_acc || !visible)
+    return SNP_ERR_INVALID;
+  if (layout->tile_counts + sizeof(uint32_t) * (size_t)V * (size_t)P > layout->bytes) return SNP_ERR_INVALID;
+  SNP_HIP(launch_densify_acc(P, N, V, *grads, wsp<uint32_t>(ws, layout->tile_counts), grad_acc, visible, stream));
+  return SNP_OK;
+}
+
+size_t snp_densify_scratch_bytes(int64_t P) { return P > 0 ? densify_scratch_bytes(P) : 0; }
+
+snp_status snp_densify_plan(int64_t P, const float* scales, const float* grad_acc, const float* visible,
+                            const snp_density_control* dc, int32_t* action, uint32_t* offsets, int64_t* new_count,
+                            void* scratch, size_t scratch_bytes, hipStream_t stream) {
+  if (P <= 0 || P > ((int64_t)1 << 31) - 1 || !scales || !grad_acc || !visible || !dc || !action || !offsets ||
+      !new_count || !scratch || scratch_bytes < densify_scratch_bytes(P))
+    return SNP_ERR_INVALID;
+  SNP_HIP(launch_densify_plan(P, scales, grad_acc, visible, *dc, action, offsets, new_count, scratch, stream));
+  return SNP_OK;
+}
+
+snp_status snp_densify_apply(int64_t P, const int32_t* action, const uint32_t* offsets, const float* centers,
+                             const float* scales, const float* quats, const float* noise, float split_shrink,
+                             const snp_row_array* arrays, int32_t n_arrays, hipStream_t stream) {
+  if (P <= 0 || !action || !offsets || !arrays || n_arrays < 0 || !(split_shrink > 0.f)) return SNP_ERR_INVALID;
+  for (int k = 0; k < n_arrays; ++k) {
+    const snp_row_array& a = arrays[k];
+    if (!a.src || !a.dst || a.width <= 0 || a.kind < SNP_ROWS_PARAM || a.kind > SNP_ROWS_SCALES)
+      return SNP_ERR_INVALID;
+    if (a.kind == SNP_ROWS_CENTERS && (a.width != 3 || !centers || !scales || !quats || !noise))
+      return SNP_ERR_INVALID;
+    if (a.kind == SNP_ROWS_SCALES && a.width != 3) return SNP_ERR_INVALID;
+  }
+  for (int k = 0; k < n_arrays; ++k)
+    SNP_HIP(launch_densify_apply(P, action, offsets, centers, scales, quats, noise, split_shrink, arrays[k], stream));
+  return SNP_OK;
+}
+
 snp_status snp_selftest_wave_sum(const float* in, float* out, int32_t waves, hipStream_t stream) {
   if (!in || !out || waves <= 0) return SNP_ERR_INVALID;
   SNP_HIP(launch_wave_sum_selftest(in, out, waves, stream));

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "../../include/snp.h"
 
 namespace snp {
@@ -253,6 +255,20 @@ hipError_t launch_render_bwd(int N, int tw, int th, int nb, bool persist, const 
 hipError_t launch_render_fwd_gauss(int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
                                    hipStream_t st);
 hipError_t launch_wave_sum_selftest(const float* in, float* out, int waves, hipStream_t st);
+// train.hip
+hipError_t launch_adam(const snp_adam_group* groups, int ng, int64_t step, double b1, double b2, double eps,
+                       hipStream_t st);
+hipError_t launch_scale_reg(int64_t P, const float* scales, float weight, float* grad, double* partials,
+                            double* loss_out, hipStream_t st);
+hipError_t launch_densify_acc(int64_t P, int N, int V, const snp_grads& g, const uint32_t* tile_counts, float* acc,
+                              float* cnt, hipStream_t st);
+size_t densify_scratch_bytes(int64_t P);
+hipError_t launch_densify_plan(int64_t P, const float* scales, const float* acc, const float* cnt,
+                               const snp_density_control& dc, int32_t* action, uint32_t* offsets, int64_t* new_count,
+                               void* scratch, hipStream_t st);
+hipError_t launch_densify_apply(int64_t P, const int32_t* action, const uint32_t* offsets, const float* centers,
+                                const float* scales, const float* quats, const float* noise, float shrink,
+                                const snp_row_array& arr, hipStream_t st);
 // loss.hip
 size_t loss_scratch_bytes();
 hipError_t launch_l1(const float* img, const float* tgt, int64_t n, double n_norm, float* grad, double* partials,
