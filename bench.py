@@ -159,6 +159,26 @@ def main(argv=None):
     log(f"[bench] raster kernels: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
     pair_cache = rast.fwd_cache
     cache_gb = rast.layout.ahat_cache_bytes / 2 ** 30
+
+    # ---- Adam over every parameter with these gradients (HBM bound; after the step, not in the metric) --
+    from paper_2510_08491_amd import train as TR
+    opt_params = {k: v.clone() for k, v in params.items() if k in TR.PAPER_LRS}
+    opt = TR.Adam(opt_params)
+    n_elems = sum(v.numel() for v in opt_params.values())
+    opt.step(grads)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        opt.step(grads)
+    e1.record()
+    torch.cuda.synchronize()
+    adam_ms = e0.elapsed_time(e1) / 5
+    adam_bytes = 28 * n_elems  # read param, grad, m, v; write param, m, v (float32)
+    optimizer = {"kernel": "adam (all groups, one launch)", "ms": round(adam_ms, 4), "elements": n_elems,
+                 "bytes": adam_bytes, "GB_per_s": round(adam_bytes / (adam_ms * 1e-3) / 1e9, 1),
+                 "frac_of_hbm_peak": round(adam_bytes / (adam_ms * 1e-3) / 8e12, 4)}
+    log(f"[bench] adam: {optimizer}")
+    del opt, opt_params
     # the per-view rasterizers below need their own workspaces
     del step, rast, images, final_T, dL, grads
     torch.cuda.empty_cache()
@@ -254,6 +274,7 @@ def main(argv=None):
         "raster_bwd_ms": bwd_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "optimizer": optimizer,
         "paper_context": "218.87 FPS forward-only full pipeline, 100k random primitives, RTX 4090 (App. A)",
     }
     print(json.dumps(out))
