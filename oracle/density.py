@@ -14,8 +14,15 @@ Eq. 8: S(t) = [W2 / (omega0 W1 d)] sin(omega0 (t W1 d + W1 o + b1)) + t b2.
        the argument is omega0 (a_k t + c_k).  For x_B = 0 and m = 1 this is
        Eq. 8 verbatim.
 
+Time-conditioned density (the dynamic-scene application): with a time
+xi_t in [0, 1] and a per-primitive temporal weight W_t (N,), the phase of
+unit k gains xi_t W_t,k, added to omega0 (W1 x + b1) unscaled as printed:
+f_sigma(x, xi_t) = W2 cos(omega0 (W1 x + b1) + xi_t W_t) + b2.  It is a
+constant along the ray, so the antiderivative keeps its form with the
+shifted phase.
+
 A primitive is passed as a dict with keys center (3,), scale (3,), w1 (N,3),
-b1 (N,), w2 (N,), b2 (scalar) and omega0.
+b1 (N,), w2 (N,), b2 (scalar) and omega0; optionally wt (N,) and time.
 """
 from __future__ import annotations
 
@@ -33,11 +40,18 @@ def _unpack(prim):
     return c, m, w1, b1, w2, b2, float(prim["omega0"])
 
 
+def time_phase(prim):
+    """xi_t W_t (N,) of the time-conditioned density; zero without W_t."""
+    if prim.get("wt") is None:
+        return 0.0
+    return float(prim.get("time", 0.0)) * np.asarray(prim["wt"], dtype=np.float64)
+
+
 def density(x, prim):
-    """sigma(x) of Eq. 5-6 at points x (..., 3)."""
+    """sigma(x) of Eq. 5-6 at points x (..., 3) (with the time term if any)."""
     c, m, w1, b1, w2, b2, om = _unpack(prim)
     u = (np.asarray(x, dtype=np.float64) - c) / m
-    return np.cos(om * (u @ w1.T + b1)) @ w2 + b2
+    return np.cos(om * (u @ w1.T + b1) + time_phase(prim)) @ w2 + b2
 
 
 def _phase_coefficients(o, d, prim):
@@ -54,7 +68,7 @@ def antiderivative(t, o, d, prim):
     _, _, _, _, w2, b2, om = _unpack(prim)
     a, cc = _phase_coefficients(o, d, prim)
     t = np.asarray(t, dtype=np.float64)[..., None]
-    return np.sum(w2 * np.sin(om * (a * t + cc)) / (om * a), axis=-1) + b2 * t[..., 0]
+    return np.sum(w2 * np.sin(om * (a * t + cc) + time_phase(prim)) / (om * a), axis=-1) + b2 * t[..., 0]
 
 
 def chord_integral_literal(o, d, t_in, t_out, prim):
@@ -91,7 +105,7 @@ def chord_integral(o, d, t_in, t_out, prim):
     L = t_out - t_in
     t_mid = 0.5 * (t_in + t_out)
     p_mid = (o + t_mid[..., None] * d - c) / m      # midpoint in MLP coordinates
-    phase = om * (p_mid @ w1.T + b1)
+    phase = om * (p_mid @ w1.T + b1) + time_phase(prim)
     a = (d @ w1.T) / m
     h = 0.5 * om * a * L[..., None]
     return np.sum(w2 * np.cos(phase) * _sinc(h), axis=-1) * L + b2 * L

@@ -25,7 +25,7 @@ import torch
 from .keys import project_all
 from .render import RenderOptions, depth_order, l1_loss, render_views
 
-PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh")
+PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "wt")
 
 
 def _rotmat_t(q):
@@ -120,14 +120,15 @@ def render_view_torch(params, meta, cam, opts: RenderOptions = RenderOptions(), 
         a = (d @ params["w1"][p].T) / m                      # (..., N)
         c = ((o - xb) @ params["w1"][p].T) / m + params["b1"][p]
         w2 = params["w2"][p]
+        tph = float(meta.get("time", 0.0)) * params["wt"][p] if params.get("wt") is not None else 0.0
         tiny = a.abs() < 1e-9
         a_safe = torch.where(tiny, torch.ones_like(a), a)
 
         def S(t):
-            return (w2 * torch.sin(om * (a_safe * t[..., None] + c)) / (om * a_safe))
+            return (w2 * torch.sin(om * (a_safe * t[..., None] + c) + tph) / (om * a_safe))
 
         lit = S(t_out) - S(t_in)
-        lim = w2 * torch.cos(om * (a * (0.5 * (t_in + t_out))[..., None] + c)) * (t_out - t_in)[..., None]
+        lim = w2 * torch.cos(om * (a * (0.5 * (t_in + t_out))[..., None] + c) + tph) * (t_out - t_in)[..., None]
         integral = torch.where(tiny, lim, lit).sum(-1) + params["b2"][p] * (t_out - t_in)
         alpha = 1.0 - torch.exp(-torch.clamp(integral, min=0.0))
         alpha = torch.clamp(alpha, max=opts.alpha_max)
@@ -149,7 +150,7 @@ def render_view_torch(params, meta, cam, opts: RenderOptions = RenderOptions(), 
 
 def autograd_loss_and_grads(scene, cams, targets, opts: RenderOptions = RenderOptions()):
     """Route 1: loss and d loss / d params (numpy float64 arrays)."""
-    meta = dict(color_mode=scene["color_mode"], omega0=scene["omega0"],
+    meta = dict(color_mode=scene["color_mode"], omega0=scene["omega0"], time=scene.get("time", 0.0),
                 cmlp_width=scene.get("cmlp_width", 0), cmlp_depth=scene.get("cmlp_depth", 0))
     params = {}
     for k in PARAM_KEYS:

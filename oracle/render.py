@@ -51,6 +51,7 @@ def primitive(scene, p, R=None):
     return dict(center=scene["centers"][p], scale=scene["scales"][p],
                 w1=scene["w1"][p], b1=scene["b1"][p], w2=scene["w2"][p],
                 b2=scene["b2"][p], omega0=scene["omega0"],
+                wt=None if scene.get("wt") is None else scene["wt"][p], time=scene.get("time", 0.0),
                 R=quat_to_rotmat(scene["quats"][p]) if R is None else R)
 
 

@@ -24,10 +24,11 @@ biases ~ U(+-1/sqrt(fan_in)), xi ~ N(0,1).
   A   8 cameras 800x800, 100k primitives, N=8, omega0=30, degree-3 SH colour
   G   A's scene as Gaussians (standard deviations a third of A's scales)
 
-Opacity (Gaussians only) ~ U(0.2, 0.9).
+Opacity (Gaussians only) ~ U(0.2, 0.9).  Temporal weights W_t (time-conditioned
+density only) ~ U(-pi, pi); the scene's time xi_t defaults to 0.
 
 Seeds: scene seed 0 (draw order: centres, scales, quats, W1, b1, W2, colours,
-SH coefficients or colour-MLP weights, xi, opacity), camera seed 1, target
+SH coefficients or colour-MLP weights, xi, opacity, W_t), camera seed 1, target
 seed 2.
 """
 from __future__ import annotations
@@ -77,6 +78,7 @@ class SceneConfig:
     scale_hi: float = 0.2
     backward: bool = True
     primitive: int = 0              # 0 neural primitive, 1 Gaussian (scales are standard deviations)
+    temporal: bool = False          # time-conditioned density: a temporal weight W_t per hidden unit
 
 
 CONFIGS = {
@@ -183,9 +185,11 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
     # opacity (used by Gaussians) is drawn last so the other arrays do not
     # depend on it
     opacity = rng.uniform(0.2, 0.9, P)
+    # temporal weights (time-conditioned density), drawn after everything else
+    wt = rng.uniform(-np.pi, np.pi, (P, N)) if cfg.temporal else None
     f32 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
     return dict(P=P, N=N, omega0=cfg.omega0, color_mode=cfg.color_mode, primitive=cfg.primitive,
-                opacity=f32(opacity),
+                opacity=f32(opacity), wt=f32(wt), time=0.0,
                 cmlp_width=cfg.cmlp_width, cmlp_depth=cfg.cmlp_depth,
                 centers=f32(centers), scales=f32(scales), quats=f32(quats),
                 w1=f32(w1), b1=f32(b1), w2=f32(w2), b2=f32(b2),
@@ -195,7 +199,7 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
 def subset_scene(scene: dict, idx) -> dict:
     """Primitives `idx` of a scene (e.g. the first 1000)."""
     out = dict(scene)
-    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity"):
+    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity", "wt"):
         if scene.get(k) is not None:
             out[k] = np.ascontiguousarray(scene[k][idx])
     out["P"] = int(out["centers"].shape[0])
@@ -218,8 +222,8 @@ def make_workload(name: str, n_prims: Optional[int] = None, sizes=None):
 
 
 def custom_scene(P, N, omega0=10.0, color_mode=0, cmlp_width=0, cmlp_depth=0,
-                 seed=SCENE_SEED, center_dist="uniform", scale_lo=0.02, scale_hi=0.2, primitive=0):
+                 seed=SCENE_SEED, center_dist="uniform", scale_lo=0.02, scale_hi=0.2, primitive=0, temporal=False):
     """A scene with the C1-C5 distributions but free sizes."""
     cfg = SceneConfig("custom", P, N, [], color_mode, cmlp_width, cmlp_depth, omega0,
-                      center_dist, scale_lo, scale_hi, primitive=primitive)
+                      center_dist, scale_lo, scale_hi, primitive=primitive, temporal=temporal)
     return make_scene(cfg, seed=seed)
