@@ -120,7 +120,11 @@ typedef struct {
  *             order and sorted by their tile bits only (fewer passes over
  *             the instances, a few more launches); 2 = instances emitted in
  *             primitive order and sorted by the whole key; 0 = 1 when
- *             V * P >= 2^16, else 2. */
+ *             V * P >= 2^16, else 2.
+ *  time       xi_t in [0, 1] of the time-conditioned density (the dynamic-
+ *             scene application): with prims.wt the phase of hidden unit k
+ *             is omega0 (W1_k x + b1_k) + time * wt_k (the time term added
+ *             unscaled, as the paper prints it); ignored without wt. */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -135,6 +139,7 @@ typedef struct {
   int64_t fwd_cache_instances;
   int32_t primitive;
   int32_t bin_order;
+  float time;
 } snp_config;
 
 typedef struct {
@@ -145,6 +150,7 @@ typedef struct {
   const float *xi;     /* color_mode 1, else NULL */
   const float *sh;     /* color_mode 2: P x 16 x 3 (basis (l, m) in order (0,0), (1,-1), (1,0), (1,1), (2,-2) ... (3,3); channel), else NULL */
   const float *opacity; /* primitive 1: P opacities in (0, 1], used as given; else NULL */
+  const float *wt;      /* P x N temporal weights of the time-conditioned density, or NULL */
 } snp_prims;
 
 /* Gradient outputs, same shapes as the parameters.  The backward ADDS into
@@ -152,6 +158,7 @@ typedef struct {
  * are only produced when non-NULL). */
 typedef struct {
   float *centers, *scales, *quats, *w1, *b1, *w2, *b2, *colors, *cmlp, *xi, *sh;
+  float *wt; /* P x N, with prims.wt */
 } snp_grads;
 
 /* Byte offsets of the internal arrays inside a workspace (for inspection by

@@ -24,18 +24,18 @@ class SnpConfig(C.Structure):
                 ("t_eps", C.c_float), ("alpha_min", C.c_float), ("alpha_max", C.c_float),
                 ("bg", C.c_float * 3), ("persistent", C.c_int32), ("bwd_batch", C.c_int32),
                 ("fwd_cache", C.c_int32), ("fwd_cache_instances", C.c_int64), ("primitive", C.c_int32),
-                ("bin_order", C.c_int32)]
+                ("bin_order", C.c_int32), ("time", C.c_float)]
 
 
 class SnpPrims(C.Structure):
     _fields_ = [("P", C.c_int64)] + [(k, C.c_void_p) for k in
                                      ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi",
-                                      "sh", "opacity")]
+                                      "sh", "opacity", "wt")]
 
 
 class SnpGrads(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in
-                ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh")]
+                ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "wt")]
 
 
 class SnpLayout(C.Structure):

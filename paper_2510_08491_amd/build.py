@@ -30,7 +30,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-a
           "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",
           # an occupancy request that the LDS of a large batch already rules out
-          "-Wno-pass-failed"]
+          "-Wno-pass-failed", "-Wshadow"]
 PER_FILE = {
     # float64 key path: one fixed operation order, no contraction
     "preprocess.hip": ["-ffp-contract=off"],

@@ -46,6 +46,7 @@ static snp_status check_cfg(const snp_config* cfg) {
   if (cfg->fwd_cache != 0 && cfg->fwd_cache != 1) return SNP_ERR_INVALID;
   if (cfg->fwd_cache_instances < 0) return SNP_ERR_INVALID;
   if (cfg->bin_order < 0 || cfg->bin_order > 2) return SNP_ERR_INVALID;
+  if (!std::isfinite(cfg->time)) return SNP_ERR_INVALID;
   return SNP_OK;
 }
 
@@ -187,7 +188,8 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
     SNP_HIP(launch_setup_cams(ch, cd, st));
   }
   if (!gaussian(cfg))
-    SNP_HIP(launch_prim_table(cfg->n_hidden, pr->P, cfg->omega0, *pr, wsp<float>(ws, L.table), counters, st));
+    SNP_HIP(launch_prim_table(cfg->n_hidden, pr->P, cfg->omega0, cfg->time, *pr, wsp<float>(ws, L.table), counters,
+                              st));
   ViewArgs va;
   va.P = pr->P;
   va.V = V;
@@ -420,6 +422,7 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
   pa.N = cfg->n_hidden;
   pa.color_mode = cfg->color_mode;
   pa.omega0 = cfg->omega0;
+  pa.time = pr->wt ? cfg->time : 0.f;
   pa.centers = pr->centers;
   pa.scales = pr->scales;
   pa.quats = pr->quats;
@@ -449,6 +452,7 @@ static snp_status zero_grads(const snp_config* cfg, int64_t P, const snp_grads* 
     SNP_HIP(zero_f32(g->xi, (int64_t)kXiDim * P, st));
   }
   if (cfg->color_mode == 2) SNP_HIP(zero_f32(g->sh, (int64_t)kShCoeffs * P, st));
+  SNP_HIP(zero_f32(g->wt, N * P, st));
   return SNP_OK;
 }
 

@@ -18,7 +18,8 @@
 // The density MLP's phase along the chord is linear in p' (Eq. 5-6 with the
 // normalisation of Eq. 5 made explicit); per primitive the table stores
 //   Wt_k = omega0 / (2 pi m) W1_k R diag(s)   (m = max s)
-//   bt_k = omega0 b1_k / (2 pi)  reduced to [-1/2, 1/2]
+//   bt_k = (omega0 b1_k + xi_t W_t,k) / (2 pi)  reduced to [-1/2, 1/2]
+//          (the time term only for the time-conditioned density)
 // so that phase_k / (2 pi) = Wt_k . p' + bt_k (revolutions).
 //
 // Culling, screen bounds and depth keys follow one fixed order of float64
@@ -108,6 +109,7 @@ __global__ void __launch_bounds__(256) prim_table_kernel(int64_t P, float omega0
                                                          const float* __restrict__ quats,
                                                          const float* __restrict__ w1, const float* __restrict__ b1,
                                                          const float* __restrict__ w2, const float* __restrict__ b2,
+                                                         const float* __restrict__ w_time, float time,
                                                          float* __restrict__ table, unsigned long long* counters) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
@@ -129,6 +131,7 @@ __global__ void __launch_bounds__(256) prim_table_kernel(int64_t P, float omega0
       l1 += fabs(wt[j]);
     }
     double bt = (double)omega0 * (double)b1[p * N + k] / 6.283185307179586476925;
+    if (w_time) bt += (double)time * (double)w_time[p * N + k] / 6.283185307179586476925;  // time-conditioned phase
     bt -= rint(bt);
     if (!(l1 < 255.0)) bad = true;
     row[4 * k + 0] = (float)wt[0];
@@ -777,6 +780,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(PreBwdArgs a) {
         gs[j] += K * gwt[j] * wk[ii] * Rp[ii][j];
       }
     if (a.g.b1) a.g.b1[p * N + k] += (float)((double)gt[4 * k + 3] * a.omega0 / twopi);
+    if (a.g.wt) a.g.wt[p * N + k] += (float)((double)gt[4 * k + 3] * a.time / twopi);
     if (a.g.w2) a.g.w2[p * N + k] += (float)((double)gt[4 * N + k] / twopi);
   }
   if (a.g.b2) a.g.b2[p] += gt[5 * N];
@@ -810,14 +814,14 @@ hipError_t launch_setup_cams(const CamChunk& ch, CamDev* out, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_prim_table(int N, int64_t P, float omega0, const snp_prims& pr, float* table,
+hipError_t launch_prim_table(int N, int64_t P, float omega0, float time, const snp_prims& pr, float* table,
                              unsigned long long* counters, hipStream_t st) {
   const dim3 grid((unsigned)((P + 255) / 256)), block(256);
   switch (N) {
-    case 4: hipLaunchKernelGGL(prim_table_kernel<4>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
-    case 8: hipLaunchKernelGGL(prim_table_kernel<8>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
-    case 16: hipLaunchKernelGGL(prim_table_kernel<16>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
-    case 32: hipLaunchKernelGGL(prim_table_kernel<32>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, table, counters); break;
+    case 4: hipLaunchKernelGGL(prim_table_kernel<4>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, pr.wt, time, table, counters); break;
+    case 8: hipLaunchKernelGGL(prim_table_kernel<8>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, pr.wt, time, table, counters); break;
+    case 16: hipLaunchKernelGGL(prim_table_kernel<16>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, pr.wt, time, table, counters); break;
+    case 32: hipLaunchKernelGGL(prim_table_kernel<32>, grid, block, 0, st, P, omega0, pr.scales, pr.quats, pr.w1, pr.b1, pr.w2, pr.b2, pr.wt, time, table, counters); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

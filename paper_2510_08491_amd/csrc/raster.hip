@@ -715,12 +715,12 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
       int it = 0;
       for (int j = 0; j < nb; ++j) {
         // the list is the waves' regions in order: entry e lies in region w
-        // with start[w] <= e < start[w + 1], at slot 64 w + e - start[w]
-        uint32_t start[NW + 1];
-        start[0] = 0;
+        // with wstart[w] <= e < wstart[w + 1], at slot 64 w + e - wstart[w]
+        uint32_t wstart[NW + 1];
+        wstart[0] = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) start[w + 1] = start[w] + s_cnt[j][w];
-        const uint32_t cnt = start[NW];
+        for (int w = 0; w < NW; ++w) wstart[w + 1] = wstart[w] + s_cnt[j][w];
+        const uint32_t cnt = wstart[NW];
         for (uint32_t c0 = 0; c0 < cnt; c0 += 64, ++it) {
           if (it % NW != wave) continue;  // wave-uniform
           const uint32_t e = c0 + lane;
@@ -728,7 +728,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           uint32_t slot = e;
 #pragma unroll
           for (int w = 1; w < NW; ++w)
-            if (e >= start[w]) slot = 64 * w + (e - start[w]);
+            if (e >= wstart[w]) slot = 64 * w + (e - wstart[w]);
           slot = act ? slot : 0;
           const int pix = act ? s_pix[j][slot] : 0;
           float wq = act ? s_wq[j][slot] : 0.f;

@@ -166,7 +166,7 @@ struct ShArgs {
 struct PreBwdArgs {
   int64_t P;
   int32_t V, N, color_mode;
-  float omega0;
+  float omega0, time;
   const float *centers, *scales, *quats, *w1;
   const CamDev* cams;
   const float* records;
@@ -217,7 +217,7 @@ struct RasterArgs {
 
 // preprocess.hip
 hipError_t launch_setup_cams(const CamChunk& ch, CamDev* out, hipStream_t st);
-hipError_t launch_prim_table(int N, int64_t P, float omega0, const snp_prims& pr, float* table,
+hipError_t launch_prim_table(int N, int64_t P, float omega0, float time, const snp_prims& pr, float* table,
                              unsigned long long* counters, hipStream_t st);
 hipError_t launch_preprocess_views(const ViewArgs& a, hipStream_t st);
 hipError_t launch_cmlp_fwd(int width, int depth, CmlpArgs a, hipStream_t st);

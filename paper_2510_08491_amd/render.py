@@ -13,7 +13,7 @@ import torch
 
 from . import _lib as L
 
-PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity")
+PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity", "wt")
 XI_DIM = 8
 
 
@@ -47,6 +47,8 @@ class RenderConfig:
     # 1 depth sort of the (view, primitive) pairs then a tile-bit instance
     # sort; 2 one sort over all key bits; 0 picks by size (same result)
     bin_order: int = 0
+    # xi_t of the time-conditioned density (used with a "wt" parameter)
+    time: float = 0.0
 
     def to_c(self) -> L.SnpConfig:
         c = L.SnpConfig()

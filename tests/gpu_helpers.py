@@ -20,6 +20,7 @@ def config_for(scene, tile=(16, 16, 1), persistent=0, t_eps=1e-4, alpha_min=0.0,
                fwd_cache=1, bin_order=0):
     return snp.RenderConfig(n_hidden=int(scene["N"]), omega0=float(scene["omega0"]),
                             primitive=int(scene.get("primitive", 0)), bin_order=bin_order,
+                            time=float(scene.get("time", 0.0)),
                             color_mode=int(scene["color_mode"]), cmlp_width=int(scene.get("cmlp_width", 0)),
                             cmlp_depth=int(scene.get("cmlp_depth", 0)), tile_w=tile[0], tile_h=tile[1],
                             px_per_lane=tile[2], bwd_batch=tile[3] if len(tile) > 3 else 0, t_eps=t_eps,

@@ -141,3 +141,14 @@ def test_bin_order_option():
     assert big[0].bytes == big[1].bytes
     bad = L.SnpLayout()
     assert lib.snp_workspace_layout(C.byref(_cfg(bin_order=3)), 1000, 2, cams, 5000, C.byref(bad)) == L.SNP_ERR_INVALID
+
+
+def test_time_must_be_finite():
+    L = _lib()
+    lib = L.lib()
+    from paper_2510_08491_amd.render import camera_array
+    cams = camera_array(S.make_cameras([(64, 64)], seed=1))
+    lay = L.SnpLayout()
+    assert lib.snp_workspace_layout(C.byref(_cfg(time=0.5)), 100, 1, cams, 500, C.byref(lay)) == L.SNP_OK
+    assert lib.snp_workspace_layout(C.byref(_cfg(time=float("nan"))), 100, 1, cams, 500,
+                                    C.byref(lay)) == L.SNP_ERR_INVALID

@@ -253,6 +253,20 @@ def test_full_size_sampled(name):
         assert fw["values"][s:e].tolist() == [p for _, p in lst]
 
 
+@pytest.mark.parametrize("fwd_cache", [1, 0])
+def test_time_conditioned_density_image_and_gradients(fwd_cache):
+    """The dynamic-scene density (phase + xi_t W_t): image and every gradient,
+    W_t included, against the oracle."""
+    scene = S.custom_scene(400, 8, seed=151, temporal=True)
+    scene["time"] = 0.63
+    cams = S.make_cameras([(72, 56), (48, 64)], seed=152)
+    targets = S.make_targets(cams, seed=153)
+    cfg = config_for(scene, tile=(16, 16, 1), persistent=1, fwd_cache=fwd_cache)
+    fw = run_forward(scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "wt"])
+
+
 @pytest.mark.parametrize("tile", [(16, 16, 1), (8, 8, 1), (32, 16, 2)])
 def test_both_binning_orders_give_the_oracle_lists(tile):
     """Depth sort of the pairs then a tile-bit sort of the instances, and one
