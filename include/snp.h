@@ -261,6 +261,17 @@ snp_status snp_graph_create(const snp_config* cfg, const snp_prims* prims, int32
 snp_status snp_graph_launch(void* graph, hipStream_t stream);
 snp_status snp_graph_destroy(void* graph);
 
+/* Captures the forward pipeline alone -- preprocess, bin, sort, forward
+ * (snp_preprocess ... snp_render_forward with these arguments, no pair
+ * counting) -- into a HIP graph, for callers that only render (both
+ * primitive kinds).  The instance count is only known on the device: a
+ * replay whose instances exceed the workspace capacity sets the overflow
+ * flag that snp_read_status reports.  Synchronises `stream`; replay with
+ * snp_graph_launch, free with snp_graph_destroy. */
+snp_status snp_graph_create_forward(const snp_config* cfg, const snp_prims* prims, int32_t V,
+                                    const snp_camera* cams, void* ws, const snp_layout* layout, float* images,
+                                    float* final_T, hipStream_t stream, void** graph_out);
+
 /* Synchronises `stream`, then reads the instance count and the flags.
  * Returns SNP_ERR_CAPACITY if the last binning overflowed and SNP_ERR_RANGE if
  * a density-MLP phase exceeded the supported range. */

@@ -88,6 +88,7 @@ def lib():
         "snp_render_backward": [cfg, prims, I32, cams, VP, lay, VP, VP, grads, VP],
         "snp_step": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, D, VP, VP, grads, VP],
         "snp_graph_create": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, D, VP, VP, grads, VP, P(VP)],
+        "snp_graph_create_forward": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, P(VP)],
         "snp_graph_launch": [VP, VP],
         "snp_graph_destroy": [VP],
         "snp_read_status": [VP, lay, P(I64), P(I64), VP],
@@ -115,7 +116,8 @@ def lib():
 
 
 EXPORTED = ["snp_workspace_layout", "snp_preprocess", "snp_bin", "snp_sort", "snp_render_forward", "snp_loss_l1",
-            "snp_render_backward", "snp_step", "snp_graph_create", "snp_graph_launch", "snp_graph_destroy",
+            "snp_render_backward", "snp_step", "snp_graph_create", "snp_graph_create_forward", "snp_graph_launch",
+            "snp_graph_destroy",
             "snp_read_status", "snp_supported_tiles", "snp_status_string", "snp_selftest_wave_sum",
             "snp_read_counters", "snp_kernel_timing", "snp_kernel_timing_read", "snp_adam_step",
             "snp_scale_regularizer", "snp_densify_accumulate", "snp_densify_scratch_bytes", "snp_densify_plan",

@@ -461,6 +461,38 @@ struct GraphHandle {
   hipGraphExec_t exec;
 };
 
+// Captures `body` (a sequence of launches on the stream it is given) into a
+// graph on a private non-blocking stream.
+template <typename F>
+static snp_status capture_graph(hipStream_t stream, void** graph_out, F body) {
+  SNP_HIP(hipStreamSynchronize(stream));
+  hipStream_t cs;
+  SNP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  GraphHandle* h = new GraphHandle();
+  snp_status s = SNP_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    s = SNP_ERR_HIP;
+  } else {
+    s = body(cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (s == SNP_OK && e != hipSuccess) s = SNP_ERR_HIP;
+    if (s == SNP_OK) {
+      h->graph = g;
+      if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) s = SNP_ERR_HIP;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (s != SNP_OK) {
+    delete h;
+    return s;
+  }
+  *graph_out = h;
+  return SNP_OK;
+}
+
 }  // namespace snp
 
 using namespace snp;
@@ -606,32 +638,24 @@ snp_status snp_graph_create(const snp_config* cfg, const snp_prims* prims, int32
   SNP_TRY(check_step_args(cfg, prims, images, final_T, targets, n_norm, loss_out, dL_dimages, grads));
   Plan pl;
   SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
-  SNP_HIP(hipStreamSynchronize(stream));
-  hipStream_t cs;
-  SNP_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  GraphHandle* h = new GraphHandle();
-  snp_status s = SNP_OK;
-  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
-    s = SNP_ERR_HIP;
-  } else {
-    s = do_step(cfg, prims, V, cams, pl, ws, images, final_T, targets, n_norm, loss_out, dL_dimages, grads, cs);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(cs, &g);
-    if (s == SNP_OK && e != hipSuccess) s = SNP_ERR_HIP;
-    if (s == SNP_OK) {
-      h->graph = g;
-      if (hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0) != hipSuccess) s = SNP_ERR_HIP;
-    } else if (g) {
-      (void)hipGraphDestroy(g);
-    }
-  }
-  (void)hipStreamDestroy(cs);
-  if (s != SNP_OK) {
-    delete h;
-    return s;
-  }
-  *graph_out = h;
-  return SNP_OK;
+  return capture_graph(stream, graph_out, [&](hipStream_t cs) {
+    return do_step(cfg, prims, V, cams, pl, ws, images, final_T, targets, n_norm, loss_out, dL_dimages, grads, cs);
+  });
+}
+
+snp_status snp_graph_create_forward(const snp_config* cfg, const snp_prims* prims, int32_t V,
+                                    const snp_camera* cams, void* ws, const snp_layout* layout, float* images,
+                                    float* final_T, hipStream_t stream, void** graph_out) {
+  if (!graph_out || !cfg || !prims || !images || !final_T) return SNP_ERR_INVALID;
+  Plan pl;
+  SNP_TRY(plan_for(cfg, prims->P, V, cams, ws, layout, &pl));
+  SNP_TRY(check_prims(cfg, prims));
+  return capture_graph(stream, graph_out, [&](hipStream_t cs) {
+    SNP_TRY(do_preprocess(cfg, prims, V, cams, pl, ws, cs));
+    SNP_TRY(do_bin(cfg, prims->P, V, pl, ws, cs));
+    SNP_TRY(do_sort(pl, ws, cs));
+    return do_forward(cfg, prims->P, V, pl, ws, images, final_T, 0, cs);
+  });
 }
 
 snp_status snp_graph_launch(void* graph, hipStream_t stream) {

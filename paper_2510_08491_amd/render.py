@@ -332,6 +332,35 @@ class GraphStep:
             self.handle = None
 
 
+class ForwardGraph:
+    """The forward pipeline alone (preprocess, bin, sort, forward) captured
+    once into a HIP graph and replayed: rendering without per-launch host
+    overhead (either primitive kind)."""
+
+    def __init__(self, rast: Rasterizer, params, images=None, final_T=None):
+        self.rast = rast
+        self.params = params
+        if images is None:
+            images, final_T = rast.new_images()
+        self.images, self.final_T = images, final_T
+        self._prims = rast._prims(params)
+        h = C.c_void_p()
+        L.check(L.lib().snp_graph_create_forward(C.byref(rast.ccfg), C.byref(self._prims), rast.V, rast.ccams,
+                                                 rast.ws_ptr, C.byref(rast.layout), _ptr(self.images),
+                                                 _ptr(self.final_T), _stream(), C.byref(h)),
+                "snp_graph_create_forward")
+        self.handle = h
+
+    def launch(self):
+        L.check(L.lib().snp_graph_launch(self.handle, _stream()), "snp_graph_launch")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            L.lib().snp_graph_destroy(h)
+            self.handle = None
+
+
 class SplatRender(torch.autograd.Function):
     """images = render(params); backward gives d loss / d params through the
     hand-written adjoint.  Inputs: the Rasterizer, then the parameter tensors

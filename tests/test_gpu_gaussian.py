@@ -114,3 +114,34 @@ def test_gaussian_full_size_sampled():
         lst = sorted(zip(pr["depth_bits"][ids][sel].tolist(), ids[sel].tolist()))
         s, e = fw["ranges"][g]
         assert fw["values"][s:e].tolist() == [p for _, p in lst]
+
+
+@pytest.mark.parametrize("primitive", [0, 1])
+def test_forward_graph_replays_equal_eager(primitive):
+    """The captured forward pipeline (preprocess, bin, sort, forward) replays
+    to the eager images bit for bit, several times with eager work between
+    replays, and follows an in-place change of the parameters."""
+    import paper_2510_08491_amd as snp
+    scene = S.custom_scene(800, 8, color_mode=2, primitive=primitive, seed=231,
+                           scale_lo=0.005 if primitive else 0.02, scale_hi=0.06 if primitive else 0.2)
+    cams = S.make_cameras([(96, 64), (64, 80), (50, 50)], seed=232)
+    cfg = config_for(scene, tile=(16, 16, 1), persistent=1, alpha_min=1.0 / 255.0 if primitive else 0.0)
+    params = snp.params_to_device(scene)
+    rast = snp.Rasterizer(cfg, scene["P"], cams)
+    rast.prepare(params)
+    img, T = rast.new_images()
+    rast.forward(params, img, T)
+    graph = snp.ForwardGraph(rast, params)
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(graph.images, img) and torch.equal(graph.final_T, T), rep
+        del junk
+    params["centers"].add_(0.01)  # the graph reads the parameters through their pointers
+    rast.prepare(params)
+    rast.forward(params, img, T)
+    graph.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(graph.images, img)
+    rast.read_status()
