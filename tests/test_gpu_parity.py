@@ -411,3 +411,40 @@ def test_central_differences_full_hd_subset():
             assert abs(fd - an) <= tol * abs(an), (key, idx, an, fd)
             checked += 1
     assert checked == 12
+
+
+@pytest.mark.parametrize("primitive", [0, 1])
+def test_degenerate_scenes(primitive):
+    """Every primitive culled (zero instances: background, T = 1, zero
+    gradients); one primitive covering a whole view; 1x1 and 3x17 views
+    batched with a larger one."""
+    import paper_2510_08491_amd as snp
+    cams = S.make_cameras([(48, 40), (1, 1), (3, 17)], seed=161)
+    # all culled: every centre just in front of camera 0, inside its near plane
+    scene = S.custom_scene(20, 8, seed=162, primitive=primitive)
+    Rinv = np.linalg.inv(np.asarray(cams[0].R, np.float64))
+    o = -Rinv @ np.asarray(cams[0].t, np.float64)
+    scene["centers"] = np.tile((o + 0.05 * Rinv[:, 2]).astype(np.float32), (20, 1))
+    scene["scales"] = np.full((20, 3), 0.01, np.float32)
+    cfg = config_for(scene, persistent=1, bg=(0.25, 0.5, 1.0))
+    fw = run_forward(scene, cams[:1], cfg)
+    assert fw["instances"] == 0 and fw["hit_pairs"] == 0
+    assert np.all(fw["T"][0] == 1.0)
+    assert np.allclose(fw["images"][0], np.array([0.25, 0.5, 1.0], np.float32))
+    if primitive == 0:
+        targets = S.make_targets(cams[:1], seed=163)
+        _, g = run_backward(fw, targets)
+        assert all(np.all(v == 0) for v in g.values())
+    # one primitive covering all of camera 0's view, plus tiny views
+    big = S.custom_scene(1, 8, seed=164, primitive=primitive)
+    big["centers"] = np.zeros((1, 3), np.float32)
+    big["scales"] = np.full((1, 3), 0.9 if primitive == 0 else 0.3, np.float32)
+    if primitive == 1:
+        big["opacity"][:] = np.float32(0.8)
+    cfg = config_for(big, tile=(16, 16, 1), persistent=1)
+    fw = run_forward(big, cams, cfg)
+    if primitive == 0:
+        _check_keys(fw, big, cams, cfg)
+        _check_images(fw, big, cams, cfg)
+    assert fw["tile_counts"][0][0] == 3 * 3  # 48x40 in 16x16 tiles, all covered
+    assert fw["instances"] >= 9
