@@ -10,6 +10,14 @@ The workloads here use a constant RGB per primitive, degree-3 spherical
 harmonics, or such a per-primitive colour MLP, evaluated once per
 (primitive, view).
 
+Relighting colour (the relighting application): a constant colour c_dc plus
+the per-primitive colour network of the view direction, the direction from
+the primitive to the view's light and xi, evaluated once per (primitive,
+view) (the paper evaluates it per ray; with a point light at l_v):
+
+    input  = [normalize(x_B - o_v) (3), normalize(l_v - x_B) (3), xi_p (8)]
+    colour = c_dc + sigmoid(MLP(input))
+
 Spherical harmonics: with d = normalize(x_B - o_v) and the 16 real
 orthonormal harmonics Y_k(d) of degrees 0..3 (order (l, m) = (0,0),
 (1,-1), (1,0), (1,1), (2,-2), ..., (3,3); real forms sqrt(2) (-1)^m Re/Im of
@@ -102,6 +110,13 @@ def primitive_colors(scene, cam):
         Y = sh_basis(dirv)                                        # (P, 16)
         sh = np.asarray(scene["sh"], dtype=np.float64)            # (P, 16, 3)
         return np.maximum(0.0, 0.5 + np.einsum("pk,pkc->pc", Y, sh))
-    x = np.concatenate([dirv, np.asarray(scene["xi"], dtype=np.float64)], axis=1)
+    parts = [dirv]
+    if scene["color_mode"] == 3:
+        ld = np.asarray(cam.light, dtype=np.float32).astype(np.float64) - np.asarray(scene["centers"], dtype=np.float64)
+        parts.append(ld / np.linalg.norm(ld, axis=1, keepdims=True))
+    x = np.concatenate(parts + [np.asarray(scene["xi"], dtype=np.float64)], axis=1)
     layers = unpack_cmlp(scene["cmlp"], scene["cmlp_width"], scene["cmlp_depth"], x.shape[1])
-    return mlp_forward(x, layers)
+    c = mlp_forward(x, layers)
+    if scene["color_mode"] == 3:
+        c = c + np.asarray(scene["colors"], dtype=np.float64)
+    return c

@@ -55,14 +55,18 @@ def _sh_basis_t(d):
         c3c * x * (5 * z * z - 1), c3e * z * (x * x - y * y), c3a * x * (x * x - 3 * y * y)], -1)
 
 
-def _colors_t(params, meta, o):
+def _colors_t(params, meta, o, cam=None):
     if meta["color_mode"] == 0:
         return params["colors"]
     dirv = params["centers"] - o
     dirv = dirv / torch.linalg.norm(dirv, dim=1, keepdim=True)
     if meta["color_mode"] == 2:
         return torch.relu(0.5 + torch.einsum("pk,pkc->pc", _sh_basis_t(dirv), params["sh"]))
-    h = torch.cat([dirv, params["xi"]], 1)
+    parts = [dirv]
+    if meta["color_mode"] == 3:
+        ld = torch.tensor(np.asarray(cam.light, dtype=np.float32).astype(np.float64)) - params["centers"]
+        parts.append(ld / torch.linalg.norm(ld, dim=1, keepdim=True))
+    h = torch.cat(parts + [params["xi"]], 1)
     vec = params["cmlp"]
     width, depth = meta["cmlp_width"], meta["cmlp_depth"]
     dims = [h.shape[1]] + [width] * depth + [3]
@@ -75,6 +79,8 @@ def _colors_t(params, meta, o):
         h = torch.einsum("poi,pi->po", Wm, h) + bb
         if li + 1 < len(dims) - 1:
             h = torch.relu(h)
+    if meta["color_mode"] == 3:
+        return params["colors"] + torch.sigmoid(h)
     return torch.sigmoid(h)
 
 
@@ -90,7 +96,7 @@ def render_view_torch(params, meta, cam, opts: RenderOptions = RenderOptions(), 
     o = -Rinv @ tc
     fx, fy, cx, cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
     Rp = _rotmat_t(params["quats"])
-    colors = _colors_t(params, meta, o)
+    colors = _colors_t(params, meta, o, cam)
     om = float(meta["omega0"])
     img = torch.zeros(H, W, 3, dtype=torch.float64)
     T = torch.ones(H, W, dtype=torch.float64)

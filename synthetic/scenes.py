@@ -61,6 +61,7 @@ class Camera:
     cy: float
     R: np.ndarray  # (3,3) float32, world -> camera
     t: np.ndarray  # (3,)  float32
+    light: Optional[np.ndarray] = None  # (3,) float32 world position of the view's light (relighting colour)
 
 
 @dataclasses.dataclass
@@ -69,7 +70,8 @@ class SceneConfig:
     n_prims: int
     n_hidden: int                   # N, width of the density MLP
     cams: List[tuple]               # list of (width, height)
-    color_mode: int                 # 0 constant RGB, 1 colour MLP, 2 spherical harmonics (degree 3)
+    color_mode: int                 # 0 constant RGB, 1 colour MLP, 2 spherical harmonics (degree 3),
+                                    # 3 relighting colour (c_dc + colour MLP of view and light direction)
     cmlp_width: int = 0
     cmlp_depth: int = 0             # number of hidden layers
     omega0: float = 10.0
@@ -133,15 +135,21 @@ def look_at_camera(width: int, height: int, position: np.ndarray,
                   float(np.float32(width / 2.0)), float(np.float32(height / 2.0)), R, t)
 
 
-def make_cameras(sizes, seed: int = CAMERA_SEED, radius: float = 3.0) -> List[Camera]:
+def make_cameras(sizes, seed: int = CAMERA_SEED, radius: float = 3.0, lights: bool = False) -> List[Camera]:
     """One camera per (width, height), each on the sphere of `radius` at a
-    uniformly random direction, looking at the origin."""
+    uniformly random direction, looking at the origin.  With `lights`, each
+    view also gets a point light at a uniformly random direction on the
+    sphere of radius 4 (drawn after all the cameras)."""
     rng = np.random.default_rng(seed)
     cams = []
     for (w, h) in sizes:
         v = rng.standard_normal(3)
         v = radius * v / np.linalg.norm(v)
         cams.append(look_at_camera(w, h, v))
+    if lights:
+        for c in cams:
+            u = rng.standard_normal(3)
+            c.light = (4.0 * u / np.linalg.norm(u)).astype(np.float32)
     return cams
 
 
@@ -173,15 +181,17 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
         sh = np.concatenate([rng.uniform(-1.5, 1.5, (P, 1, 3)), rng.uniform(-0.3, 0.3, (P, 15, 3))], axis=1)
     else:
         layers = []
-        n_in = 3 + XI_DIM
+        n_in = (6 if cfg.color_mode == 3 else 3) + XI_DIM
         dims = [n_in] + [cfg.cmlp_width] * cfg.cmlp_depth + [3]
         for a, b in zip(dims[:-1], dims[1:]):
             bound = 1.0 / math.sqrt(a)
             layers.append(rng.uniform(-bound, bound, (P, b * a)))
             layers.append(rng.uniform(-bound, bound, (P, b)))
         cmlp = np.concatenate(layers, axis=1)
-        assert cmlp.shape[1] == cmlp_param_count(cfg.cmlp_width, cfg.cmlp_depth)
+        assert cmlp.shape[1] == cmlp_param_count(cfg.cmlp_width, cfg.cmlp_depth, n_in)
         xi = rng.standard_normal((P, XI_DIM))
+        if cfg.color_mode == 3:
+            colors = rng.uniform(0.0, 0.5, (P, 3))  # c_dc
     # opacity (used by Gaussians) is drawn last so the other arrays do not
     # depend on it
     opacity = rng.uniform(0.2, 0.9, P)
