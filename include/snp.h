@@ -67,6 +67,7 @@ typedef struct {
   float fx, fy, cx, cy;
   float R[9];
   float t[3];
+  float light[3]; /* world position of the view's point light (colour mode 3 only) */
 } snp_camera;
 
 /* Rendering options.  Readings of what the paper leaves open:
@@ -78,7 +79,11 @@ typedef struct {
  *             per primitive layer after layer, each W (out x in) then b;
  *             2 = spherical harmonics of degree 3 (Sec. 3.1, four bands as
  *             in 3DGS): colour = max(0, 1/2 + sum_k Y_k(d) sh[k]) with the
- *             16 real orthonormal harmonics at d = normalize(x_B - o_v).
+ *             16 real orthonormal harmonics at d = normalize(x_B - o_v);
+ *             3 = relighting colour: colors (c_dc) + the colour network of
+ *             mode 1 with input [normalize(x_B - o_v), normalize(l_v - x_B),
+ *             xi_p] (14 inputs; l_v = the camera's light), per (primitive,
+ *             view).
  *  tile_w, tile_h, px_per_lane: rasterizer tile shape and pixels per thread;
  *             supported shapes are listed by snp_supported_tiles().
  *  z_near     a primitive is culled for a view unless its whole ellipsoid
@@ -145,9 +150,9 @@ typedef struct {
 typedef struct {
   int64_t P;
   const float *centers, *scales, *quats, *w1, *b1, *w2, *b2;
-  const float *colors; /* color_mode 0, else NULL */
-  const float *cmlp;   /* color_mode 1, else NULL */
-  const float *xi;     /* color_mode 1, else NULL */
+  const float *colors; /* color_mode 0, or c_dc of color_mode 3, else NULL */
+  const float *cmlp;   /* color_mode 1 or 3, else NULL */
+  const float *xi;     /* color_mode 1 or 3, else NULL */
   const float *sh;     /* color_mode 2: P x 16 x 3 (basis (l, m) in order (0,0), (1,-1), (1,0), (1,1), (2,-2) ... (3,3); channel), else NULL */
   const float *opacity; /* primitive 1: P opacities in (0, 1], used as given; else NULL */
   const float *wt;      /* P x N temporal weights of the time-conditioned density, or NULL */

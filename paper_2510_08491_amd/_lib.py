@@ -14,7 +14,8 @@ SNP_OK, SNP_ERR_INVALID, SNP_ERR_CAPACITY, SNP_ERR_HIP, SNP_ERR_UNSUPPORTED, SNP
 
 class SnpCamera(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
-                ("cx", C.c_float), ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3)]
+                ("cx", C.c_float), ("cy", C.c_float), ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("light", C.c_float * 3)]
 
 
 class SnpConfig(C.Structure):

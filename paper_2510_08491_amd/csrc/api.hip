@@ -34,8 +34,9 @@ static snp_status check_cfg(const snp_config* cfg) {
     if (!valid_n(cfg->n_hidden)) return SNP_ERR_UNSUPPORTED;
     if (!(cfg->omega0 > 0.f) || !std::isfinite(cfg->omega0)) return SNP_ERR_INVALID;
   }
-  if (cfg->color_mode < 0 || cfg->color_mode > 2) return SNP_ERR_INVALID;
-  if (cfg->color_mode == 1 && !cmlp_supported(cfg->cmlp_width, cfg->cmlp_depth)) return SNP_ERR_UNSUPPORTED;
+  if (cfg->color_mode < 0 || cfg->color_mode > 3) return SNP_ERR_INVALID;
+  if ((cfg->color_mode == 1 || cfg->color_mode == 3) && !cmlp_supported(cfg->cmlp_width, cfg->cmlp_depth))
+    return SNP_ERR_UNSUPPORTED;
   if (!tile_supported(cfg->tile_w, cfg->tile_h, cfg->px_per_lane)) return SNP_ERR_UNSUPPORTED;
   if (!(cfg->z_near > 0.f)) return SNP_ERR_INVALID;
   if (!(cfg->t_eps >= 0.f && cfg->t_eps < 1.f)) return SNP_ERR_INVALID;
@@ -154,6 +155,7 @@ static snp_status check_prims(const snp_config* cfg, const snp_prims* pr) {
   if (cfg->color_mode == 0 && !pr->colors) return SNP_ERR_INVALID;
   if (cfg->color_mode == 1 && (!pr->cmlp || !pr->xi)) return SNP_ERR_INVALID;
   if (cfg->color_mode == 2 && !pr->sh) return SNP_ERR_INVALID;
+  if (cfg->color_mode == 3 && (!pr->cmlp || !pr->xi || !pr->colors)) return SNP_ERR_INVALID;
   return SNP_OK;
 }
 
@@ -208,14 +210,16 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
   va.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
   va.disc_coef = wsp<double>(ws, L.disc_coef);
   SNP_HIP(launch_preprocess_views(va, st));
-  if (cfg->color_mode == 1) {
+  if (cfg->color_mode == 1 || cfg->color_mode == 3) {
     CmlpArgs ca;
     std::memset(&ca, 0, sizeof(ca));
     ca.P = pr->P;
     ca.V = V;
+    ca.relight = cfg->color_mode == 3;
     ca.centers = pr->centers;
     ca.xi = pr->xi;
     ca.cmlp = pr->cmlp;
+    ca.colors = pr->colors;
     ca.cams = cd;
     ca.tile_counts = va.tile_counts;
     ca.records = va.records;
@@ -384,14 +388,17 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
   const int nb = cfg->bwd_batch ? cfg->bwd_batch : bwd_batch_default(cfg->tile_w, cfg->tile_h);
   SNP_HIP(launch_render_bwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, nb, cfg->persistent != 0, a, st));
   timer_mark(3, st);
-  if (cfg->color_mode == 1) {
+  if (cfg->color_mode == 1 || cfg->color_mode == 3) {
     CmlpArgs ca;
     std::memset(&ca, 0, sizeof(ca));
     ca.P = P;
     ca.V = V;
+    ca.relight = cfg->color_mode == 3;
     ca.centers = pr->centers;
     ca.xi = pr->xi;
     ca.cmlp = pr->cmlp;
+    ca.colors = pr->colors;
+    ca.g_centers = cfg->color_mode == 3 ? g->centers : nullptr;
     ca.cams = a.cams;
     ca.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
     ca.records = wsp<float>(ws, L.records);
@@ -446,9 +453,10 @@ static snp_status zero_grads(const snp_config* cfg, int64_t P, const snp_grads* 
   SNP_HIP(zero_f32(g->b1, N * P, st));
   SNP_HIP(zero_f32(g->w2, N * P, st));
   SNP_HIP(zero_f32(g->b2, P, st));
-  if (cfg->color_mode == 0) SNP_HIP(zero_f32(g->colors, 3 * P, st));
-  if (cfg->color_mode == 1) {
-    SNP_HIP(zero_f32(g->cmlp, (int64_t)cmlp_param_count(cfg->cmlp_width, cfg->cmlp_depth) * P, st));
+  if (cfg->color_mode == 0 || cfg->color_mode == 3) SNP_HIP(zero_f32(g->colors, 3 * P, st));
+  if (cfg->color_mode == 1 || cfg->color_mode == 3) {
+    SNP_HIP(zero_f32(g->cmlp, (int64_t)cmlp_param_count(cfg->cmlp_width, cfg->cmlp_depth, cfg->color_mode == 3) * P,
+                     st));
     SNP_HIP(zero_f32(g->xi, (int64_t)kXiDim * P, st));
   }
   if (cfg->color_mode == 2) SNP_HIP(zero_f32(g->sh, (int64_t)kShCoeffs * P, st));

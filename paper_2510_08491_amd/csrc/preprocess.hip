@@ -46,6 +46,7 @@ __global__ void setup_cams_kernel(CamChunk ch, CamDev* out) {
   d.ntx = (c.width + ch.tile_w - 1) / ch.tile_w;
   d.nty = (c.height + ch.tile_h - 1) / ch.tile_h;
   d.tile_base = ch.tile_base[i];
+  for (int k = 0; k < 3; ++k) d.light[k] = c.light[k];
   d.pad0 = 0;
   d.pix_base = ch.pix_base[i];
   d.fx = c.fx;
@@ -396,11 +397,26 @@ __global__ void __launch_bounds__(256) preprocess_views_kernel(ViewArgs a) {
 // hit the same addresses.
 // ---------------------------------------------------------------------------
 
-template <int WIDTH, int DEPTH>
+// IN = 11: [view direction, xi] (colour mode 1); IN = 14: [view direction,
+// light direction, xi] (relighting colour, mode 3)
+template <int WIDTH, int DEPTH, int IN>
 struct CmlpShape {
-  static constexpr int K = kCmlpIn * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH) + WIDTH * 3 + 3;
+  static constexpr int K = IN * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH) + WIDTH * 3 + 3;
 };
 
+// light direction normalize(l_v - x_B) of the relighting colour
+__device__ __forceinline__ void light_dir(const CmlpArgs& a, int64_t p, const CamDev& cam, float* ld, float* inv_len) {
+  const float dx = cam.light[0] - a.centers[3 * p];
+  const float dy = cam.light[1] - a.centers[3 * p + 1];
+  const float dz = cam.light[2] - a.centers[3 * p + 2];
+  const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+  ld[0] = dx * il;
+  ld[1] = dy * il;
+  ld[2] = dz * il;
+  *inv_len = il;
+}
+
+template <int IN>
 __device__ __forceinline__ void cmlp_input(const CmlpArgs& a, int64_t p, int v, float* x, float* rawdir,
                                            float* inv_len) {
   const CamDev& cam = a.cams[v];
@@ -415,34 +431,38 @@ __device__ __forceinline__ void cmlp_input(const CmlpArgs& a, int64_t p, int v, 
   x[0] = rawdir[0];
   x[1] = rawdir[1];
   x[2] = rawdir[2];
+  if constexpr (IN == kCmlpIn + 3) {
+    float il2;
+    light_dir(a, p, cam, x + 3, &il2);
+  }
 #pragma unroll
-  for (int k = 0; k < kXiDim; ++k) x[3 + k] = a.xi[p * kXiDim + k];
+  for (int k = 0; k < kXiDim; ++k) x[IN - kXiDim + k] = a.xi[p * kXiDim + k];
 }
 
-template <int WIDTH, int DEPTH>
+template <int WIDTH, int DEPTH, int IN>
 __global__ void __launch_bounds__(256) cmlp_fwd_kernel(CmlpArgs a) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t p = gid / a.GS;
   const int lane_v = (int)(gid - p * a.GS);
   if (p >= a.P) return;
-  constexpr int K = CmlpShape<WIDTH, DEPTH>::K;
+  constexpr int K = CmlpShape<WIDTH, DEPTH, IN>::K;
   const float* Wp = a.cmlp + p * K;
   for (int v = lane_v; v < a.V; v += a.GS) {
     const int64_t i = (int64_t)v * a.P + p;
     if (a.tile_counts[i] == 0) continue;
-    float x[kCmlpIn], dir[3], il;
-    cmlp_input(a, p, v, x, dir, &il);
+    float x[IN], dir[3], il;
+    cmlp_input<IN>(a, p, v, x, dir, &il);
     float h[WIDTH], g[WIDTH];
     int off = 0;
     // layer 0
 #pragma unroll
     for (int o = 0; o < WIDTH; ++o) {
-      float acc = Wp[off + kCmlpIn * WIDTH + o];
+      float acc = Wp[off + IN * WIDTH + o];
 #pragma unroll
-      for (int k = 0; k < kCmlpIn; ++k) acc = __builtin_fmaf(Wp[off + o * kCmlpIn + k], x[k], acc);
+      for (int k = 0; k < IN; ++k) acc = __builtin_fmaf(Wp[off + o * IN + k], x[k], acc);
       h[o] = fmaxf(acc, 0.f);
     }
-    off += kCmlpIn * WIDTH + WIDTH;
+    off += IN * WIDTH + WIDTH;
 #pragma unroll
     for (int l = 1; l < DEPTH; ++l) {
 #pragma unroll
@@ -463,6 +483,7 @@ __global__ void __launch_bounds__(256) cmlp_fwd_kernel(CmlpArgs a) {
 #pragma unroll
       for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], h[k], acc);
       out[o] = 1.0f / (1.0f + expf(-acc));
+      if (IN == 14) out[o] += a.colors[3 * p + o];  // relighting: c_dc + network
     }
     float* rec = a.records + i * kRecFloats;
     rec[11] = out[0];
@@ -480,10 +501,10 @@ __global__ void __launch_bounds__(256) cmlp_fwd_kernel(CmlpArgs a) {
 // and summed over the views from LDS, so no cross-lane reduction or atomic
 // is needed; the sums are added to the gradient in HBM with coalesced
 // read-add-writes.  Views culled for the primitive carry zero deltas.
-template <int WIDTH, int DEPTH>
+template <int WIDTH, int DEPTH, int IN>
 __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
-  constexpr int K = CmlpShape<WIDTH, DEPTH>::K;
-  constexpr int IN = kCmlpIn;
+  constexpr int K = CmlpShape<WIDTH, DEPTH, IN>::K;
+  constexpr int XI0 = IN - kXiDim;  // first xi input
   constexpr int VC = 16;            // views per chunk
   constexpr int QW = WIDTH / 4;     // units per lane and layer
   constexpr int LAST = IN * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH);  // output layer offset
@@ -498,6 +519,7 @@ __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
   const float* Wg = a.cmlp + p * K;
   for (int i = lane; i < K; i += 64) sW[i] = Wg[i];
   float xi_acc = 0.f;  // lanes 0..7: sum over views of d loss / d xi[lane]
+  float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;  // relighting: d loss / d x_B through the light direction
   __syncthreads();
   for (int v0 = 0; v0 < a.V; v0 += VC) {
     const int v = v0 + vi;
@@ -508,7 +530,7 @@ __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
       float x[IN], dir[3], il = 0.f;
 #pragma unroll
       for (int k = 0; k < IN; ++k) x[k] = 0.f;
-      if (act) cmlp_input(a, p, v, x, dir, &il);
+      if (act) cmlp_input<IN>(a, p, v, x, dir, &il);
 #pragma unroll
       for (int k = 0; k < IN; ++k) sX[vi][k] = x[k];
     }
@@ -601,10 +623,20 @@ __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
       gv[21] = sGx[vi][0];
       gv[22] = sGx[vi][1];
       gv[23] = sGx[vi][2];
+      if constexpr (IN == 14) {
+        // ld = normalize(l - x_B): d loss / d x_B = -(g - ld (ld . g)) / |l - x_B|
+        float ld[3], il2;
+        light_dir(a, p, a.cams[v], ld, &il2);
+        const float g0 = sGx[vi][3], g1 = sGx[vi][4], g2 = sGx[vi][5];
+        const float dd = ld[0] * g0 + ld[1] * g1 + ld[2] * g2;
+        gc0 -= (g0 - ld[0] * dd) * il2;
+        gc1 -= (g1 - ld[1] * dd) * il2;
+        gc2 -= (g2 - ld[2] * dd) * il2;
+      }
     }
     if (lane < kXiDim) {
 #pragma unroll
-      for (int w = 0; w < VC; ++w) xi_acc += sGx[w][3 + lane];
+      for (int w = 0; w < VC; ++w) xi_acc += sGx[w][XI0 + lane];
     }
     // ---- weight gradients: entries idx = lane, lane + 64, ..., summed over
     // the chunk's views and added to the gradient in HBM
@@ -652,6 +684,18 @@ __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
     __syncthreads();
   }
   if (a.g_xi && lane < kXiDim) a.g_xi[p * kXiDim + lane] += xi_acc;
+  if (IN == 14 && a.g_centers) {
+    // the light-direction terms of the 16 view lanes (lanes 0..15, q = 0)
+    gc0 += __shfl_xor(gc0, 1); gc1 += __shfl_xor(gc1, 1); gc2 += __shfl_xor(gc2, 1);
+    gc0 += __shfl_xor(gc0, 2); gc1 += __shfl_xor(gc1, 2); gc2 += __shfl_xor(gc2, 2);
+    gc0 += __shfl_xor(gc0, 4); gc1 += __shfl_xor(gc1, 4); gc2 += __shfl_xor(gc2, 4);
+    gc0 += __shfl_xor(gc0, 8); gc1 += __shfl_xor(gc1, 8); gc2 += __shfl_xor(gc2, 8);
+    if (lane == 0) {
+      a.g_centers[3 * p] += gc0;
+      a.g_centers[3 * p + 1] += gc1;
+      a.g_centers[3 * p + 2] += gc2;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -730,12 +774,13 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(PreBwdArgs a) {
         gU[r][c] += g_op[r] * om[c];
       }
     for (int c = 0; c < 3; ++c) gxb[c] -= U[0][c] * g_op[0] + U[1][c] * g_op[1] + U[2][c] * g_op[2];
-    // colour
-    if (a.color_mode == 0) {
+    // colour (the constant colour, or the relighting colour's c_dc)
+    if (a.color_mode == 0 || a.color_mode == 3) {
       gcol[0] += gv[18];
       gcol[1] += gv[19];
       gcol[2] += gv[20];
-    } else {
+    }
+    if (a.color_mode != 0) {
       // dir = normalize(x_B - o): d dir / d x_B = (I - dir dir^T) / |x_B - o|
       const double dvec[3] = {-om[0], -om[1], -om[2]};
       const double len = sqrt(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
@@ -802,7 +847,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(PreBwdArgs a) {
     for (int k = 0; k < 3; ++k) a.g.scales[3 * p + k] += (float)gs[k];
   if (a.g.centers)
     for (int k = 0; k < 3; ++k) a.g.centers[3 * p + k] += (float)gxb[k];
-  if (a.color_mode == 0 && a.g.colors)
+  if ((a.color_mode == 0 || a.color_mode == 3) && a.g.colors)
     for (int k = 0; k < 3; ++k) a.g.colors[3 * p + k] += (float)gcol[k];
 }
 
@@ -839,15 +884,20 @@ static int group_size(int V) {
   return gs;
 }
 
-#define SNP_CMLP_DISPATCH(KERNEL, width, depth, grid, block, st, a)                                  \
-  do {                                                                                                \
-    if (width == 16 && depth == 1) hipLaunchKernelGGL((KERNEL<16, 1>), grid, block, 0, st, a);        \
-    else if (width == 16 && depth == 2) hipLaunchKernelGGL((KERNEL<16, 2>), grid, block, 0, st, a);   \
-    else if (width == 16 && depth == 3) hipLaunchKernelGGL((KERNEL<16, 3>), grid, block, 0, st, a);   \
-    else if (width == 32 && depth == 1) hipLaunchKernelGGL((KERNEL<32, 1>), grid, block, 0, st, a);   \
-    else if (width == 32 && depth == 2) hipLaunchKernelGGL((KERNEL<32, 2>), grid, block, 0, st, a);   \
-    else if (width == 32 && depth == 3) hipLaunchKernelGGL((KERNEL<32, 3>), grid, block, 0, st, a);   \
-    else return hipErrorInvalidValue;                                                                 \
+#define SNP_CMLP_DISPATCH_IN(KERNEL, IN, width, depth, grid, block, st, a)                                \
+  do {                                                                                                     \
+    if (width == 16 && depth == 1) hipLaunchKernelGGL((KERNEL<16, 1, IN>), grid, block, 0, st, a);         \
+    else if (width == 16 && depth == 2) hipLaunchKernelGGL((KERNEL<16, 2, IN>), grid, block, 0, st, a);    \
+    else if (width == 16 && depth == 3) hipLaunchKernelGGL((KERNEL<16, 3, IN>), grid, block, 0, st, a);    \
+    else if (width == 32 && depth == 1) hipLaunchKernelGGL((KERNEL<32, 1, IN>), grid, block, 0, st, a);    \
+    else if (width == 32 && depth == 2) hipLaunchKernelGGL((KERNEL<32, 2, IN>), grid, block, 0, st, a);    \
+    else if (width == 32 && depth == 3) hipLaunchKernelGGL((KERNEL<32, 3, IN>), grid, block, 0, st, a);    \
+    else return hipErrorInvalidValue;                                                                      \
+  } while (0)
+#define SNP_CMLP_DISPATCH(KERNEL, width, depth, grid, block, st, a)                 \
+  do {                                                                               \
+    if (a.relight) SNP_CMLP_DISPATCH_IN(KERNEL, 14, width, depth, grid, block, st, a); \
+    else SNP_CMLP_DISPATCH_IN(KERNEL, 11, width, depth, grid, block, st, a);           \
   } while (0)
 
 hipError_t launch_cmlp_fwd(int width, int depth, CmlpArgs a, hipStream_t st) {
@@ -869,8 +919,9 @@ bool cmlp_supported(int width, int depth) {
   return (width == 16 || width == 32) && depth >= 1 && depth <= 3;
 }
 
-int cmlp_param_count(int width, int depth) {
-  return kCmlpIn * width + width + (depth - 1) * (width * width + width) + width * 3 + 3;
+int cmlp_param_count(int width, int depth, bool relight) {
+  const int in = kCmlpIn + (relight ? 3 : 0);
+  return in * width + width + (depth - 1) * (width * width + width) + width * 3 + 3;
 }
 
 hipError_t launch_preprocess_bwd(const PreBwdArgs& a, hipStream_t st) {

@@ -32,6 +32,7 @@ struct CamDev {
   float t[3];
   float Rinv_f[9];    // camera -> world, float copy for per-pixel directions
   float o_f[3];
+  float light[3];     // the view's point light (relighting colour)
   double Rinv[9];     // camera -> world (exact inverse of R, float64)
   double o[3];        // camera centre -R^-1 t
 };
@@ -143,13 +144,15 @@ struct ViewArgs {
 struct CmlpArgs {
   int64_t P;
   int32_t V, GS;
-  const float *centers, *xi, *cmlp;
+  int32_t relight;  // 1: relighting colour (light direction input, plus c_dc = colors)
+  const float *centers, *xi, *cmlp, *colors;
   const CamDev* cams;
   const uint32_t* tile_counts;
   float* records;
   float* gview;
   float* g_cmlp;
   float* g_xi;
+  float* g_centers;  // relighting: the light direction's chain to the centres
 };
 
 struct ShArgs {
@@ -226,7 +229,7 @@ hipError_t launch_cmlp_bwd(int width, int depth, CmlpArgs a, hipStream_t st);
 hipError_t launch_sh_fwd(const ShArgs& a, hipStream_t st);
 hipError_t launch_sh_bwd(const ShArgs& a, hipStream_t st);
 bool cmlp_supported(int width, int depth);
-int cmlp_param_count(int width, int depth);
+int cmlp_param_count(int width, int depth, bool relight);
 hipError_t launch_preprocess_bwd(const PreBwdArgs& a, hipStream_t st);
 // binning.hip
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);

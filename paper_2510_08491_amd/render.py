@@ -62,10 +62,13 @@ class RenderConfig:
         return c
 
 
-def cmlp_param_count(width: int, depth: int) -> int:
+def cmlp_param_count(width: int, depth: int, relight: bool = False) -> int:
+    """Colour-network parameters per primitive: inputs view direction and
+    xi (11), plus the light direction (14) for the relighting colour."""
     if depth <= 0:
         return 0
-    return 11 * width + width + (depth - 1) * (width * width + width) + 3 * width + 3
+    n_in = 14 if relight else 11
+    return n_in * width + width + (depth - 1) * (width * width + width) + 3 * width + 3
 
 
 def camera_array(cams) -> "C.Array":
@@ -78,6 +81,8 @@ def camera_array(cams) -> "C.Array":
         a.fx, a.fy, a.cx, a.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
         a.R = (C.c_float * 9)(*np.asarray(c.R, np.float32).ravel().tolist())
         a.t = (C.c_float * 3)(*np.asarray(c.t, np.float32).ravel().tolist())
+        light = getattr(c, "light", None)
+        a.light = (C.c_float * 3)(*(np.zeros(3) if light is None else np.asarray(light, np.float32)).ravel().tolist())
     return arr
 
 

@@ -68,7 +68,12 @@ def test_layout_and_validation():
     assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
     assert lib.snp_workspace_layout(C.byref(_cfg(tile_w=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
     assert lib.snp_workspace_layout(C.byref(_cfg(alpha_max=1.0)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
-    assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=3)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
+    assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=4)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
+    # the relighting colour needs a supported colour-network shape
+    assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=3)), 10, 2, cams, 100,
+                                    C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
+    assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=3, cmlp_width=16, cmlp_depth=2)), 10, 2, cams, 100,
+                                    C.byref(lay)) == L.SNP_OK
     assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=2)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_OK
     assert lib.snp_workspace_layout(C.byref(_cfg()), 0, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
     assert lib.snp_workspace_layout(C.byref(_cfg()), 10, 0, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID

@@ -145,3 +145,11 @@ def test_forward_graph_replays_equal_eager(primitive):
     torch.cuda.synchronize()
     assert torch.equal(graph.images, img)
     rast.read_status()
+
+
+def test_gaussian_relighting_colour():
+    scene = S.custom_scene(400, 8, color_mode=3, cmlp_width=16, cmlp_depth=2, primitive=1, scale_lo=0.01,
+                           scale_hi=0.08, seed=241)
+    cams = S.make_cameras([(64, 48), (48, 64)], seed=242, lights=True)
+    cfg = config_for(scene, tile=(16, 16, 1), alpha_min=1.0 / 255.0)
+    _check(run_forward(scene, cams, cfg), scene, cams, cfg)

@@ -448,3 +448,18 @@ def test_degenerate_scenes(primitive):
         _check_images(fw, big, cams, cfg)
     assert fw["tile_counts"][0][0] == 3 * 3  # 48x40 in 16x16 tiles, all covered
     assert fw["instances"] >= 9
+
+
+@pytest.mark.parametrize("width,depth,fwd_cache", [(16, 2, 1), (32, 1, 0)])
+def test_relighting_colour_image_and_gradients(width, depth, fwd_cache):
+    """Colour mode 3 (c_dc + colour network of view and light direction and
+    xi, one point light per view): image and every gradient, the light
+    direction's chain to the centres included, against the oracle."""
+    scene = S.custom_scene(300, 8, color_mode=3, cmlp_width=width, cmlp_depth=depth, seed=171)
+    cams = S.make_cameras([(64, 56), (56, 64), (48, 48)], seed=172, lights=True)
+    targets = S.make_targets(cams, seed=173)
+    cfg = config_for(scene, tile=(16, 16, 1), persistent=1, fwd_cache=fwd_cache)
+    fw = run_forward(scene, cams, cfg)
+    _check_images(fw, scene, cams, cfg)
+    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp",
+                                             "xi"])
