@@ -16,8 +16,9 @@
  *    pointers read during the call only.
  *  - Every call only enqueues work on `stream` (a hipStream_t; 0 = null
  *    stream).  No call allocates memory, synchronises, or keeps a pointer
- *    after it returns -- except snp_read_status (synchronises the stream) and
- *    the snp_graph_* calls (documented there).
+ *    after it returns -- except snp_read_status and snp_read_counters
+ *    (synchronise the stream), snp_kernel_timing_read (waits for its events)
+ *    and the snp_graph_* calls (documented there).
  *  - Arguments are validated on the host before anything is enqueued; an
  *    invalid call returns SNP_ERR_INVALID and enqueues nothing.
  *  - Sizes that are only known on the device (the number of tile instances)
@@ -28,8 +29,11 @@
  *    H_v x W_v x 3 block (RGB); transmittances likewise as H_v x W_v.
  *  - Primitive arrays (P primitives, N hidden units): centers P x 3,
  *    scales P x 3 (semi-axis lengths, > 0), quats P x 4 (w, x, y, z; need not
- *    be normalised), w1 P x N x 3, b1 P x N, w2 P x N, b2 P, and either
- *    colors P x 3 (color_mode 0) or cmlp P x K with xi P x 8 (color_mode 1).
+ *    be normalised), w1 P x N x 3, b1 P x N, w2 P x N, b2 P, optionally wt
+ *    P x N (time-conditioned density), and the colour: colors P x 3
+ *    (color_mode 0), cmlp P x K with xi P x 8 (color_mode 1; K from 11
+ *    network inputs), sh P x 16 x 3 (color_mode 2), or colors (c_dc), cmlp
+ *    (K from 14 inputs) and xi (color_mode 3).
  *  - A second primitive kind (snp_config.primitive = 1) renders 3D Gaussians
  *    through the same tiling, sorting and blending, as the 3DGS splatting
  *    kernel the paper measures against (App. A, integration-cost table):

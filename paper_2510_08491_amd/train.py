@@ -100,6 +100,8 @@ def densify(params: Dict[str, torch.Tensor], state: Dict[str, torch.Tensor], acc
     kinds = {"centers": L.ROWS_CENTERS, "scales": L.ROWS_SCALES}
     new_p = {k: torch.empty((n_new,) + tuple(v.shape[1:]), dtype=v.dtype, device=dev) for k, v in params.items()}
     new_s = {k: torch.empty((n_new,) + tuple(v.shape[1:]), dtype=v.dtype, device=dev) for k, v in state.items()}
+    if n_new == 0:  # everything pruned: no rows to carry over
+        return new_p, new_s, action
     items = [(params[k], new_p[k], kinds.get(k, L.ROWS_PARAM)) for k in params] + \
             [(state[k], new_s[k], L.ROWS_STATE) for k in state]
     arr = (L.SnpRowArray * len(items))()

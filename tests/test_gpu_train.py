@@ -140,3 +140,21 @@ def test_densify_plan_and_apply_against_oracle():
             assert np.array_equal(got, p_ref[k]), k
     for k in state:
         assert np.array_equal(new_s[k].cpu().numpy().astype(np.float64), s_ref[k]), k
+
+
+def test_densify_everything_pruned_and_empty_adam_group():
+    """All primitives pruned: zero rows, no kernel writes; an empty tensor in
+    an Adam step is allowed and the others still update."""
+    P = 64
+    scales = np.full((P, 3), 0.9, np.float32)  # above the pruning scale
+    params = {"centers": np.zeros((P, 3), np.float32), "scales": scales,
+              "quats": np.tile(np.array([1, 0, 0, 0], np.float32), (P, 1))}
+    new_p, new_s, act = TR.densify({k: _dev(v) for k, v in params.items()}, {}, _dev(np.ones(P)),
+                                   _dev(np.ones(P)), _dev(np.zeros((P, 2, 3))))
+    torch.cuda.synchronize()
+    assert np.all(act.cpu().numpy() == T.PRUNE) and new_p["centers"].shape == (0, 3)
+    dev = {"centers": _dev(np.ones((5, 3))), "b2": torch.zeros(0, device="cuda")}
+    opt = TR.Adam(dev)
+    opt.step({"centers": _dev(np.ones((5, 3))), "b2": torch.zeros(0, device="cuda")})
+    torch.cuda.synchronize()
+    assert np.allclose(dev["centers"].cpu().numpy(), 1.0 - TR.PAPER_LRS["centers"], rtol=0, atol=1e-7)
