@@ -189,28 +189,67 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* counts, i
   return hipGetLastError();
 }
 
-// thread j emits the instances of the j-th (view, primitive) pair, in depth
-// order (or primitive order when order is null), at offsets[j]
+// Instances of the pairs j (in depth order, or primitive order when order is
+// null) at offsets[j] on.  A wave takes 64 consecutive pairs, whose
+// instances are one contiguous output range, and writes that range 64
+// instances at a time (lane l writes position base + l), so the writes are
+// coalesced: each lane finds its pair by a binary search over the wave's
+// offsets in LDS and its tile from the pair's tile rectangle.
 __global__ void __launch_bounds__(256) emit_kernel(EmitArgs a) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= a.P * a.V) return;
-  const int64_t i = a.order ? (int64_t)a.order[j] : j;
-  const uint32_t cnt = a.tile_counts[i];
-  if (cnt == 0) return;
-  const int v = (int)(i / a.P);
-  const uint32_t p = (uint32_t)(i - (int64_t)v * a.P);
-  const CamDev& cam = a.cams[v];
-  const int tx0 = a.rects[4 * i] / cam.tile_w, tx1 = a.rects[4 * i + 1] / cam.tile_w;
-  const int ty0 = a.rects[4 * i + 2] / cam.tile_h, ty1 = a.rects[4 * i + 3] / cam.tile_h;
-  const unsigned long long dbits = a.depth_bits[i];
-  int64_t pos = a.offsets[j];
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx, ++pos) {
-      if (pos >= a.capacity) return;
-      const unsigned long long tile = (unsigned long long)(cam.tile_base + ty * cam.ntx + tx);
-      a.keys[pos] = (tile << 31) | dbits;
-      a.values[pos] = p;
+  constexpr int NW = 4;
+  __shared__ uint32_t s_off[NW][65];   // first instance of each pair, relative to the wave's base; [64] = end
+  __shared__ int32_t s_tx0[NW][64], s_nx[NW][64], s_ty0[NW][64], s_v[NW][64];
+  __shared__ uint32_t s_p[NW][64], s_d[NW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t n = a.P * a.V;
+  const int64_t j0 = ((int64_t)blockIdx.x * NW + w) * 64;
+  const bool wave_has_pairs = j0 < n;  // wave-uniform; every wave still reaches the barrier
+  const int64_t j = j0 + lane;
+  uint32_t cnt = 0;
+  if (j < n) {
+    const int64_t i = a.order ? (int64_t)a.order[j] : j;
+    cnt = a.tile_counts[i];
+    const int v = (int)(i / a.P);
+    const CamDev& cam = a.cams[v];
+    const int tx0 = a.rects[4 * i] / cam.tile_w, tx1 = a.rects[4 * i + 1] / cam.tile_w;
+    s_tx0[w][lane] = tx0;
+    s_nx[w][lane] = tx1 - tx0 + 1;
+    s_ty0[w][lane] = a.rects[4 * i + 2] / cam.tile_h;
+    s_v[w][lane] = v;
+    s_p[w][lane] = (uint32_t)(i - (int64_t)v * a.P);
+    s_d[w][lane] = a.depth_bits[i];
+  }
+  // the wave's offsets are the exclusive scan values of its pairs (uint32
+  // arithmetic: the differences stay exact if the scan wrapped)
+  const uint32_t base = wave_has_pairs ? a.offsets[j0] : 0u;
+  const int last = wave_has_pairs ? (int)min((int64_t)63, n - 1 - j0) : 0;
+  s_off[w][lane] = j < n ? a.offsets[j] - base : 0xFFFFFFFFu;
+  if (wave_has_pairs && lane == last) s_off[w][64] = (a.offsets[j] - base) + cnt;
+  __syncthreads();
+  const uint32_t total = wave_has_pairs ? s_off[w][64] : 0u;
+  for (uint32_t o0 = 0; o0 < total; o0 += 64) {
+    const uint32_t o = o0 + lane;
+    if (o < total) {
+      // the last pair k with s_off[k] <= o (pairs without instances share
+      // their offset with the next one and are skipped by taking the last)
+      int lo = 0, hi = last;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[w][mid] <= o) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t k = o - s_off[w][lo];
+      const int nx = s_nx[w][lo];
+      const int ty = s_ty0[w][lo] + (int)(k / (uint32_t)nx);
+      const int tx = s_tx0[w][lo] + (int)(k % (uint32_t)nx);
+      const CamDev& cam = a.cams[s_v[w][lo]];
+      const int64_t pos = (int64_t)base + (int64_t)o;
+      if (pos < a.capacity) {
+        const unsigned long long tile = (unsigned long long)(cam.tile_base + ty * cam.ntx + tx);
+        a.keys[pos] = (tile << 31) | (unsigned long long)s_d[w][lo];
+        a.values[pos] = s_p[w][lo];
+      }
     }
+  }
 }
 
 __global__ void check_capacity_kernel(unsigned long long* counters, int64_t capacity) {
@@ -219,7 +258,7 @@ __global__ void check_capacity_kernel(unsigned long long* counters, int64_t capa
 
 hipError_t launch_emit(const EmitArgs& a, unsigned long long* counters, hipStream_t st) {
   const int64_t n = a.P * a.V;
-  hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  if (n > 0) hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
   hipLaunchKernelGGL(check_capacity_kernel, dim3(1), dim3(1), 0, st, counters, a.capacity);
   return hipGetLastError();
 }
