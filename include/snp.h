@@ -98,7 +98,10 @@ typedef struct {
  *  alpha_max  alpha is clamped to at most alpha_max (< 1).
  *  bg         background colour added as T_final * bg.
  *  persistent 1 = one persistent launch over all (view, tile) work items
- *             with a device work queue; 0 = one workgroup per tile.
+ *             with a device work queue (for neural primitives the queue
+ *             hands out the tiles with the most instances first, so the
+ *             heaviest tiles do not form the tail); 0 = one workgroup per
+ *             tile.
  *  bwd_batch  instances per batch of the backward rasterizer (0 = the
  *             default for the tile shape); the tile shape is shared with the
  *             forward, and the backward runs one pixel per thread.

@@ -16,11 +16,13 @@ struct Plan {
   size_t scan_scratch, sort_scratch, loss_partials, cams_bytes;
   size_t keys_alt, values_alt;
   size_t dkeys[2], dvals[2], counts_sorted;  // depth sort of the (view, primitive) pairs
+  size_t tkeys[2], tvals[2], tile_n;          // persistent launches: tile order by instance count
   std::vector<int32_t> tile_base;
   std::vector<int64_t> pix_base;
   int64_t total_pixels;
   int tile_bits;  // significant bits of the global tile id
   bool depth_first;  // depth sort of the pairs, then the instances by tile bits only
+  bool tile_order_on;  // persistent launches take the tiles by instance count, descending
 };
 
 static bool valid_n(int n) { return n == 4 || n == 8 || n == 16 || n == 32; }
@@ -90,6 +92,9 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   int tb = 1;
   while (((int64_t)1 << tb) < tiles) ++tb;
   pl->tile_bits = tb;
+  // the heaviest-first order pays for its sort where tiles are expensive (neural
+  // primitives); the Gaussians' cheap tiles do not need it
+  pl->tile_order_on = cfg->persistent != 0 && cfg->primitive == 0;
   pl->depth_first = cfg->bin_order == 1 || (cfg->bin_order == 0 && (int64_t)V * P >= ((int64_t)1 << 16));
   // Gaussians have no density table, float64 discriminants, backward arrays
   // or pair cache
@@ -126,8 +131,16 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   pl->keys_alt = take(sizeof(unsigned long long) * (size_t)cap);
   L.values = take(sizeof(uint32_t) * (size_t)cap);
   pl->values_alt = take(sizeof(uint32_t) * (size_t)cap);
-  pl->sort_scratch = take(sort_scratch_bytes(pl->depth_first && VP > cap ? VP : cap));
+  int64_t sort_n = pl->depth_first && VP > cap ? VP : cap;
+  if (pl->tile_order_on && tiles > sort_n) sort_n = tiles;
+  pl->sort_scratch = take(sort_scratch_bytes(sort_n));
   L.ranges = take(sizeof(uint32_t) * 2 * (size_t)tiles);
+  const size_t tn = pl->tile_order_on ? (size_t)tiles : 0;
+  for (int k = 0; k < 2; ++k) {
+    pl->tkeys[k] = take(sizeof(unsigned long long) * tn);
+    pl->tvals[k] = take(sizeof(uint32_t) * tn);
+  }
+  pl->tile_n = take(sizeof(unsigned long long));
   L.gview = take(gs ? 0 : sizeof(float) * (size_t)VP * kGViewFloats);
   L.gtable = take(sizeof(float) * (size_t)P * TS);
   if (cfg->fwd_cache && !gs) {
@@ -241,6 +254,7 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
 }
 
 constexpr int kDepthBits = 31;  // positive float32 depth: the sign bit is zero
+constexpr int kTileKeyBits = 16;  // instance count of a tile, saturated, for the work-queue order
 
 // key bits the instance sort orders: the tile bits only when the instances
 // are emitted in depth order, else depth and tile bits
@@ -305,6 +319,16 @@ static snp_status do_sort(const Plan& pl, void* ws, hipStream_t st) {
   else
     SNP_HIP(radix_sort(k_main, v_main, k_alt, v_alt, L.capacity, n_inst, sort_lo(pl), sort_bits(pl), scr, st));
   SNP_HIP(launch_ranges(k_main, counters, L.capacity, wsp<uint32_t>(ws, L.ranges), L.total_tiles, st));
+  if (pl.tile_order_on) {
+    // tiles by instance count, descending, for the persistent rasterizers' work queue
+    unsigned long long* tk0 = wsp<unsigned long long>(ws, pl.tkeys[0]);
+    unsigned long long* tk1 = wsp<unsigned long long>(ws, pl.tkeys[1]);
+    uint32_t* tv0 = wsp<uint32_t>(ws, pl.tvals[0]);
+    uint32_t* tv1 = wsp<uint32_t>(ws, pl.tvals[1]);
+    unsigned long long* tn = wsp<unsigned long long>(ws, pl.tile_n);
+    SNP_HIP(launch_tile_keys(wsp<uint32_t>(ws, L.ranges), L.total_tiles, tk0, tv0, tn, st));
+    SNP_HIP(radix_sort(tk0, tv0, tk1, tv1, L.total_tiles, tn, 0, kTileKeyBits, wsp<void>(ws, pl.sort_scratch), st));
+  }
   return SNP_OK;
 }
 
@@ -320,6 +344,8 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   a.records = wsp<float>(ws, L.records);
   a.values = wsp<uint32_t>(ws, L.values);
   a.ranges = wsp<uint32_t>(ws, L.ranges);
+  // the sorted tile ids (2 passes over the 16 key bits: back in the first buffer)
+  a.tile_order = pl.tile_order_on ? wsp<uint32_t>(ws, pl.tvals[radix_passes(kTileKeyBits) % 2]) : nullptr;
   a.rects = wsp<int32_t>(ws, L.rects);
   a.gview = wsp<float>(ws, L.gview);
   a.gtable = wsp<float>(ws, L.gtable);

@@ -401,6 +401,29 @@ __global__ void __launch_bounds__(256) ranges_kernel(const unsigned long long* _
   }
 }
 
+// (16-bit key, tile id) for the order in which persistent rasterizers take
+// the tiles: key = 2^16 - 1 - min(instances, 2^16 - 1), so an ascending
+// stable sort puts the tiles with the most instances first (equal or
+// saturated counts in tile order); two radix passes
+__global__ void __launch_bounds__(256) tile_keys_kernel(const uint32_t* __restrict__ ranges, int64_t n,
+                                                        unsigned long long* __restrict__ keys,
+                                                        uint32_t* __restrict__ ids, unsigned long long* n_out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) *n_out = (unsigned long long)n;
+  if (t >= n) return;
+  const uint32_t cnt = ranges[2 * t + 1] - ranges[2 * t];
+  keys[t] = 0xFFFFull - (unsigned long long)(cnt < 0xFFFFu ? cnt : 0xFFFFu);
+  ids[t] = (uint32_t)t;
+}
+
+hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n_tiles, unsigned long long* keys, uint32_t* ids,
+                            unsigned long long* n_out, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_keys_kernel, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, st, ranges, n_tiles,
+                     keys, ids, n_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_ranges(const unsigned long long* keys, const unsigned long long* counters, int64_t capacity,
                          uint32_t* ranges, int64_t n_tiles, hipStream_t st) {
   hipError_t e = fill_u32(ranges, 2 * n_tiles, 0u, st);

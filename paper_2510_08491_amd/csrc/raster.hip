@@ -222,9 +222,12 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
       __syncthreads();
     }
     if (item >= a.total_tiles) break;
-    const int v = view_of_tile(a.cams, a.V, item);
+    // persistent launches take the tiles in the order of tile_order (most
+    // instances first), so the heaviest tiles do not form the tail
+    const int tile = (PERSIST && a.tile_order) ? (int)a.tile_order[item] : item;
+    const int v = view_of_tile(a.cams, a.V, tile);
     const CamDev& cam = a.cams[v];
-    const int local = item - cam.tile_base;
+    const int local = tile - cam.tile_base;
     const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
     PixelBlock<TW, TH, PPL> pb;
     pb.init(cam, tx, ty);
@@ -236,7 +239,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
       C0[q] = C1[q] = C2[q] = 0.f;
       done[q] = pb.pix[q] < 0;
     }
-    const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += FB) {
       const int nb = (int)min((uint32_t)FB, end - b0);
       stage_batch<N, decltype(S)::DQ4 != 0, NT, decltype(S)::NB>(S, a, v, b0, nb);
@@ -361,9 +364,12 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_gauss_kernel(RasterA
       __syncthreads();
     }
     if (item >= a.total_tiles) break;
-    const int v = view_of_tile(a.cams, a.V, item);
+    // persistent launches take the tiles in the order of tile_order (most
+    // instances first), so the heaviest tiles do not form the tail
+    const int tile = (PERSIST && a.tile_order) ? (int)a.tile_order[item] : item;
+    const int v = view_of_tile(a.cams, a.V, tile);
     const CamDev& cam = a.cams[v];
-    const int local = item - cam.tile_base;
+    const int local = tile - cam.tile_base;
     const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
     PixelBlock<TW, TH, PPL> pb;
     pb.init(cam, tx, ty);
@@ -380,7 +386,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_gauss_kernel(RasterA
     }
     const int64_t vbase = (int64_t)v * a.P;
     const float4* rec4 = reinterpret_cast<const float4*>(a.records);
-    const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NT) {
       const int nb = (int)min((uint32_t)NT, end - b0);
       if ((int)threadIdx.x < nb) {
@@ -594,9 +600,12 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
       __syncthreads();
     }
     if (item >= a.total_tiles) break;
-    const int v = view_of_tile(a.cams, a.V, item);
+    // persistent launches take the tiles in the order of tile_order (most
+    // instances first), so the heaviest tiles do not form the tail
+    const int tile = (PERSIST && a.tile_order) ? (int)a.tile_order[item] : item;
+    const int v = view_of_tile(a.cams, a.V, tile);
     const CamDev& cam = a.cams[v];
-    const int local = item - cam.tile_base;
+    const int local = tile - cam.tile_base;
     const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
     PixelBlock<TW, TH, 1> pb;
     pb.init(cam, tx, ty);
@@ -609,7 +618,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
     const float F0 = done ? 0.f : a.images_in[3 * pxi + 0];
     const float F1 = done ? 0.f : a.images_in[3 * pxi + 1];
     const float F2 = done ? 0.f : a.images_in[3 * pxi + 2];
-    const uint32_t start = a.ranges[2 * item], end = a.ranges[2 * item + 1];
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
       if (threadIdx.x < NB * NW) (&s_cnt[0][0])[threadIdx.x] = 0u;

@@ -202,6 +202,7 @@ struct RasterArgs {
   const float* records;
   const uint32_t* values;
   const uint32_t* ranges;
+  const uint32_t* tile_order;  // persistent launches: tiles by instance count, descending (null: in id order)
   const int32_t* rects;   // per (view, primitive) pixel rectangle x0, x1, y0, y1
   float* images;          // forward output
   float* final_T;         // forward output
@@ -247,6 +248,8 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* counts, i
 int radix_passes(int key_bits);
 hipError_t launch_ranges(const unsigned long long* keys, const unsigned long long* counters, int64_t capacity,
                          uint32_t* ranges, int64_t n_tiles, hipStream_t st);
+hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n_tiles, unsigned long long* keys, uint32_t* ids,
+                            unsigned long long* n_out, hipStream_t st);
 // raster.hip
 int supported_tiles(int32_t* triples, int32_t max);
 bool tile_supported(int tw, int th, int ppl);
