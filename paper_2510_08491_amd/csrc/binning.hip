@@ -289,18 +289,55 @@ __global__ void __launch_bounds__(kSortThreads) radix_hist_kernel(const unsigned
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = s_h[threadIdx.x];
 }
 
+// Stable scatter of one block's chunk.  The chunk's keys are first placed
+// in LDS in digit order (the block's own digit counts from the histogram
+// give each digit's local start; ballot ranks keep the input order within a
+// digit), then written out from LDS in that order, so consecutive threads
+// write consecutive addresses of a digit's output run (runs of about
+// chunk / 256 keys) instead of one scattered key each.
 __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const unsigned long long* __restrict__ kin, const uint32_t* __restrict__ vin,
     unsigned long long* __restrict__ kout, uint32_t* __restrict__ vout, const unsigned long long* count,
-    int64_t capacity, int shift, const uint32_t* __restrict__ offs, int64_t nblocks) {
+    int64_t capacity, int shift, const uint32_t* __restrict__ offs, const uint32_t* __restrict__ hist,
+    int64_t nblocks) {
   constexpr int NW = kSortThreads / 64;
-  __shared__ uint32_t s_off[kRadix];        // global offset of each digit for this block (running)
+  __shared__ unsigned long long s_key[kSortChunk];
+  __shared__ uint32_t s_val[kSortChunk];
+  __shared__ uint32_t s_lstart[kRadix];     // first local position of each digit
+  __shared__ uint32_t s_run[kRadix];        // running local position of each digit
+  __shared__ uint32_t s_goff[kRadix];       // global start of each digit for this block
   __shared__ uint32_t s_wcnt[NW][kRadix];   // per-wave digit counts in the current round
+  __shared__ uint32_t s_wsum[NW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  s_off[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  // local digit starts: exclusive scan of this block's digit counts
+  const uint32_t c = hist[(int64_t)t * nblocks + blockIdx.x];
+  uint32_t inc = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_wsum[w] = inc;
+  s_goff[t] = offs[(int64_t)t * nblocks + blockIdx.x];
+  __syncthreads();
+  uint32_t wbase = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) wbase += k < w ? s_wsum[k] : 0u;
+  s_lstart[t] = wbase + inc - c;
+  s_run[t] = wbase + inc - c;
   const int64_t n = sort_count(count, capacity);
   const int64_t base = (int64_t)blockIdx.x * kSortChunk;
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // all of this thread's keys and values first, so their loads are in flight together
+  unsigned long long rkey[kSortRounds];
+  uint32_t rval[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + (int64_t)r * kSortThreads + t;
+    rkey[r] = i < n ? kin[i] : 0ull;
+    rval[r] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t rbase = base + (int64_t)r * kSortThreads;
     if (rbase >= n) break;  // uniform over the block
@@ -309,13 +346,9 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     __syncthreads();
     const int64_t i = rbase + t;
     const bool valid = i < n;
-    unsigned long long key = 0;
-    uint32_t val = 0, d = 0;
-    if (valid) {
-      key = kin[i];
-      val = vin[i];
-      d = (uint32_t)((key >> shift) & 0xFF);
-    }
+    const unsigned long long key = rkey[r];
+    const uint32_t val = rval[r];
+    const uint32_t d = valid ? (uint32_t)((key >> shift) & 0xFF) : 0u;
     // lanes of this wave holding the same digit
     unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -326,24 +359,33 @@ __global__ void __launch_bounds__(kSortThreads) radix_scatter_kernel(
     const uint32_t rank_w = (uint32_t)__popcll(peers & lt_mask);
     if (valid && rank_w == 0) s_wcnt[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
-    // per digit: prefix over the waves, advance the running offset
+    // per digit: prefix over the waves, advance the running local position
     {
-      uint32_t run = s_off[t];
+      uint32_t run = s_run[t];
 #pragma unroll
       for (int k = 0; k < NW; ++k) {
-        const uint32_t c = s_wcnt[k][t];
+        const uint32_t cw = s_wcnt[k][t];
         s_wcnt[k][t] = run;
-        run += c;
+        run += cw;
       }
-      s_off[t] = run;
+      s_run[t] = run;
     }
     __syncthreads();
     if (valid) {
-      const uint32_t pos = s_wcnt[w][d] + rank_w;
-      kout[pos] = key;
-      vout[pos] = val;
+      const uint32_t lpos = s_wcnt[w][d] + rank_w;
+      s_key[lpos] = key;
+      s_val[lpos] = val;
     }
     __syncthreads();
+  }
+  // write the chunk out in digit order
+  const int64_t nloc = n - base < kSortChunk ? n - base : kSortChunk;
+  for (int q = t; q < nloc; q += kSortThreads) {
+    const unsigned long long key = s_key[q];
+    const uint32_t d = (uint32_t)((key >> shift) & 0xFF);
+    const uint32_t pos = s_goff[d] + ((uint32_t)q - s_lstart[d]);
+    kout[pos] = key;
+    vout[pos] = s_val[q];
   }
 }
 
@@ -376,7 +418,7 @@ hipError_t radix_sort(unsigned long long* k0, uint32_t* v0, unsigned long long* 
     hipError_t e = scan_exclusive_u32(hist, offs, nh, scan_scr, nullptr, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nblocks), dim3(kSortThreads), 0, st, ki, vi, ko, vo,
-                       count, capacity, shift, offs, nblocks);
+                       count, capacity, shift, offs, hist, nblocks);
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
