@@ -35,9 +35,11 @@ TRANS_WEIGHT = 4.0               # issue slots per transcendental (quarter rate)
 
 def ops_per_pair(N):
     """Algorithmic work of the rasterizer per pair, in VALU lane-ops and
-    transcendentals, counted from the formulation:
-    forward per hit pair; backward per hit pair plus per live pair (pairs
-    with a positive, unclamped integral, which carry gradient)."""
+    transcendentals, counted from the formulation (ray frame and
+    discriminant, chord, per hidden unit the phase, half-width, cos, sin,
+    reciprocal and sinc, then alpha and blending): forward per hit pair;
+    backward per hit pair plus per live pair (pairs with a positive,
+    unclamped integral, which carry gradient)."""
     fwd_v, fwd_t = 50 + 11 * N, 3 * N + 3
     bwd_hit_v, bwd_hit_t = fwd_v + 25, fwd_t
     # with the forward's pair integrals at hand, a hit pair in the backward
@@ -74,7 +76,7 @@ def main(argv=None):
                     help="profiling aid: only run --steps eager steps (no graph, no per-view, no CPU leg) and print timings")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
     import torch
