@@ -463,3 +463,37 @@ def test_relighting_colour_image_and_gradients(width, depth, fwd_cache):
     _check_images(fw, scene, cams, cfg)
     _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp",
                                              "xi"])
+
+
+def test_large_image_many_tiles():
+    """One 8192x4096 view (131072 tiles: 17 tile bits, three instance-sort
+    passes): rectangles, depth keys and tile counts of every primitive, the
+    lists of sampled tiles and sampled pixels against the oracle."""
+    scene = S.custom_scene(3000, 8, seed=181, scale_lo=0.01, scale_hi=0.1)
+    cams = S.make_cameras([(8192, 4096)], seed=182)
+    cfg = config_for(scene, tile=(16, 16, 1), persistent=1)
+    fw = run_forward(scene, cams, cfg)
+    cam = cams[0]
+    pr = project_all(scene, cam, cfg.tile_w, cfg.tile_h, cfg.z_near)
+    ne = pr["nonempty"]
+    assert np.array_equal(fw["tile_counts"][0], pr["n_tiles"].astype(np.int32))
+    assert np.array_equal(fw["rects"][0][ne], pr["rect"][ne].astype(np.int32))
+    assert np.array_equal(fw["depth_bits"][0][ne], pr["depth_bits"][ne])
+    assert fw["instances"] == int(pr["n_tiles"].sum())
+    rng = np.random.default_rng(183)
+    ntx = (cam.width + 15) // 16
+    ids = np.nonzero(ne)[0]
+    tr = pr["trect"][ids]
+    busy = np.nonzero(fw["ranges"][:, 1] > fw["ranges"][:, 0])[0]
+    for g in rng.choice(busy, 12, replace=False):
+        ty, tx = divmod(int(g), ntx)
+        sel = (tr[:, 0] <= tx) & (tx <= tr[:, 1]) & (tr[:, 2] <= ty) & (ty <= tr[:, 3])
+        lst = sorted(zip(pr["depth_bits"][ids][sel].tolist(), ids[sel].tolist()))
+        s, e = fw["ranges"][g]
+        assert fw["values"][s:e].tolist() == [p for _, p in lst]
+    cols = rng.integers(2048, 6144, 40)
+    rows = rng.integers(1024, 3072, 40)
+    c, t, _ = render_pixels(scene, cam, cols, rows, options_for(cfg), proj=pr)
+    err = np.max(np.abs(fw["images"][0][rows, cols] - c))
+    say(f"  instances {fw['instances']}, sampled image err {err:.2e}")
+    assert err <= IMG_TOL and np.max(np.abs(fw["T"][0][rows, cols] - t)) <= IMG_TOL
