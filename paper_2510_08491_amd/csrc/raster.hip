@@ -397,6 +397,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_gauss_kernel(RasterA
         S.cb[threadIdx.x] = a.records[r * kRecFloats + 19];
       }
       __syncthreads();
+#pragma unroll 4
       for (int j = 0; j < nb; ++j) {
         const int4 rc = S.rect[j];
         if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
