@@ -157,3 +157,46 @@ def test_time_must_be_finite():
     assert lib.snp_workspace_layout(C.byref(_cfg(time=0.5)), 100, 1, cams, 500, C.byref(lay)) == L.SNP_OK
     assert lib.snp_workspace_layout(C.byref(_cfg(time=float("nan"))), 100, 1, cams, 500,
                                     C.byref(lay)) == L.SNP_ERR_INVALID
+
+
+def test_training_and_graph_entry_points_validate_on_the_host():
+    """Invalid calls of the forward graph and the training extras return
+    SNP_ERR_INVALID before anything reaches the device."""
+    L = _lib()
+    lib = L.lib()
+    from paper_2510_08491_amd.render import camera_array
+    cams = camera_array(S.make_cameras([(64, 64)], seed=1))
+    lay = L.SnpLayout()
+    assert lib.snp_workspace_layout(C.byref(_cfg()), 100, 1, cams, 500, C.byref(lay)) == L.SNP_OK
+    pr = L.SnpPrims()
+    pr.P = 100
+    h = C.c_void_p()
+    fake = C.c_void_p(256)
+    # forward graph: null images / graph handle
+    assert lib.snp_graph_create_forward(C.byref(_cfg()), C.byref(pr), 1, cams, fake, C.byref(lay), None, fake, None,
+                                        C.byref(h)) == L.SNP_ERR_INVALID
+    assert lib.snp_graph_create_forward(C.byref(_cfg()), C.byref(pr), 1, cams, fake, C.byref(lay), fake, fake, None,
+                                        None) == L.SNP_ERR_INVALID
+    # Adam: step 0, too many groups, beta out of range, a non-empty group without moments
+    g = (L.SnpAdamGroup * 1)()
+    g[0].n = 0
+    assert lib.snp_adam_step(g, 1, 0, 0.9, 0.999, 1e-15, None) == L.SNP_ERR_INVALID
+    assert lib.snp_adam_step(g, L.MAX_ADAM_GROUPS + 1, 1, 0.9, 0.999, 1e-15, None) == L.SNP_ERR_INVALID
+    assert lib.snp_adam_step(g, 1, 1, 1.0, 0.999, 1e-15, None) == L.SNP_ERR_INVALID
+    g[0].n = 10
+    g[0].param = g[0].grad = fake
+    assert lib.snp_adam_step(g, 1, 1, 0.9, 0.999, 1e-15, None) == L.SNP_ERR_INVALID
+    # regulariser: no loss output
+    assert lib.snp_scale_regularizer(100, fake, 0.1, None, None, fake, C.byref(lay), None) == L.SNP_ERR_INVALID
+    # population control: scratch too small, bad array kind, centres without noise
+    dc = L.SnpDensityControl()
+    dc.split_shrink = 1.6
+    assert lib.snp_densify_plan(100, fake, fake, fake, C.byref(dc), fake, fake, fake, fake, 16,
+                                None) == L.SNP_ERR_INVALID
+    arr = (L.SnpRowArray * 1)()
+    arr[0].src = arr[0].dst = fake
+    arr[0].width, arr[0].kind = 3, 7
+    assert lib.snp_densify_apply(100, fake, fake, fake, fake, fake, fake, 1.6, arr, 1, None) == L.SNP_ERR_INVALID
+    arr[0].kind = L.ROWS_CENTERS
+    assert lib.snp_densify_apply(100, fake, fake, fake, fake, fake, None, 1.6, arr, 1, None) == L.SNP_ERR_INVALID
+    assert lib.snp_densify_scratch_bytes(100) > 400
