@@ -200,3 +200,15 @@ def test_training_and_graph_entry_points_validate_on_the_host():
     arr[0].kind = L.ROWS_CENTERS
     assert lib.snp_densify_apply(100, fake, fake, fake, fake, fake, None, 1.6, arr, 1, None) == L.SNP_ERR_INVALID
     assert lib.snp_densify_scratch_bytes(100) > 400
+
+
+def test_tuning_cache_lookup():
+    """The autotuner's cache key and lookup: the stored 16-view entry gives
+    its tile shape and backward batch; unknown classes give None."""
+    from paper_2510_08491_amd import tuning
+    cams = S.make_cameras([(640, 480)] * 4 + [(1280, 720)] * 8 + [(1920, 1080)] * 4, seed=1)
+    assert tuning.key_of(16, 1, cams) == "gfx950/N16/cm1/V16_MP17"
+    assert tuning.lookup(16, 1, cams) == (16, 16, 1, 8)
+    assert tuning.lookup(8, 0, S.make_cameras([(64, 64)], seed=1)) is None
+    shapes = tuning.supported_shapes()
+    assert (16, 16, 1) in shapes and (8, 8, 1) in shapes and len(shapes) == 6

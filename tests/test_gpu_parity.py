@@ -497,3 +497,18 @@ def test_large_image_many_tiles():
     err = np.max(np.abs(fw["images"][0][rows, cols] - c))
     say(f"  instances {fw['instances']}, sampled image err {err:.2e}")
     assert err <= IMG_TOL and np.max(np.abs(fw["T"][0][rows, cols] - t)) <= IMG_TOL
+
+
+def test_autotuner_picks_a_measured_shape():
+    """The autotuner times each candidate on a forward + backward, checks
+    that all render the same image, and returns one of the candidates."""
+    import paper_2510_08491_amd as snp
+    from paper_2510_08491_amd import tuning
+    _, scene, cams, targets = S.make_workload("C1")
+    cfg = config_for(scene, persistent=1)
+    params = snp.params_to_device(scene)
+    tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()
+    best, table = tuning.autotune(cfg, scene["P"], cams, params, tg, reps=1, shapes=[(16, 16, 1), (8, 8, 1)],
+                                  write=False, log=say)
+    assert best[:3] in [(16, 16, 1), (8, 8, 1)]
+    assert all(v["img_diff"] <= 1e-5 for v in table.values())
