@@ -224,3 +224,40 @@ def test_early_termination_changes_pixels_by_at_most_t_eps():
     b = G.render_view_gaussian(sc, cam, RenderOptions(t_eps=0.0))
     assert np.max(np.abs(a["image"] - b["image"])) <= 1e-3
     assert a["hit_pairs"] < b["hit_pairs"]
+
+
+def test_alpha_min_skips_faint_gaussian_pairs_by_hand():
+    """alpha_min for Gaussians: inside the rectangle every pixel is a hit, but
+    pixels whose alpha is below alpha_min change neither colour nor
+    transmittance; composited by hand from o exp(-m^2 / 2) with numpy's
+    inverse covariance."""
+    cam = S.make_cameras([(80, 64)], seed=3)[0]
+    Rinv = np.linalg.inv(np.asarray(cam.R, float))
+    o = -Rinv @ np.asarray(cam.t, float)
+    fwd = Rinv[:, 2]
+    front, back = o + 2.5 * fwd, o + 3.2 * fwd + 0.05 * Rinv[:, 0]
+    cols = [[1.0, 0.0, 0.0], [0.0, 0.5, 1.0]]
+    amin = 0.3
+    opts = RenderOptions(t_eps=0.0, alpha_min=amin)
+    sc = _scene([back, front], [0.08, 0.05], colors=[cols[1], cols[0]], opacity=[0.9, 0.7])
+    out = G.render_view_gaussian(sc, cam, opts)
+    pr = G.project_gaussians(sc, cam)
+    rows, cc = np.mgrid[0:64, 0:80]
+
+    def alpha_of(p, op):
+        d = np.stack([cc + 0.5 - pr["mean2d"][p, 0], rows + 0.5 - pr["mean2d"][p, 1]], -1)
+        m2 = np.einsum("...i,ij,...j->...", d, np.linalg.inv(pr["cov2d"][p]), d)
+        x0, x1, y0, y1 = pr["rect"][p]
+        inr = (cc >= x0) & (cc <= x1) & (rows >= y0) & (rows <= y1)
+        return inr, np.where(inr, np.minimum(0.99, float(np.float32(op)) * np.exp(-0.5 * m2)), 0.0)
+
+    in_b, a_b = alpha_of(0, 0.9)
+    in_f, a_f = alpha_of(1, 0.7)
+    u_f = in_f & (a_f >= amin)
+    u_b = in_b & (a_b >= amin)
+    assert np.any(in_f & ~u_f) and np.any(u_f) and np.any(in_b & ~u_b)
+    af, ab = np.where(u_f, a_f, 0.0), np.where(u_b, a_b, 0.0)
+    expect = af[..., None] * np.array(cols[0]) + ((1 - af) * ab)[..., None] * np.array(cols[1])
+    assert np.max(np.abs(out["image"] - expect)) < 1e-12
+    assert np.max(np.abs(out["T"] - (1 - af) * (1 - ab))) < 1e-12
+    assert out["hit_pairs"] == int(in_f.sum() + in_b.sum())

@@ -174,3 +174,46 @@ def test_colour_mlp_identity_weights():
     scene["cmlp"] = np.tile(vec2, (20, 1)).astype(np.float32)
     expect2 = 1.0 / (1.0 + np.exp(-bias.astype(np.float32).astype(float)))
     assert np.max(np.abs(primitive_colors(scene, cam) - expect2)) < 1e-12
+
+
+def test_alpha_min_skips_faint_pairs_by_hand():
+    """alpha_min (the 3DGS skip of faint pairs): a pair whose alpha is below
+    alpha_min leaves colour and transmittance unchanged but is still a hit.
+    Front sphere faint everywhere (skipped at every pixel), back sphere
+    faint near its silhouette only; composited by hand from the analytic
+    constant-density alphas 1 - exp(-sigma 2 sqrt(r^2 - b^2))."""
+    cam = S.make_cameras([(64, 64)], seed=3)[0]
+    o = -np.linalg.inv(np.asarray(cam.R, float)) @ np.asarray(cam.t, float)
+    fwd = -o / np.linalg.norm(o)
+    front, back = o + 2.6 * fwd, o + 3.4 * fwd
+    cols = [[1.0, 0.0, 0.0], [0.0, 0.5, 1.0]]
+    r_f, r_b, s_f, s_b = 0.25, 0.3, 0.02, 2.0
+    scene = _sphere_scene([back, front], [r_b, r_f], [cols[1], cols[0]], [s_b, s_f])
+    amin = 0.45
+    out = R.render_view(scene, cam, R.RenderOptions(t_eps=0.0, alpha_min=amin))
+    rows, cc = np.mgrid[0:64, 0:64]
+    oo, d = pixel_rays(cam, cc, rows)
+
+    def analytic(center, r, s_w2):
+        b = np.linalg.norm(np.cross(np.asarray(center, np.float32).astype(float) - oo, d), axis=-1)
+        r64 = float(np.float32(r))
+        sigma = float(np.sum((np.float32(s_w2) * np.ones(8, np.float32) / np.float32(8)).astype(float)))
+        chord = 2 * np.sqrt(np.maximum(r64 * r64 - b * b, 0.0))
+        return chord > 0, np.minimum(1 - np.exp(-sigma * chord), 0.99)
+
+    hit_f, a_f = analytic(front, r_f, s_f)
+    hit_b, a_b = analytic(back, r_b, s_b)
+    assert np.all(a_f < amin) and np.any(hit_f)              # front: every pair skipped
+    assert np.any(hit_b & (a_b < amin)) and np.any(a_b >= amin)  # back: skipped at the rim only
+    use_b = hit_b & (a_b >= amin)
+    expect_T = np.where(use_b, 1 - a_b, 1.0)
+    expect_C = np.where(use_b, a_b, 0.0)[..., None] * np.array(cols[1])
+    assert np.max(np.abs(out["T"] - expect_T)) <= 1e-12
+    assert np.max(np.abs(out["image"] - expect_C)) <= 1e-12
+    assert out["hit_pairs"] == int(hit_f.sum() + hit_b.sum())
+    # the pixel-by-pixel renderer takes the same decisions
+    sel = np.random.default_rng(4).integers(0, 64, (2, 48))
+    c, t, h = R.render_pixels(scene, cam, sel[0], sel[1], R.RenderOptions(t_eps=0.0, alpha_min=amin))
+    assert np.max(np.abs(c - expect_C[sel[1], sel[0]])) <= 1e-12
+    assert np.max(np.abs(t - expect_T[sel[1], sel[0]])) <= 1e-12
+    assert np.array_equal(h, hit_f[sel[1], sel[0]].astype(int) + hit_b[sel[1], sel[0]].astype(int))
