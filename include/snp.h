@@ -217,8 +217,11 @@ snp_status snp_workspace_layout(const snp_config* cfg, int64_t P, int32_t V, con
 snp_status snp_preprocess(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
                           void* ws, const snp_layout* layout, hipStream_t stream);
 
-/* Tile binning: the exclusive scan of the tile counts and one (key, value)
- * instance per covered tile, key = (global tile id << 31) | depth bits,
+/* Tile binning, the "tiling" stage of the full rendering pipeline the paper
+ * times (App. A, Integration Cost: preprocessing, primitive sorting/tiling,
+ * integration, alpha blending); it prepares the per-ray set of intersected
+ * primitives in depth order that Eq. 4 composites.  Computes the exclusive
+ * scan of the tile counts and one (key, value) instance per covered tile, key = (global tile id << 31) | depth bits,
  * value = primitive id; instance count and overflow flag on the device.
  * With bin_order 1 the (view, primitive) pairs are first sorted by depth
  * bits (stably, so equal depths keep primitive order) and the scan and the
@@ -226,8 +229,12 @@ snp_status snp_preprocess(const snp_config* cfg, const snp_prims* prims, int32_t
 snp_status snp_bin(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
                    const snp_layout* layout, hipStream_t stream);
 
-/* Stable device radix sort of the instances into key order (equal keys in
- * primitive order) and the [start, end) range of every global tile.  With
+/* The "sorting" stage (App. A, Integration Cost): Eq. 4 blends the
+ * primitives met by a ray in depth order, so every tile's list is put in
+ * ascending depth.  Stable device radix sort of the instances into key order
+ * (equal keys in primitive order) and the [start, end) range of every global
+ * tile; per tile the values are then the primitive ids in (depth bits, id)
+ * order.  With
  * bin_order 1 the instances arrive from snp_bin in depth order, so the tile
  * bits of the key alone are sorted. */
 snp_status snp_sort(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, void* ws,
@@ -248,10 +255,20 @@ snp_status snp_loss_l1(const snp_config* cfg, int32_t V, const snp_camera* cams,
                        const float* targets, double n_norm, void* ws, const snp_layout* layout, double* loss_out,
                        float* dL_dimages, hipStream_t stream);
 
-/* Backward: gradients of the loss with respect to every primitive parameter
- * given dL/dimages, the forward's images and the workspace the forward left.
- * The traversal recomputes transmittance in forward order; nothing per pixel
- * or per pair is stored between the passes.  Adds into `grads`. */
+/* Backward of the differentiable splatting renderer the primitives are
+ * trained through (Sec. 3.3, Training: the 3DGS image loss, optimised by
+ * gradient descent; Sec. 6: neural primitives in a differentiable
+ * splatting-based renderer): the exact adjoint of snp_render_forward,
+ * giving the gradients of the loss with respect to every primitive parameter
+ * from dL/dimages, the forward's images and the workspace the forward left
+ * (its sorted tile lists, records and tables).  The traversal walks each
+ * tile's list in forward order and recomputes the transmittance; no per-pixel
+ * history is kept.  What it reads per (pixel, instance) pair depends on
+ * cfg.fwd_cache: with 1 the forward stored the integral of every pair it
+ * evaluated in the workspace (layout.ahat_cache, for the leading
+ * fwd_cache_instances instances) and the backward reads it back; with 0, and
+ * for batches past the cached instances, it re-evaluates the density
+ * integral.  Adds into `grads`. */
 snp_status snp_render_backward(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
                                void* ws, const snp_layout* layout, const float* images, const float* dL_dimages,
                                const snp_grads* grads, hipStream_t stream);
@@ -317,7 +334,7 @@ const char* snp_status_string(snp_status s);
 snp_status snp_selftest_wave_sum(const float* in, float* out, int32_t waves, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
- * Training-step extras after the backward (Sec. 4, "Training" and
+ * Training-step extras after the backward (Sec. 3.3, "Training" and
  * "Population Control"; the appendix on hyperparameters: Adam with learning
  * rates 1.6e-4 for means, 5e-3 scales, 1e-3 quaternions, 2.5e-3 SH, 1e-3
  * MLP; densify / prune thresholds 1e-4 / 2e-6, growing scale 1e-2, pruning

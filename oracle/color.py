@@ -3,7 +3,7 @@
 Test infrastructure only (see the package docstring).
 
 The paper's novel-view-synthesis colour is spherical harmonics of four
-bands, as in 3DGS (Sec. 3.1 and Sec. 4, implementation details); its
+bands, as in 3DGS (Sec. 3.1 and Sec. 3.3, implementation details); its
 relighting application uses a per-primitive colour network (App. D.2,
 Eq. 14) whose inputs include the view direction relative to the primitive.
 The workloads here use a constant RGB per primitive, degree-3 spherical

@@ -12,7 +12,7 @@ path and carry no gradient.
 
 Route 2 is central finite differences of the numpy renderer's loss.
 
-The paper's renderer is differentiable (Sec. 5: a differentiable
+The paper's renderer is differentiable (Sec. 6: a differentiable
 splatting-based renderer) but its adjoint is not described; these routes
 define the reference gradient of the loss with respect to centres, scales,
 raw quaternions, W1, b1, W2, b2 and colours (or colour-MLP weights).

@@ -6,11 +6,11 @@ Test infrastructure only (see the package docstring).
 The paper trains with Adam (Kingma & Ba) at per-group learning rates (means
 1.6e-4, scales 5e-3, quaternions 1e-3, SH 2.5e-3, MLP 1e-3; App. on
 hyperparameters), adds to the 3DGS loss a regulariser that penalises the
-standard deviation of each primitive's scale components (Sec. 4,
+standard deviation of each primitive's scale components (Sec. 3.3,
 "Training"), and controls the population by the gradient magnitude of the
 primitives' network weights: primitives whose gradient exceeds a threshold
 are duplicated or split, those with low gradient are pruned, with a growing
-scale threshold 1e-2 and a pruning scale threshold 0.5 (Sec. 4, "Population
+scale threshold 1e-2 and a pruning scale threshold 0.5 (Sec. 3.3, "Population
 Control"; App. on hyperparameters).  Readings of what it leaves open:
 
   * Adam as in Kingma & Ba's algorithm: m = b1 m + (1 - b1) g,

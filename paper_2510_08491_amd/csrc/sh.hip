@@ -1,5 +1,5 @@
 // Spherical-harmonics colour of degree 3 (the colour the paper adopts for
-// novel-view synthesis, Sec. 3.1; four bands as in 3DGS, Sec. 4): per
+// novel-view synthesis, Sec. 3.1; four bands as in 3DGS, Sec. 3.3): per
 // (primitive, view), with d = normalize(x_B - o_v) and the 16 real
 // orthonormal harmonics Y_k of degrees 0..3 in (l, m) order (0,0), (1,-1),
 // (1,0), (1,1), (2,-2) ... (3,3),

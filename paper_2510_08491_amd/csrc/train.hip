@@ -1,6 +1,6 @@
 // Training-step extras after the backward: Adam over every parameter group
 // in one launch, the scale regulariser, and population control by the
-// gradient magnitude of the primitives' density-MLP weights (Sec. 4,
+// gradient magnitude of the primitives' density-MLP weights (Sec. 3.3,
 // "Training" and "Population Control"; the appendix on hyperparameters).
 //
 // All of it is bound by HBM traffic (a few flops per float moved): plain

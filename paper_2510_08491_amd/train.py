@@ -1,6 +1,6 @@
 """Training-step extras on the device, through the C ABI: Adam over all
 parameter groups in one launch, the scale regulariser, and population
-control by the density-MLP gradient magnitude (Sec. 4, "Training" and
+control by the density-MLP gradient magnitude (Sec. 3.3, "Training" and
 "Population Control"; the appendix on hyperparameters).  Argument
 marshalling only; every step runs in libsnp's kernels."""
 from __future__ import annotations

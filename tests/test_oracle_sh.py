@@ -1,6 +1,6 @@
 """Pins of the oracle's spherical-harmonics colour (degree 3, 16 basis
 functions per channel; the colour the paper adopts for novel-view synthesis,
-Sec. 3.1, four bands as in 3DGS, Sec. 4 implementation details)."""
+Sec. 3.1, four bands as in 3DGS, Sec. 3.3 implementation details)."""
 import numpy as np
 from scipy import special
 
