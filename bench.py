@@ -67,39 +67,57 @@ def main(argv=None):
     ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "A"],
                     help="C3/C4/C5: fwd+bwd step; A: forward-only frames/s of the 100k-primitive throughput workload")
     ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,bwd_batch] (default: tuned)")
+    ap.add_argument("--fwd-cache", type=int, default=None, choices=[0, 1],
+                    help="1: the forward keeps every pair's integral for the backward; 0: the backward "
+                         "re-evaluates (default: 1 for C3/C4, 0 for C5, whose step recomputes per-tile state)")
     ap.add_argument("--bin-order", type=int, default=0, choices=[0, 1, 2],
                     help="1 depth sort of the pairs then tile-bit instance sort, 2 full-key sort, 0 by size")
     ap.add_argument("--no-per-view", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--oracle-views", type=int, default=16,
+                    help="views whose sampled tile is checked against the oracle (one tile per view)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--eager-only", action="store_true",
                     help="profiling aid: only run --steps eager steps (no graph, no per-view, no CPU leg) and print timings")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print(json.dumps({"error": "this benchmark measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU only: the path would shard over the "
+                                   "views, with one gradient reduction per step; run with --gpus 1"}))
         sys.exit(2)
 
     import torch
+    import synthetic as S
+
+    if a.workload == "A":
+        torch.cuda.set_device(0)
+        return forward_fps(a)
+    cfg0, scene, cams, targets = S.make_workload(a.workload)
+    fwd_cache = a.fwd_cache if a.fwd_cache is not None else (0 if a.workload == "C5" else 1)
+
+    # ---- the oracle on the host's cores, before the GPU is touched (the
+    # worker processes are forked from a process without a GPU context) -----------
+    cpu = None
+    if not a.no_cpu_baseline and not a.eager_only:
+        cpu = cpu_baseline(scene, cams, targets, a.cpu_seconds, a.workload)
+        log(f"[bench] cpu oracle: {cpu}")
+
     import paper_2510_08491_amd as snp
     from paper_2510_08491_amd import tuning
     import paper_2510_08491_amd.render as rmod
-    import synthetic as S
 
     torch.cuda.set_device(0)
-    if a.workload == "A":
-        return forward_fps(a)
-    cfg0, scene, cams, targets = S.make_workload(a.workload)
     N = scene["N"]
     if a.tile:
         tile = tuple(int(x) for x in a.tile.split(","))
     else:
-        tile = tuning.lookup(N, scene["color_mode"], cams) or (16, 16, 1)
+        tile = tuning.lookup(N, scene["color_mode"], cams, fwd_cache) or (16, 16, 1)
     if len(tile) == 3:
         tile = tile + (0,)
     cfg = snp.RenderConfig(n_hidden=N, omega0=scene["omega0"], color_mode=scene["color_mode"], bin_order=a.bin_order,
                            cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], tile_w=tile[0],
-                           tile_h=tile[1], px_per_lane=tile[2], bwd_batch=tile[3], persistent=1)
-    log(f"[bench] workload {a.workload}: P={scene['P']} V={len(cams)} N={N} tile={tile}")
+                           tile_h=tile[1], px_per_lane=tile[2], bwd_batch=tile[3], persistent=1, fwd_cache=fwd_cache)
+    log(f"[bench] workload {a.workload}: P={scene['P']} V={len(cams)} N={N} tile={tile} fwd_cache={fwd_cache}")
     params = snp.params_to_device(scene)
     tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()
     n_norm = float(tg.numel())
@@ -113,8 +131,10 @@ def main(argv=None):
     rast.forward(params, images, final_T, count_pairs=True)
     cnt = rast.counters()
     hit_pairs, live_pairs = cnt["hit_pairs"], cnt["live_pairs"]
+    tile_pairs = rast.tile_pairs().cpu().numpy().astype(np.int64)
     log(f"[bench] instances {inst}, hit pairs {hit_pairs}, live pairs {live_pairs}, "
-        f"pair cache {rast.fwd_cache} ({rast.layout.ahat_cache_bytes / 2 ** 30:.1f} GiB)")
+        f"pair cache {rast.fwd_cache} ({rast.layout.ahat_cache_bytes / 2 ** 30:.1f} GiB, "
+        f"{rast.cached_instances} of {inst} instances)")
     if a.eager_only:
         loss = torch.zeros(1, dtype=torch.float64, device="cuda")
         dL = torch.empty_like(images)
@@ -124,6 +144,7 @@ def main(argv=None):
             rast.step(params, images, final_T, tg, n_norm, loss, dL, grads)
             torch.cuda.synchronize()
             log(f"[bench] eager step {s}: {1e3 * (time.perf_counter() - t0):.1f} ms")
+        rast.read_status()
         return
 
     # ---- batched: one graph per step -------------------------------------------------
@@ -142,95 +163,61 @@ def main(argv=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = e0.elapsed_time(e1) / a.steps
-    log(f"[bench] batched graph: {ms_step:.3f} ms/step (wall {1e3 * wall / a.steps:.3f})")
+    # the replays' device flags: instance overflow, phase range (raises on either)
+    step.check()
+    status_ok = True
+    log(f"[bench] batched graph: {ms_step:.3f} ms/step (wall {1e3 * wall / a.steps:.3f}), status ok")
     img_batched = step.images.clone()
 
     # ---- rasterizer kernels timed live (eager step, HIP events on the launch stream) --
-    rmod.kernel_timing(True)
-    fwd_ms, bwd_ms = [], []
-    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    dL = torch.empty_like(images)
-    grads = snp.zeros_like_params(params)
-    for _ in range(max(3, min(a.steps, 5))):
-        rast.step(params, images, final_T, tg, n_norm, loss, dL, grads)
-        f, b = rmod.kernel_timing_read()
-        fwd_ms.append(f)
-        bwd_ms.append(b)
-    rmod.kernel_timing(False)
-    fwd_ms, bwd_ms = float(np.mean(fwd_ms)), float(np.mean(bwd_ms))
+    fwd_ms, bwd_ms = eager_kernel_ms(snp, rmod, torch, rast, params, images, final_T, tg, n_norm, a.steps)
     log(f"[bench] raster kernels: forward {fwd_ms:.3f} ms, backward {bwd_ms:.3f} ms")
     pair_cache = rast.fwd_cache
     cache_gb = rast.layout.ahat_cache_bytes / 2 ** 30
-    # the Adam leg and the per-view rasterizers below need the workspace's memory
-    del step, rast, images, final_T, dL
+    cached_frac = rast.cached_instances / max(inst, 1) if pair_cache else 0.0
+    del step, rast, images, final_T
     torch.cuda.empty_cache()
 
-    # ---- Adam over every parameter with these gradients (HBM bound; after the step, not in the metric) --
-    from paper_2510_08491_amd import train as TR
-    opt_params = {k: v.clone() for k, v in params.items() if k in TR.PAPER_LRS}
-    opt = TR.Adam(opt_params)
-    n_elems = sum(v.numel() for v in opt_params.values())
-    opt.step(grads)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(5):
-        opt.step(grads)
-    e1.record()
-    torch.cuda.synchronize()
-    adam_ms = e0.elapsed_time(e1) / 5
-    adam_bytes = 28 * n_elems  # read param, grad, m, v; write param, m, v (float32)
-    optimizer = {"kernel": "adam (all groups, one launch)", "ms": round(adam_ms, 4), "elements": n_elems,
-                 "bytes": adam_bytes, "GB_per_s": round(adam_bytes / (adam_ms * 1e-3) / 1e9, 1),
-                 "frac_of_hbm_peak": round(adam_bytes / (adam_ms * 1e-3) / 8e12, 4)}
+    # ---- the oracle on sampled tiles of the batched images (untimed) -----------------
+    check = None
+    if not a.no_oracle_check:
+        check = oracle_check(scene, cams, cfg, img_batched, tile_pairs, a.oracle_views)
+        log(f"[bench] oracle check: {check}")
+
+    # ---- the same step re-evaluating every pair in the backward (no pair cache) --------
+    recompute = None
+    if pair_cache:
+        cfg_rc = snp.RenderConfig(**{**cfg.__dict__, "fwd_cache": 0})
+        r0 = snp.Rasterizer(cfg_rc, scene["P"], cams)
+        r0._alloc(int(r0.prepare(params) * 1.1) + 4096)
+        im0, T0 = r0.new_images()
+        f_rc, b_rc = eager_kernel_ms(snp, rmod, torch, r0, params, im0, T0, tg, n_norm, a.steps)
+        same = bool(torch.equal(im0, img_batched))
+        del r0, im0, T0
+        torch.cuda.empty_cache()
+        recompute = {"fwd_ms": round(f_rc, 4), "bwd_ms": round(b_rc, 4), "images_identical": same}
+        log(f"[bench] without the pair cache: forward {f_rc:.3f} ms, backward {b_rc:.3f} ms, images identical {same}")
+
+    # ---- Adam over every parameter (HBM bound; after the step, not in the metric) --
+    optimizer = adam_leg(snp, torch, params)
     log(f"[bench] adam: {optimizer}")
-    del opt, opt_params, grads
-    torch.cuda.empty_cache()
 
     # ---- per-view plain launches ---------------------------------------------------------
     per_view_ms = None
     per_view_equal = None
     if not a.no_per_view:
-        cfg_pv = snp.RenderConfig(**{**cfg.__dict__, "persistent": 0})
-        rv = []
-        for c in cams:
-            r = snp.Rasterizer(cfg_pv, scene["P"], [c])
-            r._alloc(int(r.prepare(params) * 1.1) + 4096)
-            rv.append(r)
-        offs = np.cumsum([0] + [c.width * c.height for c in cams])
-        outs = [r.new_images() for r in rv]
-        dls = [torch.empty_like(o[0]) for o in outs]
-        losses = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in rv]
-        pv_grads = snp.zeros_like_params(params)
-
-        def per_view_step():
-            for g in pv_grads.values():
-                g.zero_()
-            for v, r in enumerate(rv):
-                r.preprocess(params)
-                r.bin()
-                r.sort()
-                r.forward(params, outs[v][0], outs[v][1])
-                r.loss_l1(outs[v][0], tg[3 * offs[v]:3 * offs[v + 1]], n_norm, losses[v], dls[v])
-                r.backward(params, outs[v][0], dls[v], pv_grads)
-
-        for _ in range(a.warmup):
-            per_view_step()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(a.steps):
-            per_view_step()
-        e1.record()
-        torch.cuda.synchronize()
-        per_view_ms = e0.elapsed_time(e1) / a.steps
-        per_view_equal = all(torch.equal(outs[v][0], img_batched[3 * offs[v]:3 * offs[v + 1]])
-                             for v in range(len(cams)))
+        per_view_ms, per_view_equal = per_view_leg(snp, torch, cfg, scene, cams, params, tg, n_norm, img_batched, a)
         log(f"[bench] per-view plain launches: {per_view_ms:.3f} ms/step, images identical: {per_view_equal}")
 
     # ---- roofline of the dominant kernel ----------------------------------------------------
     ops = ops_per_pair(N)
+
+    def bwd_slots_of(cached_fraction):
+        hit = hit_pairs * (cached_fraction * slots(ops["bwd_hit_cached"]) + (1 - cached_fraction) * slots(ops["bwd_hit"]))
+        return hit + live_pairs * slots(ops["bwd_live"])
+
     fwd_slots = hit_pairs * slots(ops["fwd"])
-    bwd_slots = hit_pairs * slots(ops["bwd_hit_cached" if pair_cache else "bwd_hit"]) + \
-        live_pairs * slots(ops["bwd_live"])
+    bwd_slots = bwd_slots_of(cached_frac)
     if bwd_ms >= fwd_ms:
         dom, dom_ms, dom_slots = "render_bwd", bwd_ms, bwd_slots
     else:
@@ -238,16 +225,17 @@ def main(argv=None):
     achieved = dom_slots / (dom_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": round(PEAK_SLOTS / 1e12, 3),
                 "unit": "Tslot/s", "frac": round(achieved / (PEAK_SLOTS / 1e12), 4),
-                "traffic": measured_traffic(a.workload, dom),
+                "traffic": measured_traffic(a.workload, dom, pair_cache),
                 "kernel_ms": round(dom_ms, 4),
                 "fwd_frac": round(fwd_slots / (fwd_ms * 1e-3) / PEAK_SLOTS, 4),
-                "bwd_frac": round(bwd_slots / (bwd_ms * 1e-3) / PEAK_SLOTS, 4)}
-
-    # ---- oracle on a bounded crop, on the host ---------------------------------------------------
-    cpu = None
-    if not a.no_cpu_baseline:
-        cpu = cpu_baseline(scene, cams, targets, a.cpu_seconds)
-        log(f"[bench] cpu oracle: {cpu}")
+                "bwd_frac": round(bwd_slots / (bwd_ms * 1e-3) / PEAK_SLOTS, 4),
+                "fwd_bwd_frac": round((fwd_slots + bwd_slots) / ((fwd_ms + bwd_ms) * 1e-3) / PEAK_SLOTS, 4),
+                "slots_per_pair": {"fwd_hit": slots(ops["fwd"]), "bwd_hit_cached": slots(ops["bwd_hit_cached"]),
+                                   "bwd_hit_recomputed": slots(ops["bwd_hit"]), "bwd_live": slots(ops["bwd_live"])}}
+    if recompute is not None:
+        rb = bwd_slots_of(0.0)
+        recompute["bwd_frac"] = round(rb / (recompute["bwd_ms"] * 1e-3) / PEAK_SLOTS, 4)
+        recompute["fwd_frac"] = round(fwd_slots / (recompute["fwd_ms"] * 1e-3) / PEAK_SLOTS, 4)
 
     value = hit_pairs / (ms_step * 1e-3)
     out = {
@@ -266,21 +254,170 @@ def main(argv=None):
         "config": {"workload": workload_name(a.workload, cams), "primitives": scene["P"], "n_hidden": N,
                    "colour_mlp": [scene["cmlp_width"], scene["cmlp_depth"]], "tile": list(tile),
                    "batched": "one HIP graph per step, persistent rasterizer launches",
-                   "pair_cache": pair_cache, "pair_cache_gib": round(cache_gb, 2)},
+                   "pair_cache": pair_cache, "pair_cache_gib": round(cache_gb, 2),
+                   "pair_cache_instances_frac": round(cached_frac, 4)},
         "hit_pairs_per_step": hit_pairs,
         "live_pairs_per_step": live_pairs,
         "instances_per_step": inst,
+        "status_ok": status_ok,
+        "max_img_err": None if check is None else check["max_img_err"],
+        "oracle_check": check,
         "per_view_ms_per_step": per_view_ms,
         "batched_speedup_vs_per_view": (per_view_ms / ms_step) if per_view_ms else None,
         "per_view_images_identical": per_view_equal,
         "raster_fwd_ms": fwd_ms,
         "raster_bwd_ms": bwd_ms,
+        "without_pair_cache": recompute,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "optimizer": optimizer,
         "paper_context": "218.87 FPS forward-only full pipeline, 100k random primitives, RTX 4090 (App. A)",
     }
     print(json.dumps(out))
+
+
+def eager_kernel_ms(snp, rmod, torch, rast, params, images, final_T, tg, n_norm, steps):
+    """Mean forward and backward rasterizer kernel times (ms) over a few
+    eager steps, from the HIP events the library records on the launch
+    stream around each launch."""
+    rmod.kernel_timing(True)
+    fwd_ms, bwd_ms = [], []
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dL = torch.empty_like(images)
+    grads = snp.zeros_like_params(params)
+    rast.step(params, images, final_T, tg, n_norm, loss, dL, grads)
+    for _ in range(max(3, min(steps, 5))):
+        rast.step(params, images, final_T, tg, n_norm, loss, dL, grads)
+        f, b = rmod.kernel_timing_read()
+        fwd_ms.append(f)
+        bwd_ms.append(b)
+    rmod.kernel_timing(False)
+    rast.read_status()
+    return float(np.mean(fwd_ms)), float(np.mean(bwd_ms))
+
+
+def adam_leg(snp, torch, params):
+    """One Adam step over every parameter group (one launch), timed."""
+    from paper_2510_08491_amd import train as TR
+    grads = {k: torch.randn_like(v) * 1e-3 for k, v in params.items() if k in TR.PAPER_LRS}
+    opt_params = {k: v.clone() for k, v in params.items() if k in TR.PAPER_LRS}
+    opt = TR.Adam(opt_params)
+    n_elems = sum(v.numel() for v in opt_params.values())
+    opt.step(grads)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        opt.step(grads)
+    e1.record()
+    torch.cuda.synchronize()
+    adam_ms = e0.elapsed_time(e1) / 5
+    adam_bytes = 28 * n_elems  # read param, grad, m, v; write param, m, v (float32)
+    del opt, opt_params, grads
+    torch.cuda.empty_cache()
+    return {"kernel": "adam (all groups, one launch)", "ms": round(adam_ms, 4), "elements": n_elems,
+            "bytes": adam_bytes, "GB_per_s": round(adam_bytes / (adam_ms * 1e-3) / 1e9, 1),
+            "frac_of_hbm_peak": round(adam_bytes / (adam_ms * 1e-3) / 8e12, 4)}
+
+
+def per_view_leg(snp, torch, cfg, scene, cams, params, tg, n_norm, img_batched, a):
+    """The same step as V separate pipelines of plain launches (one camera
+    each, no graph, no persistent grid, the same kernels and tile shape).
+    Returns (ms per step, images bitwise equal to the batched ones)."""
+    cfg_pv = snp.RenderConfig(**{**cfg.__dict__, "persistent": 0})
+    rv = []
+    for c in cams:
+        r = snp.Rasterizer(cfg_pv, scene["P"], [c])
+        r._alloc(int(r.prepare(params) * 1.1) + 4096)
+        rv.append(r)
+    offs = np.cumsum([0] + [c.width * c.height for c in cams])
+    outs = [r.new_images() for r in rv]
+    dls = [torch.empty_like(o[0]) for o in outs]
+    losses = [torch.zeros(1, dtype=torch.float64, device="cuda") for _ in rv]
+    pv_grads = snp.zeros_like_params(params)
+
+    def per_view_step():
+        for g in pv_grads.values():
+            g.zero_()
+        for v, r in enumerate(rv):
+            r.preprocess(params)
+            r.bin()
+            r.sort()
+            r.forward(params, outs[v][0], outs[v][1])
+            r.loss_l1(outs[v][0], tg[3 * offs[v]:3 * offs[v + 1]], n_norm, losses[v], dls[v])
+            r.backward(params, outs[v][0], dls[v], pv_grads)
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(a.warmup):
+        per_view_step()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(a.steps):
+        per_view_step()
+    e1.record()
+    torch.cuda.synchronize()
+    for r in rv:
+        r.read_status()
+    ms = e0.elapsed_time(e1) / a.steps
+    equal = all(torch.equal(outs[v][0], img_batched[3 * offs[v]:3 * offs[v + 1]]) for v in range(len(cams)))
+    del rv, outs, dls
+    torch.cuda.empty_cache()
+    return ms, bool(equal)
+
+
+def oracle_check(scene, cams, cfg, images, tile_pairs, max_views):
+    """One tile per view (up to max_views views, spread over the list),
+    chosen by a seeded draw among the tiles whose oracle instance count is
+    at least the view's median (the deep lists): the oracle renders the
+    tile's window in float64 (oracle.render.render_window), compared with
+    the batched step's image there and with the GPU's hit-pair count of that
+    tile.  Returns the largest image and transmittance-free colour error and
+    both pair totals."""
+    from oracle.keys import project_all
+    from oracle.render import RenderOptions, render_window
+
+    opts = RenderOptions(z_near=cfg.z_near, t_eps=cfg.t_eps, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
+                         bg=tuple(cfg.bg))
+    rng = np.random.default_rng(4)
+    img = images.cpu().numpy()
+    V = len(cams)
+    views = sorted(set(np.linspace(0, V - 1, min(V, max_views)).round().astype(int).tolist()))
+    tw, th = cfg.tile_w, cfg.tile_h
+    pix_off = np.cumsum([0] + [c.width * c.height for c in cams])
+    tile_off = np.cumsum([0] + [((c.width + tw - 1) // tw) * ((c.height + th - 1) // th) for c in cams])
+    t0 = time.perf_counter()
+    worst, gpu_pairs, ora_pairs, npix, eq = 0.0, 0, 0, 0, True
+    picked = []
+    for v in views:
+        cam = cams[v]
+        proj = project_all(scene, cam, tw, th, cfg.z_near)
+        ntx, nty = (cam.width + tw - 1) // tw, (cam.height + th - 1) // th
+        # instances per tile from the oracle's tile rectangles (2-D difference array)
+        tr = proj["trect"][proj["nonempty"]]
+        diff = np.zeros((nty + 1, ntx + 1), np.int64)
+        np.add.at(diff, (tr[:, 2], tr[:, 0]), 1)
+        np.add.at(diff, (tr[:, 2], tr[:, 1] + 1), -1)
+        np.add.at(diff, (tr[:, 3] + 1, tr[:, 0]), -1)
+        np.add.at(diff, (tr[:, 3] + 1, tr[:, 1] + 1), 1)
+        counts = diff.cumsum(0).cumsum(1)[:nty, :ntx].ravel()
+        cand = np.nonzero(counts >= max(1, np.median(counts)))[0]
+        t = int(rng.choice(cand))
+        ty, tx = divmod(t, ntx)
+        x0, y0 = tx * tw, ty * th
+        w, h = min(tw, cam.width - x0), min(th, cam.height - y0)
+        ref = render_window(scene, cam, x0, y0, w, h, opts, proj=proj)
+        view_img = img[3 * pix_off[v]:3 * pix_off[v + 1]].reshape(cam.height, cam.width, 3)
+        err = float(np.max(np.abs(view_img[y0:y0 + h, x0:x0 + w] - ref["image"])))
+        worst = max(worst, err)
+        gp = int(tile_pairs[tile_off[v] + t])
+        gpu_pairs += gp
+        ora_pairs += int(ref["hit_pairs"])
+        eq = eq and gp == int(ref["hit_pairs"])
+        npix += w * h
+        picked.append([int(v), int(t), int(ref["primitives"])])
+    return {"views": len(views), "tiles": len(picked), "pixels": npix, "max_img_err": worst,
+            "hit_pairs_gpu": gpu_pairs, "hit_pairs_oracle": ora_pairs, "hit_pairs_equal": bool(eq),
+            "tiles_view_tile_primitives": picked, "seconds": round(time.perf_counter() - t0, 1)}
 
 
 def _fps(snp, torch, scene, cams, cfg, a, label):
@@ -425,13 +562,14 @@ def forward_fps(a):
     print(json.dumps(out))
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, pair_cache):
     """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary in profiles/ (scaled by a copy kernel of known size),
-    or None when there is none for this workload or the rasterizer source
-    has changed since the counters were taken."""
+    or None when there is none for this workload and pair-cache mode, or the
+    rasterizer source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{workload.lower()}_render_traffic.md")
+    suffix = "" if pair_cache else "_recompute"
+    path = os.path.join(ROOT, "profiles", f"{workload.lower()}_render_traffic{suffix}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -457,42 +595,81 @@ def workload_name(w, cams):
             "C5": "32 cameras 1600x900, 1M primitives, N=32, colour MLP W32 D3, batched fwd+bwd"}[w]
 
 
-def cpu_baseline(scene, cams, targets, budget_s):
-    """FP64 oracle forward + autograd backward on square crops of the first
-    camera, each with the primitives whose screen bounds touch the crop (the
-    only ones that contribute to it; selecting them is not timed), repeated
-    until about `budget_s` seconds of work; returns pairs/s."""
+def _oracle_crop(job):
+    """One crop: the FP64 oracle's forward (numpy) and its autograd backward
+    (torch float64) on the primitives that touch the crop.  Returns (hit
+    pairs, seconds)."""
     import torch
-    import synthetic as S
     from oracle.grad import autograd_loss_and_grads
-    from oracle.keys import project_all
     from oracle.render import RenderOptions, render_view
+    torch.set_num_threads(1)
+    sub, crop, tgt = job
+    t0 = time.perf_counter()
+    r = render_view(sub, crop, RenderOptions())
+    autograd_loss_and_grads(sub, [crop], tgt, RenderOptions())
+    return r["hit_pairs"], time.perf_counter() - t0
 
-    threads = os.cpu_count() or 1
-    torch.set_num_threads(threads)
-    cam = cams[0]
-    size = 16
-    pairs, spent, crops, prims = 0, 0.0, 0, 0
+
+def host_cores():
+    """The cores this process may run on, at most 16 (one GPU's share of
+    the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(scene, cams, targets, budget_s, workload):
+    """The FP64 oracle (numpy forward + torch float64 autograd backward) on
+    16x16-pixel crops of the workload's views, each with the primitives whose
+    screen bounds touch it (the only ones that contribute to it; selecting
+    them is not timed), one crop per worker process at a time over the
+    host's cores; about `budget_s` seconds of wall time.  Returns hit pairs
+    per wall-clock second.  Also times the 64x64, 256-primitive scene's
+    whole forward + backward in one process."""
+    import multiprocessing as mp
+    import synthetic as S
+    from oracle.keys import project_all
+
+    cores = host_cores()
     rng = np.random.default_rng(3)
-    while spent < budget_s and crops < 32:
+    size = 16
+
+    def make_job():
+        v = int(rng.integers(0, len(cams)))
+        cam = cams[v]
         x0 = int(rng.integers(cam.width // 4, 3 * cam.width // 4 - size))
         y0 = int(rng.integers(cam.height // 4, 3 * cam.height // 4 - size))
         crop = S.Camera(size, size, cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, cam.R, cam.t)
         ids = np.nonzero(project_all(scene, crop)["nonempty"])[0]
-        sub = S.subset_scene(scene, ids)
-        tgt = [targets[0][y0:y0 + size, x0:x0 + size]]
-        t0 = time.perf_counter()
-        r = render_view(sub, crop, RenderOptions())
-        autograd_loss_and_grads(sub, [crop], tgt, RenderOptions())
-        spent += time.perf_counter() - t0
-        pairs += r["hit_pairs"]
-        prims += len(ids)
-        crops += 1
-    return {"value": pairs / spent, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{crops} random {size}x{size} px crops of the central half of camera 0 "
-                      f"({cam.width}x{cam.height}), each with the primitives whose bounds touch it "
-                      f"({prims // max(crops, 1)} on average of {scene['P']}); FP64 numpy forward + torch "
-                      f"float64 autograd backward; {pairs} hit pairs in {spent:.1f} s"}
+        return S.subset_scene(scene, ids), crop, [targets[v][y0:y0 + size, x0:x0 + size]]
+
+    # calibrate the crop count on one crop, then run them all in the pool
+    probe = make_job()
+    pairs0, sec0 = _oracle_crop(probe)
+    n_jobs = max(cores, int(round(budget_s / max(sec0, 1e-3))) * cores)
+    n_jobs = min(n_jobs, 8 * cores)
+    jobs = [make_job() for _ in range(n_jobs)]
+    prims = sum(j[0]["P"] for j in jobs)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_crop, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    pairs = sum(r[0] for r in res)
+    busy = sum(r[1] for r in res)
+    # the smallest workload, whole: 64x64, 256 primitives, N = 8, constant colour
+    _, s1, c1, t1 = S.make_workload("C1")
+    p1, sec1 = _oracle_crop((s1, c1[0], t1))
+    return {"value": pairs / wall, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_jobs} random {size}x{size} px crops of the central half of random views of the "
+                      f"{workload} workload, each with the primitives whose bounds touch it "
+                      f"({prims // max(n_jobs, 1)} on average of {scene['P']}); FP64 numpy forward + torch "
+                      f"float64 autograd backward; {cores} worker processes (one thread each, "
+                      f"{busy / wall:.1f} busy on average); {pairs} hit pairs in {wall:.1f} s wall",
+            "c1_full_fwd_bwd": {"seconds": round(sec1, 3), "hit_pairs": int(p1), "pairs_per_s": p1 / sec1,
+                                "threads": 1}}
 
 
 if __name__ == "__main__":

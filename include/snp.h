@@ -197,6 +197,7 @@ typedef struct {
   int32_t total_tiles;    /* tiles over all views */
   size_t ahat_cache;      /* fwd_cache = 1: float per (instance, tile pixel), else unused */
   size_t ahat_cache_bytes; /* 0 when fwd_cache = 0; cached instances x tile pixels x 4 */
+  size_t tile_pairs;      /* per global tile uint32: hit pairs counted by a forward with count_pairs != 0 */
 } snp_layout;
 
 /* Size and layout of the workspace for P primitives seen by V cameras with
@@ -243,7 +244,8 @@ snp_status snp_sort(const snp_config* cfg, int64_t P, int32_t V, const snp_camer
 /* Forward rasterizer (Eq. 3-4, 7-9).  images: sum_v H_v W_v 3 floats;
  * final_T: sum_v H_v W_v floats.  count_pairs != 0 also counts the hit pairs
  * (pixel, primitive with the ray meeting the ellipsoid, pixel not yet
- * terminated) into the workspace counter [2]. */
+ * terminated) into the workspace counter [2], and per tile into the
+ * layout.tile_pairs array (cleared by the same call). */
 snp_status snp_render_forward(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
                               void* ws, const snp_layout* layout, float* images, float* final_T, int32_t count_pairs,
                               hipStream_t stream);

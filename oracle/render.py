@@ -144,6 +144,42 @@ def render_pixels(scene, cam, cols, rows, opts: RenderOptions = RenderOptions(),
     return out_c, out_t, out_h
 
 
+def window_camera(cam, x0, y0, w, h):
+    """The camera of a w x h window of `cam`'s image whose top-left pixel is
+    (x0, y0): the same pose and focal lengths, the principal point moved by
+    (-x0, -y0).  Its pixel (i, j) has the ray of `cam`'s pixel (x0+i, y0+j)
+    (exactly, when cx - x0 and cy - y0 are exact in float32)."""
+    import dataclasses as _dc
+    return _dc.replace(cam, width=int(w), height=int(h), cx=float(cam.cx) - x0, cy=float(cam.cy) - y0)
+
+
+def render_window(scene, cam, x0, y0, w, h, opts: RenderOptions = RenderOptions(), proj=None):
+    """Image, transmittance and hit-pair count of the w x h window at (x0, y0)
+    of view `cam`, without rendering the whole view: the primitives whose
+    rectangle in `cam` meets the window (in index order, so their depth
+    order is kept) rendered through the window's camera.  Every pixel a
+    primitive hits lies inside its rectangle, so the window's pixels see
+    exactly the pairs they see in the full view.  Returns
+    dict(image (h,w,3), T (h,w), hit_pairs, primitives)."""
+    if proj is None:
+        proj = project_all(scene, cam, 16, 16, opts.z_near)
+    r = proj["rect"]
+    meets = proj["nonempty"] & (r[:, 0] <= x0 + w - 1) & (r[:, 1] >= x0) & (r[:, 2] <= y0 + h - 1) & (r[:, 3] >= y0)
+    ids = np.nonzero(meets)[0]
+    sub = dict(scene)
+    for k, v in scene.items():
+        if isinstance(v, np.ndarray) and v.ndim >= 1 and v.shape[0] == scene["P"] and k != "P":
+            sub[k] = v[ids]
+    sub["P"] = len(ids)
+    wcam = window_camera(cam, x0, y0, w, h)
+    if len(ids) == 0:
+        T = np.ones((h, w))
+        return dict(image=T[..., None] * np.asarray(opts.bg, dtype=np.float64), T=T, hit_pairs=0, primitives=0)
+    out = render_view(sub, wcam, opts)
+    out["primitives"] = len(ids)
+    return out
+
+
 def l1_loss(images, targets):
     """Mean absolute error over all views, pixels and channels, and its
     gradient with respect to each image (sign(C - target) / count)."""

@@ -44,7 +44,7 @@ class SnpLayout(C.Structure):
                 ("bytes", "cams", "table", "records", "rects", "depth_bits", "tile_counts", "offsets", "keys",
                  "values", "ranges", "counters", "gview", "gtable", "loss", "disc_coef")] + \
                [("capacity", C.c_int64), ("table_stride", C.c_int32), ("total_tiles", C.c_int32),
-                ("ahat_cache", C.c_size_t), ("ahat_cache_bytes", C.c_size_t)]
+                ("ahat_cache", C.c_size_t), ("ahat_cache_bytes", C.c_size_t), ("tile_pairs", C.c_size_t)]
 
 
 class SnpAdamGroup(C.Structure):

@@ -135,6 +135,7 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   if (pl->tile_order_on && tiles > sort_n) sort_n = tiles;
   pl->sort_scratch = take(sort_scratch_bytes(sort_n));
   L.ranges = take(sizeof(uint32_t) * 2 * (size_t)tiles);
+  L.tile_pairs = take(sizeof(uint32_t) * (size_t)tiles);
   const size_t tn = pl->tile_order_on ? (size_t)tiles : 0;
   for (int k = 0; k < 2; ++k) {
     pl->tkeys[k] = take(sizeof(unsigned long long) * tn);
@@ -332,6 +333,8 @@ static snp_status do_sort(const Plan& pl, void* ws, hipStream_t st) {
   return SNP_OK;
 }
 
+static int64_t L_tiles(const Plan& pl) { return pl.L.total_tiles; }
+
 static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const Plan& pl, void* ws) {
   const snp_layout& L = pl.L;
   RasterArgs a;
@@ -353,6 +356,7 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   a.ahat_cache = cfg->fwd_cache ? wsp<float>(ws, L.ahat_cache) : nullptr;
   a.cache_instances = cfg->fwd_cache ? (int64_t)(L.ahat_cache_bytes / (sizeof(float) * cfg->tile_w * cfg->tile_h)) : 0;
   a.counters = wsp<unsigned long long>(ws, L.counters);
+  a.tile_pairs = wsp<uint32_t>(ws, L.tile_pairs);
   a.t_eps = cfg->t_eps;
   a.alpha_min = cfg->alpha_min;
   a.alpha_max = cfg->alpha_max;
@@ -389,6 +393,7 @@ static snp_status do_forward(const snp_config* cfg, int64_t P, int32_t V, const 
   a.images = images;
   a.final_T = final_T;
   if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_FWD, st));
+  if (count) SNP_HIP(fill_u32(a.tile_pairs, L_tiles(pl), 0u, st));
   timer_mark(0, st);
   if (gaussian(cfg))
     SNP_HIP(launch_render_fwd_gauss(cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0, count != 0, a,
@@ -555,7 +560,7 @@ static bool same_layout(const snp_layout& a, const snp_layout& b) {
          a.counters == b.counters && a.gview == b.gview && a.gtable == b.gtable && a.loss == b.loss &&
          a.disc_coef == b.disc_coef &&
          a.capacity == b.capacity && a.table_stride == b.table_stride && a.total_tiles == b.total_tiles &&
-         a.ahat_cache == b.ahat_cache && a.ahat_cache_bytes == b.ahat_cache_bytes;
+         a.ahat_cache == b.ahat_cache && a.ahat_cache_bytes == b.ahat_cache_bytes && a.tile_pairs == b.tile_pairs;
 }
 
 // Rebuilds the plan of a call from its arguments and checks it against the

@@ -108,17 +108,18 @@ struct PixelBlock {
   }
 };
 
-// LDS stage of one batch; the backward also stages the float64
-// discriminant coefficients (3 float4 = 6 doubles per instance).
-template <int N, bool BWD, int B>
+// LDS stage of one batch: records, tables and the float64 discriminant
+// coefficients (3 float4 = 6 doubles per instance) that decide the hits
+// near the silhouette.
+template <int N, int B>
 struct Stage {
   static constexpr int NB = B;
   static constexpr int TS = 5 * N + 4;
-  static constexpr int DQ4 = BWD ? 3 : 0;
+  static constexpr int DQ4 = 3;
   static constexpr int F = 6 + TS / 4 + DQ4;  // float4 per instance
   float4 rec[B][6];
   float4 tab[B][TS / 4];
-  float4 dq[BWD ? B : 1][3];
+  float4 dq[B][3];
   int4 rect[B];  // the primitive's inclusive pixel rectangle in this view
   uint32_t id[B];
 };
@@ -129,8 +130,8 @@ struct Stage {
 // barrier (at the end) suffices.  The caller's previous barrier (the end of
 // the previous batch, or the work-queue fetch) guarantees nobody still
 // reads the stage.
-template <int N, bool BWD, int NT, int B>
-__device__ __forceinline__ void stage_batch(Stage<N, BWD, B>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
+template <int N, int NT, int B>
+__device__ __forceinline__ void stage_batch(Stage<N, B>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
   const int64_t vbase = (int64_t)v * a.P;
   for (int t = threadIdx.x; t < nb; t += NT) {
     const uint32_t p = a.values[b0 + t];
@@ -140,8 +141,8 @@ __device__ __forceinline__ void stage_batch(Stage<N, BWD, B>& S, const RasterArg
   const float4* rec4 = reinterpret_cast<const float4*>(a.records);
   const float4* tab4 = reinterpret_cast<const float4*>(a.table);
   const float4* dq4 = reinterpret_cast<const float4*>(a.disc_coef);
-  constexpr int F = Stage<N, BWD, B>::F;
-  constexpr int T4 = Stage<N, BWD, B>::TS / 4;
+  constexpr int F = Stage<N, B>::F;
+  constexpr int T4 = Stage<N, B>::TS / 4;
   for (int idx = threadIdx.x; idx < nb * F; idx += NT) {
     const int j = idx / F, c = idx - j * F;
     const uint32_t p = a.values[b0 + j];
@@ -149,7 +150,7 @@ __device__ __forceinline__ void stage_batch(Stage<N, BWD, B>& S, const RasterArg
       S.rec[j][c] = rec4[(vbase + p) * 6 + c];
     else if (c < 6 + T4)
       S.tab[j][c - 6] = tab4[(int64_t)p * T4 + (c - 6)];
-    else if (BWD)
+    else
       S.dq[j][c - 6 - T4] = dq4[(vbase + p) * 3 + (c - 6 - T4)];
   }
   __syncthreads();
@@ -163,11 +164,21 @@ struct PairGeom {
   float p0, p1, p2, e0, e1, e2;
 };
 
-// dq: float64 discriminant coefficients (backward only, else null): pairs
-// within 1% of A of the silhouette take their discriminant from them.
+// dq: the float64 coefficients of the discriminant as a quadratic in the
+// pixel offset from the record's reference pixel.  The float32 discriminant
+// A - M is off by about 1e-6 |o'| A (o' = the camera centre in the
+// primitive's unit-sphere frame: the rounding of m' = o' x d' grows with it),
+// which stays far below 1% of A up to |o'| ~ 1e4, i.e. a camera 10^4
+// semi-axes away; so its sign decides a hit everywhere outside that band; inside
+// it the float64 form, evaluated at the exact offset (the difference of two
+// floats is exact in float64), decides the hit and gives the value.  The
+// oracle decides with its own float64 discriminant, so the hit pairs of both
+// sides are the same pairs (up to ties within float64 rounding).  The same
+// function serves the forward and both phases of the backward, so they agree
+// on every hit.
 __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
                                           const float4& r4, const float4& r5, float px, float py, PairGeom& g,
-                                          const double* dq = nullptr) {
+                                          const double* dq) {
   g.dx = px - r0.w;
   g.dy = py - r1.w;
   g.d0 = __builtin_fmaf(r2.x, g.dy, __builtin_fmaf(r1.x, g.dx, r0.x));
@@ -179,15 +190,17 @@ __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, co
   g.A = __builtin_fmaf(g.d2, g.d2, __builtin_fmaf(g.d1, g.d1, g.d0 * g.d0));
   const float M = __builtin_fmaf(g.m2, g.m2, __builtin_fmaf(g.m1, g.m1, g.m0 * g.m0));
   float disc = g.A - M;
-  if (dq && fabsf(disc) < 0.01f * g.A) {
-    const double x = g.dx, y = g.dy;
-    disc = (float)(dq[0] + x * (dq[1] + dq[3] * x + dq[4] * y) + y * (dq[2] + dq[5] * y));
+  bool hit = disc > 0.f;
+  if (fabsf(disc) < 0.01f * g.A) {
+    const double x = (double)px - (double)r0.w, y = (double)py - (double)r1.w;
+    const double dd = dq[0] + x * (dq[1] + dq[3] * x + dq[4] * y) + y * (dq[2] + dq[5] * y);
+    hit = dd > 0.0;
+    disc = (float)dd;
   }
-  const bool hit = disc > 0.f;
   // every field stays finite for a miss (H = 0, e' = 0), so loops over the
   // hidden units can run without per-pixel branches and be masked afterwards
   g.rA = fast_rcp(g.A);
-  g.sq = fast_sqrt(hit ? disc : 0.f);
+  g.sq = fast_sqrt(hit ? fmaxf(disc, 0.f) : 0.f);
   g.H = g.sq * g.rA;
   g.p0 = (g.d1 * g.m2 - g.d2 * g.m1) * g.rA;
   g.p1 = (g.d2 * g.m0 - g.d0 * g.m2) * g.rA;
@@ -203,6 +216,12 @@ __device__ __forceinline__ float alpha_of(float ahat, float alpha_max) {
   return fminf(al, alpha_max);
 }
 
+// adds the wave's total of v to *slot (one atomic per wave)
+__device__ __forceinline__ void count_tile_pairs(uint32_t* slot, uint32_t v) {
+  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(slot, v);
+}
+
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
@@ -210,7 +229,7 @@ template <int N, int TW, int TH, int PPL, bool PERSIST, bool COUNT>
 __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH / PPL;
   constexpr int FB = fwd_batch<N>();
-  __shared__ Stage<N, false, FB> S;
+  __shared__ Stage<N, FB> S;
   __shared__ int s_item;
   unsigned long long npairs = 0, nlive = 0;
   int item = blockIdx.x;
@@ -239,15 +258,17 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
       C0[q] = C1[q] = C2[q] = 0.f;
       done[q] = pb.pix[q] < 0;
     }
+    uint32_t tpairs = 0;  // this thread's hit pairs in this tile (COUNT)
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += FB) {
       const int nb = (int)min((uint32_t)FB, end - b0);
-      stage_batch<N, decltype(S)::DQ4 != 0, NT, decltype(S)::NB>(S, a, v, b0, nb);
+      stage_batch<N, NT, FB>(S, a, v, b0, nb);
       for (int j = 0; j < nb; ++j) {
         const int4 rc = S.rect[j];
         if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
+        const double* dqj = reinterpret_cast<const double*>(S.dq[j]);
         PairGeom g[PPL];
         bool hit[PPL];
         bool any = false;
@@ -255,11 +276,11 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
           // geometry for every lane (finite for misses), so the unit loops can run unmasked
-          const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q]);
+          const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[q], pb.pyc[q], g[q], dqj);
           hit[q] = !done[q] && gh;
           any |= hit[q];
           Q[q] = 0.f;
-          if (COUNT) npairs += hit[q] ? 1 : 0;
+          if (COUNT) tpairs += hit[q] ? 1u : 0u;
         }
         if (__ballot(any) == 0) continue;  // wave-uniform skip
         const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
@@ -306,6 +327,10 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
 #pragma unroll
       for (int q = 0; q < PPL; ++q) mine = mine && done[q];
       if (__syncthreads_and(mine)) break;
+    }
+    if (COUNT) {
+      npairs += tpairs;
+      count_tile_pairs(a.tile_pairs + tile, tpairs);
     }
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
@@ -386,6 +411,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_gauss_kernel(RasterA
     }
     const int64_t vbase = (int64_t)v * a.P;
     const float4* rec4 = reinterpret_cast<const float4*>(a.records);
+    uint32_t tpairs = 0;  // this thread's hit pairs in this tile (COUNT)
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NT) {
       const int nb = (int)min((uint32_t)NT, end - b0);
@@ -406,7 +432,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_gauss_kernel(RasterA
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
           const bool hit = !done[q] && px[q] >= rc.x && px[q] <= rc.y && py[q] >= rc.z && py[q] <= rc.w;
-          if (COUNT) npairs += hit ? 1 : 0;
+          if (COUNT) tpairs += hit ? 1u : 0u;
           const float dx = pb.pxc[q] - g0.x, dy = pb.pyc[q] - g0.y;
           // log2 of the Gaussian factor; <= 0 for the positive definite conic
           const float pw = fminf(__builtin_fmaf(dx, __builtin_fmaf(g1.x, dy, g0.z * dx), g1.y * dy * dy), 0.f);
@@ -426,6 +452,10 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_gauss_kernel(RasterA
 #pragma unroll
       for (int q = 0; q < PPL; ++q) mine = mine && done[q];
       if (__syncthreads_and(mine)) break;
+    }
+    if (COUNT) {
+      npairs += tpairs;
+      count_tile_pairs(a.tile_pairs + tile, tpairs);
     }
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
@@ -579,7 +609,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
   constexpr int NW = NT / 64;
   constexpr int TS = 5 * N + 4;
   constexpr int ACC = TS + kGViewFloats;  // per instance: table grads, then record grads
-  __shared__ Stage<N, true, NB> S;
+  __shared__ Stage<N, NB> S;
   __shared__ float s_acc[NB][ACC];
   __shared__ uint32_t s_cnt[NB][NW];  // live pairs per (instance, wave)
   __shared__ uint16_t s_pix[NB][NT];
@@ -623,7 +653,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
       if (threadIdx.x < NB * NW) (&s_cnt[0][0])[threadIdx.x] = 0u;
-      stage_batch<N, true, NT, NB>(S, a, v, b0, nb);
+      stage_batch<N, NT, NB>(S, a, v, b0, nb);
       // ---------------- phase 1: pixels ----------------
       // One instance for this thread's pixel.  `cached`: the integral comes
       // from the forward's store (ahc) instead of the density MLP.
@@ -633,7 +663,8 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
         PairGeom g;
-        const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[0], pb.pyc[0], g);
+        const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[0], pb.pyc[0], g,
+                                  reinterpret_cast<const double*>(S.dq[j]));
         const bool hit = !done && gh;
         if (__ballot(hit) == 0) return;  // wave-uniform
         float ahat, QB = 0.f;  // QB = Q + b2 (recomputed path only)

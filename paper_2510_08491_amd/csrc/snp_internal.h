@@ -210,11 +210,12 @@ struct RasterArgs {
   const float* dL;        // backward: d loss / d images
   float* gview;
   float* gtable;
-  const double* disc_coef;  // backward: float64 discriminant near silhouettes
+  const double* disc_coef;  // float64 discriminant coefficients: hit decisions near silhouettes
   int64_t cache_instances;  // leading instances covered by ahat_cache
   float* ahat_cache;        // per (instance, tile pixel) integral: the forward writes it,
                             // the backward reads it (null: the backward re-evaluates)
   unsigned long long* counters;
+  uint32_t* tile_pairs;     // forward with pair counting: hit pairs per global tile
   float t_eps, alpha_min, alpha_max;
   float bg0, bg1, bg2;
 };

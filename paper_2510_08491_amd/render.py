@@ -122,6 +122,10 @@ class Rasterizer:
         self.total_pixels = sum(self.pixels)
         self.layout = None
         self.ws = None
+        # bumped by every call that rewrites the workspace (the stages, a
+        # step, a graph replay, a re-allocation); a backward checks that the
+        # workspace still holds the forward it differentiates
+        self.generation = 0
         self._alloc(capacity if capacity is not None else max(1 << 16, 8 * self.P))
 
     # -- workspace ---------------------------------------------------------------
@@ -134,6 +138,7 @@ class Rasterizer:
         return lay
 
     def _alloc(self, capacity: int):
+        self.generation += 1
         self.ws = None
         lay = self._layout(capacity, self.cfg.fwd_cache)
         if lay.ahat_cache_bytes:
@@ -183,6 +188,11 @@ class Rasterizer:
     def ranges(self):
         return self._view("ranges", torch.int32, 2 * self.layout.total_tiles).view(-1, 2)
 
+    def tile_pairs(self):
+        """Hit pairs per global tile, counted by the last forward with
+        count_pairs=True (tiles of view 0 first, row-major in each view)."""
+        return self._view("tile_pairs", torch.int32, self.layout.total_tiles)
+
     def rects(self):
         return self._view("rects", torch.int32, 4 * self.V * self.P).view(self.V, self.P, 4)
 
@@ -201,14 +211,17 @@ class Rasterizer:
         return pr
 
     def preprocess(self, params):
+        self.generation += 1
         L.check(L.lib().snp_preprocess(C.byref(self.ccfg), C.byref(self._prims(params)), self.V, self.ccams,
                                        self.ws_ptr, C.byref(self.layout), _stream()), "snp_preprocess")
 
     def bin(self):
+        self.generation += 1
         L.check(L.lib().snp_bin(C.byref(self.ccfg), self.P, self.V, self.ccams, self.ws_ptr, C.byref(self.layout),
                                 _stream()), "snp_bin")
 
     def sort(self):
+        self.generation += 1
         L.check(L.lib().snp_sort(C.byref(self.ccfg), self.P, self.V, self.ccams, self.ws_ptr, C.byref(self.layout),
                                  _stream()), "snp_sort")
 
@@ -247,6 +260,7 @@ class Rasterizer:
         return img, T
 
     def forward(self, params, images, final_T, count_pairs=False):
+        self.generation += 1
         L.check(L.lib().snp_render_forward(C.byref(self.ccfg), C.byref(self._prims(params)), self.V, self.ccams,
                                            self.ws_ptr, C.byref(self.layout), _ptr(images), _ptr(final_T),
                                            1 if count_pairs else 0, _stream()), "snp_render_forward")
@@ -274,6 +288,7 @@ class Rasterizer:
                                             _stream()), "snp_render_backward")
 
     def step(self, params, images, final_T, targets, n_norm, loss_out, dL, grads):
+        self.generation += 1
         g = self.grads_struct(grads)
         L.check(L.lib().snp_step(C.byref(self.ccfg), C.byref(self._prims(params)), self.V, self.ccams, self.ws_ptr,
                                  C.byref(self.layout), _ptr(images), _ptr(final_T), _ptr(targets), float(n_norm),
@@ -307,7 +322,12 @@ def zeros_like_params(params: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor
 
 class GraphStep:
     """A whole training step (zero grads, preprocess, bin, sort, forward, L1
-    loss, backward) captured once into a HIP graph and replayed."""
+    loss, backward) captured once into a HIP graph and replayed.
+
+    The instance count is only known on the device: a replay whose tile
+    instances exceed the workspace capacity, or whose density phases leave
+    the supported range, only sets a device flag.  Call check() after
+    replays (it synchronises) before trusting their results."""
 
     def __init__(self, rast: Rasterizer, params, targets: torch.Tensor, n_norm: float):
         self.rast = rast
@@ -328,7 +348,14 @@ class GraphStep:
         self.handle = h
 
     def launch(self):
+        self.rast.generation += 1
         L.check(L.lib().snp_graph_launch(self.handle, _stream()), "snp_graph_launch")
+
+    def check(self):
+        """Synchronises and raises SnpError if a replay overflowed the
+        workspace (SNP_ERR_CAPACITY) or met a phase out of range
+        (SNP_ERR_RANGE)."""
+        self.rast.read_status()
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -357,6 +384,7 @@ class ForwardGraph:
         self.handle = h
 
     def launch(self):
+        self.rast.generation += 1
         L.check(L.lib().snp_graph_launch(self.handle, _stream()), "snp_graph_launch")
 
     def __del__(self):
@@ -369,7 +397,14 @@ class ForwardGraph:
 class SplatRender(torch.autograd.Function):
     """images = render(params); backward gives d loss / d params through the
     hand-written adjoint.  Inputs: the Rasterizer, then the parameter tensors
-    in PARAM_KEYS order (None for absent ones)."""
+    in PARAM_KEYS order (None for absent ones).
+
+    The backward reads the workspace the forward left (sorted lists, records,
+    the pair cache).  If anything has rewritten that workspace since -- a
+    second render on the same Rasterizer, a step, a re-allocation -- the
+    backward first runs preprocess, bin, sort and forward again from the
+    saved parameters (the forward is deterministic, so this restores the
+    same workspace and images bit for bit)."""
 
     @staticmethod
     def forward(ctx, rast: Rasterizer, *tensors):
@@ -379,6 +414,7 @@ class SplatRender(torch.autograd.Function):
         images, final_T = rast.new_images()
         rast.forward(params, images, final_T)
         ctx.rast = rast
+        ctx.generation = rast.generation
         ctx.keys = [k for k, t in zip(PARAM_KEYS, tensors) if t is not None]
         ctx.save_for_backward(images, *[params[k] for k in ctx.keys])
         ctx.mark_non_differentiable(final_T)
@@ -388,8 +424,14 @@ class SplatRender(torch.autograd.Function):
     def backward(ctx, dL_dimages, _dT):
         images, *saved = ctx.saved_tensors
         params = dict(zip(ctx.keys, saved))
+        rast = ctx.rast
+        if rast.generation != ctx.generation:
+            rast.prepare(params)
+            again, T = rast.new_images()
+            rast.forward(params, again, T)
+            images = again
         grads = zeros_like_params(params)
-        ctx.rast.backward(params, images, dL_dimages.contiguous(), grads)
+        rast.backward(params, images, dL_dimages.contiguous(), grads)
         out = [None]
         for k in PARAM_KEYS:
             out.append(grads.get(k) if k in params else None)

@@ -32,9 +32,13 @@ def resolution_class(cams) -> str:
     return f"V{len(cams)}_MP{max(1, round(px / 1e6))}"
 
 
-def key_of(N: int, color_mode: int, cams) -> str:
+def key_of(N: int, color_mode: int, cams, fwd_cache: int = 1) -> str:
+    """Workload class: density width, colour mode, resolution class, and
+    whether the backward reads the forward's pair cache (the two backwards
+    favour different batch sizes)."""
     arch = "gfx950"
-    return f"{arch}/N{N}/cm{color_mode}/{resolution_class(cams)}"
+    mode = "" if fwd_cache else "/recompute"
+    return f"{arch}/N{N}/cm{color_mode}/{resolution_class(cams)}{mode}"
 
 
 def _load() -> Dict:
@@ -44,9 +48,9 @@ def _load() -> Dict:
     return {}
 
 
-def lookup(N: int, color_mode: int, cams) -> Optional[Tuple[int, int, int, int]]:
+def lookup(N: int, color_mode: int, cams, fwd_cache: int = 1) -> Optional[Tuple[int, int, int, int]]:
     """(tile_w, tile_h, px_per_lane, bwd_batch) tuned for this class, or None."""
-    entry = _load().get(key_of(N, color_mode, cams))
+    entry = _load().get(key_of(N, color_mode, cams, fwd_cache))
     if not entry:
         return None
     return tuple(entry["tile"]) + (int(entry.get("bwd_batch", 0)),)
@@ -129,7 +133,7 @@ def autotune(base: RenderConfig, P: int, cams, params, targets: torch.Tensor, re
     best_shape = best[1]
     if write:
         cache = _load()
-        cache[key_of(base.n_hidden, base.color_mode, cams)] = {
+        cache[key_of(base.n_hidden, base.color_mode, cams, base.fwd_cache)] = {
             "tile": list(best_shape[:3]), "bwd_batch": best_shape[3], "ms": best[0], "candidates": results}
         with open(CACHE, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
@@ -147,6 +151,10 @@ def main(argv=None):
     ap.add_argument("--workload", default="C4")
     ap.add_argument("--out", default=None, help="also write the cache to this file")
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--fwd-cache", type=int, default=None, choices=[0, 1],
+                    help="pair-cache mode to tune for (default: 0 for C5, else 1)")
+    ap.add_argument("--shapes", default=None,
+                    help="only these tile shapes, e.g. 16x16x1,32x16x2 (default: every built shape)")
     a = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
@@ -154,13 +162,18 @@ def main(argv=None):
     from .render import params_to_device
 
     _, scene, cams, targets = S.make_workload(a.workload)
+    fwd_cache = a.fwd_cache if a.fwd_cache is not None else (0 if a.workload == "C5" else 1)
     base = RenderConfig(n_hidden=scene["N"], omega0=scene["omega0"], color_mode=scene["color_mode"],
-                        cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], persistent=1)
+                        cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], persistent=1,
+                        fwd_cache=fwd_cache)
     params = params_to_device(scene)
     tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()
-    best, _ = autotune(base, scene["P"], cams, params, tg, reps=a.reps,
+    shapes = None
+    if a.shapes:
+        shapes = [tuple(int(x) for x in sh.split("x")) for sh in a.shapes.split(",")]
+    best, _ = autotune(base, scene["P"], cams, params, tg, reps=a.reps, shapes=shapes,
                        log=lambda m: print(m, flush=True))
-    print(f"[tune] best tile for {key_of(base.n_hidden, base.color_mode, cams)}: {best}", flush=True)
+    print(f"[tune] best tile for {key_of(base.n_hidden, base.color_mode, cams, fwd_cache)}: {best}", flush=True)
     if a.out:
         with open(CACHE) as f, open(a.out, "w") as g:
             g.write(f.read())

@@ -8,7 +8,10 @@ import numpy as np
 import torch
 
 import paper_2510_08491_amd as snp
-from oracle.render import RenderOptions
+from oracle.grad import autograd_loss_and_grads
+from oracle.render import RenderOptions, render_view
+
+IMG_TOL = 1e-4
 
 
 def say(msg):
@@ -84,3 +87,51 @@ def grad_close(g, ref, rel=1e-3, elem_rel=1e-3, elem_floor=1e-2, kink=None):
         big &= ~kink
     e_rel = np.max(np.abs(g - ref)[big] / np.abs(ref[big])) if np.any(big) else 0.0
     return (err <= rel and e_rel <= elem_rel), err, e_rel
+
+
+def pairs_must_match(cfg, oracle_T_min):
+    """Hit pairs are decided in float64 on both sides, so their counts are
+    equal -- unless a pixel's transmittance came near the early-termination
+    threshold, where float32 and float64 may stop at different primitives."""
+    return cfg.t_eps == 0 or oracle_T_min > 2.0 * cfg.t_eps
+
+
+def check_images(fw, scene, cams, cfg, tol=IMG_TOL):
+    """Every view against the oracle's full render (image and T within tol),
+    and the hit-pair count (equal, see pairs_must_match)."""
+    opts = options_for(cfg)
+    pairs, tmin = 0, 1.0
+    for v, cam in enumerate(cams):
+        ref = render_view(scene, cam, opts)
+        err = np.max(np.abs(fw["images"][v] - ref["image"]))
+        terr = np.max(np.abs(fw["T"][v] - ref["T"]))
+        say(f"  view {v} {cam.width}x{cam.height}: image err {err:.2e}, T err {terr:.2e}")
+        assert err <= tol and terr <= tol
+        pairs += ref["hit_pairs"]
+        tmin = min(tmin, float(ref["T"].min()))
+    say(f"  hit pairs gpu {fw['hit_pairs']} oracle {pairs}")
+    if pairs_must_match(cfg, tmin):
+        assert fw["hit_pairs"] == pairs
+    else:
+        assert abs(fw["hit_pairs"] - pairs) <= 1e-3 * pairs + 2
+
+
+def grad_parity(scene, cams, targets, cfg, keys, ref=None, fw=None):
+    """HIP loss and gradients (through the C ABI) against the oracle's
+    float64 autograd route; `ref` may carry a precomputed (loss, grads)."""
+    fw = run_forward(scene, cams, cfg) if fw is None else fw
+    loss, g = run_backward(fw, targets)
+    if ref is None:
+        L_ref, g_ref, _ = autograd_loss_and_grads(scene, cams, targets, options_for(cfg))
+    else:
+        L_ref, g_ref = ref
+    say(f"  loss gpu {loss:.8f} oracle {L_ref:.8f}")
+    assert abs(loss - L_ref) <= 1e-5
+    bad = []
+    for k in keys:
+        ok, err, erel = grad_close(g[k], g_ref[k])
+        worst = np.unravel_index(np.argmax(np.abs(g[k] - g_ref[k])), g[k].shape)
+        say(f"  grad {k}: max err / max {err:.2e}, elementwise rel {erel:.2e}, worst at {worst}")
+        if not ok:
+            bad.append(k)
+    assert not bad, bad

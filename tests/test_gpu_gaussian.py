@@ -3,8 +3,9 @@ kernel) through the C ABI with the FP64 oracle.
 
 Bars as for the neural primitives: tile lists, sort order, rectangles, depth
 keys and tile counts bit-exact; images and transmittance within 1e-4 max
-abs; hit-pair counts equal up to pixels whose early termination (T < t_eps)
-is decided differently in float32 and float64."""
+abs; hit-pair counts equal (a Gaussian's hits are the pixels of its
+rectangle), except in scenes whose pixels come near the early-termination
+threshold, where float32 and float64 may stop at different primitives."""
 import numpy as np
 import pytest
 import torch
@@ -12,7 +13,7 @@ import torch
 import synthetic as S
 from oracle.gaussian import project_gaussians, render_pixels_gaussian, render_view_gaussian
 from oracle.keys import sorted_instances, tile_lists, tile_ranges
-from tests.gpu_helpers import config_for, options_for, run_forward, say
+from tests.gpu_helpers import config_for, options_for, pairs_must_match, run_forward, say
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +38,7 @@ def _check(fw, scene, cams, cfg):
     nonempty = ranges[:, 1] > ranges[:, 0]
     assert np.array_equal(fw["ranges"][nonempty], ranges[nonempty])
     opts = options_for(cfg)
-    pairs = 0
+    pairs, tmin = 0, 1.0
     for v, (cam, pr) in enumerate(zip(cams, projs)):
         ne = pr["nonempty"]
         assert np.array_equal(fw["tile_counts"][v], pr["n_tiles"].astype(np.int32))
@@ -49,8 +50,12 @@ def _check(fw, scene, cams, cfg):
         say(f"  view {v} {cam.width}x{cam.height}: image err {err:.2e}, T err {terr:.2e}")
         assert err <= IMG_TOL and terr <= IMG_TOL
         pairs += ref["hit_pairs"]
+        tmin = min(tmin, float(ref["T"].min()))
     say(f"  instances {fw['instances']}, hit pairs gpu {fw['hit_pairs']} oracle {pairs}")
-    assert abs(fw["hit_pairs"] - pairs) <= 1e-3 * pairs + 2
+    if pairs_must_match(cfg, tmin):
+        assert fw["hit_pairs"] == pairs
+    else:
+        assert abs(fw["hit_pairs"] - pairs) <= 1e-3 * pairs + 2
 
 
 @pytest.mark.parametrize("tile,persistent,bin_order", [((16, 16, 1), 0, 2), ((16, 16, 2), 1, 1), ((16, 16, 4), 0, 1),

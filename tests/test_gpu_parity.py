@@ -3,8 +3,9 @@
 Bars: tile lists, sort order, rectangles and depth keys bit-exact; images and
 transmittance within 1e-4 max abs; gradients within 1e-3 (max error over a
 tensor relative to its largest entry, and elementwise on entries above 1% of
-it); hit-pair counts equal up to silhouette pixels whose float32 and float64
-discriminants disagree in sign."""
+it); hit-pair counts equal (both sides decide a hit with a float64
+discriminant near the silhouette), except in scenes whose pixels come near
+the early-termination threshold."""
 import numpy as np
 import pytest
 import torch
@@ -13,11 +14,11 @@ import synthetic as S
 from oracle.grad import autograd_loss_and_grads
 from oracle.keys import project_all, sorted_instances, tile_lists, tile_ranges
 from oracle.render import render_pixels, render_view
-from tests.gpu_helpers import config_for, grad_close, options_for, run_backward, run_forward, say
+from tests.gpu_helpers import (IMG_TOL, check_images, config_for, grad_close, grad_parity, options_for,
+                               run_backward, run_forward, say)
 
 pytestmark = pytest.mark.gpu
 
-IMG_TOL = 1e-4
 
 
 @pytest.fixture(autouse=True)
@@ -46,20 +47,6 @@ def _check_keys(fw, scene, cams, cfg):
         assert np.array_equal(fw["depth_bits"][v][ne], pr["depth_bits"][ne])
 
 
-def _check_images(fw, scene, cams, cfg, tol=IMG_TOL):
-    opts = options_for(cfg)
-    pairs = 0
-    for v, cam in enumerate(cams):
-        ref = render_view(scene, cam, opts)
-        err = np.max(np.abs(fw["images"][v] - ref["image"]))
-        terr = np.max(np.abs(fw["T"][v] - ref["T"]))
-        say(f"  view {v} {cam.width}x{cam.height}: image err {err:.2e}, T err {terr:.2e}")
-        assert err <= tol and terr <= tol
-        pairs += ref["hit_pairs"]
-    say(f"  hit pairs gpu {fw['hit_pairs']} oracle {pairs}")
-    assert abs(fw["hit_pairs"] - pairs) <= 1e-3 * pairs + 2
-
-
 def test_wave_reduction_selftest():
     import ctypes as C
     from paper_2510_08491_amd import _lib
@@ -77,7 +64,7 @@ def test_c1_keys_and_image():
     cfg = config_for(scene)
     fw = run_forward(scene, cams, cfg)
     _check_keys(fw, scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
+    check_images(fw, scene, cams, cfg)
 
 
 @pytest.mark.parametrize("tile", [(16, 16, 1), (16, 16, 2), (16, 16, 4), (8, 8, 1), (32, 16, 2), (32, 16, 4)])
@@ -88,7 +75,7 @@ def test_tile_shapes_ragged_image(tile):
     cfg = config_for(scene, tile=tile)
     fw = run_forward(scene, cams, cfg)
     _check_keys(fw, scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
+    check_images(fw, scene, cams, cfg)
 
 
 @pytest.mark.parametrize("N", [4, 8, 32])
@@ -97,10 +84,10 @@ def test_hidden_widths_with_gradients(N):
     cams = S.make_cameras([(96, 80)], seed=61)
     cfg = config_for(scene, tile=(16, 16, 2))
     fw = run_forward(scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
+    check_images(fw, scene, cams, cfg)
     small = S.subset_scene(scene, np.arange(200))
     small["N"], small["omega0"] = scene["N"], scene["omega0"]
-    _grad_parity(small, cams, S.make_targets(cams, seed=62), config_for(small, tile=(16, 16, 1)),
+    grad_parity(small, cams, S.make_targets(cams, seed=62), config_for(small, tile=(16, 16, 1)),
                  ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
@@ -112,7 +99,7 @@ def test_multiview_batched_and_persistent():
     _check_keys(a, scene, cams, config_for(scene))
     for v in range(len(cams)):
         assert np.array_equal(a["images"][v], b["images"][v])
-    _check_images(b, scene, cams, config_for(scene, persistent=1))
+    check_images(b, scene, cams, config_for(scene, persistent=1))
 
 
 @pytest.mark.parametrize("width,depth,N", [(16, 2, 16), (32, 2, 16), (32, 3, 32)])
@@ -121,7 +108,7 @@ def test_colour_mlp_image(width, depth, N):
     cams = S.make_cameras([(120, 90), (64, 48)], seed=82)
     cfg = config_for(scene, tile=(16, 16, 2))
     fw = run_forward(scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
+    check_images(fw, scene, cams, cfg)
 
 
 def test_dense_scene_early_termination():
@@ -132,7 +119,7 @@ def test_dense_scene_early_termination():
         cfg = config_for(scene, t_eps=t_eps)
         fw = run_forward(scene, cams, cfg)
         assert np.sum(fw["T"][0] < 1e-3) > 10
-        _check_images(fw, scene, cams, cfg)
+        check_images(fw, scene, cams, cfg)
 
 
 def test_background_alpha_min_alpha_max():
@@ -141,30 +128,14 @@ def test_background_alpha_min_alpha_max():
     cams = S.make_cameras([(64, 56)], seed=92)
     cfg = config_for(scene, alpha_min=1.0 / 255.0, alpha_max=0.5, bg=(0.25, 0.5, 1.0))
     fw = run_forward(scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
-
-
-def _grad_parity(scene, cams, targets, cfg, keys):
-    fw = run_forward(scene, cams, cfg)
-    loss, g = run_backward(fw, targets)
-    L_ref, g_ref, _ = autograd_loss_and_grads(scene, cams, targets, options_for(cfg))
-    say(f"  loss gpu {loss:.8f} oracle {L_ref:.8f}")
-    assert abs(loss - L_ref) <= 1e-5
-    bad = []
-    for k in keys:
-        ok, err, erel = grad_close(g[k], g_ref[k])
-        worst = np.unravel_index(np.argmax(np.abs(g[k] - g_ref[k])), g[k].shape)
-        say(f"  grad {k}: max err / max {err:.2e}, elementwise rel {erel:.2e}, worst at {worst}")
-        if not ok:
-            bad.append(k)
-    assert not bad, bad
+    check_images(fw, scene, cams, cfg)
 
 
 @pytest.mark.parametrize("fwd_cache", [1, 0])
 def test_c1_gradients(fwd_cache):
     _, scene, cams, targets = S.make_workload("C1")
     cfg = config_for(scene, fwd_cache=fwd_cache)
-    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
 @pytest.mark.parametrize("tile,fwd_cache", [((16, 16, 1), 1), ((16, 16, 4), 1), ((32, 16, 2), 1), ((32, 16, 2, 4), 0),
@@ -174,7 +145,7 @@ def test_gradients_multiview_tiles(tile, fwd_cache):
     cams = S.make_cameras([(72, 56), (48, 64)], seed=102)
     targets = S.make_targets(cams, seed=103)
     cfg = config_for(scene, tile=tile, persistent=1, fwd_cache=fwd_cache)
-    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors"])
 
 
 def test_cached_and_recomputed_backward_agree():
@@ -222,7 +193,7 @@ def test_colour_mlp_gradients(tile, fwd_cache):
     cams = S.make_cameras([(64, 48), (48, 40), (56, 56)], seed=112)
     targets = S.make_targets(cams, seed=113)
     cfg = config_for(scene, tile=tile, fwd_cache=fwd_cache)
-    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
 
 
 @pytest.mark.parametrize("name", ["C2", "C3"])
@@ -263,8 +234,8 @@ def test_time_conditioned_density_image_and_gradients(fwd_cache):
     targets = S.make_targets(cams, seed=153)
     cfg = config_for(scene, tile=(16, 16, 1), persistent=1, fwd_cache=fwd_cache)
     fw = run_forward(scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
-    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "wt"])
+    check_images(fw, scene, cams, cfg)
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "wt"])
 
 
 @pytest.mark.parametrize("tile", [(16, 16, 1), (8, 8, 1), (32, 16, 2)])
@@ -300,7 +271,7 @@ def test_capacity_overflow_is_reported_then_grown():
     assert code == _lib.SNP_ERR_CAPACITY and inst > 16
     fw = run_forward(scene, cams, cfg, capacity=16)
     assert fw["rast"].capacity >= fw["instances"]
-    _check_images(fw, scene, cams, cfg)
+    check_images(fw, scene, cams, cfg)
 
 
 @pytest.mark.parametrize("width,depth,n_views", [(32, 2, 3), (32, 3, 18), (16, 1, 17)])
@@ -312,7 +283,7 @@ def test_colour_mlp_gradients_widths_and_view_chunks(width, depth, n_views):
     cams = S.make_cameras(sizes[:n_views], seed=142)
     targets = S.make_targets(cams, seed=143)
     cfg = config_for(scene, tile=(16, 16, 1), persistent=1)
-    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "cmlp", "xi"])
 
 
 @pytest.mark.parametrize("fwd_cache", [1, 0])
@@ -324,8 +295,8 @@ def test_sh_colour_image_and_gradients(fwd_cache):
     targets = S.make_targets(cams, seed=153)
     cfg = config_for(scene, tile=(16, 16, 1), persistent=1, fwd_cache=fwd_cache)
     fw = run_forward(scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
-    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "sh"])
+    check_images(fw, scene, cams, cfg)
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "sh"])
 
 
 def test_graph_replay_matches_eager():
@@ -445,7 +416,7 @@ def test_degenerate_scenes(primitive):
     fw = run_forward(big, cams, cfg)
     if primitive == 0:
         _check_keys(fw, big, cams, cfg)
-        _check_images(fw, big, cams, cfg)
+        check_images(fw, big, cams, cfg)
     assert fw["tile_counts"][0][0] == 3 * 3  # 48x40 in 16x16 tiles, all covered
     assert fw["instances"] >= 9
 
@@ -460,8 +431,8 @@ def test_relighting_colour_image_and_gradients(width, depth, fwd_cache):
     targets = S.make_targets(cams, seed=173)
     cfg = config_for(scene, tile=(16, 16, 1), persistent=1, fwd_cache=fwd_cache)
     fw = run_forward(scene, cams, cfg)
-    _check_images(fw, scene, cams, cfg)
-    _grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp",
+    check_images(fw, scene, cams, cfg)
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp",
                                              "xi"])
 
 

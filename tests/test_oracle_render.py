@@ -217,3 +217,22 @@ def test_alpha_min_skips_faint_pairs_by_hand():
     assert np.max(np.abs(c - expect_C[sel[1], sel[0]])) <= 1e-12
     assert np.max(np.abs(t - expect_T[sel[1], sel[0]])) <= 1e-12
     assert np.array_equal(h, hit_f[sel[1], sel[0]].astype(int) + hit_b[sel[1], sel[0]].astype(int))
+
+
+@pytest.mark.parametrize("win", [(24, 24, 16, 16), (16, 32, 16, 16), (41, 7, 23, 19), (48, 48, 16, 16)])
+def test_window_render_equals_the_window_of_the_full_view(win):
+    """render_window (a window of a view rendered through a shifted camera
+    with the primitives whose rectangle meets it) equals that window of the
+    full render: image, transmittance, and the hit pairs of its pixels."""
+    scene = S.custom_scene(300, 16, color_mode=1, cmlp_width=16, cmlp_depth=2, seed=21)
+    cam = S.make_cameras([(64, 64)], seed=22)[0]
+    full = R.render_view(scene, cam)
+    x0, y0, w, h = win
+    w, h = min(w, 64 - x0), min(h, 64 - y0)
+    out = R.render_window(scene, cam, x0, y0, w, h)
+    assert np.max(np.abs(out["image"] - full["image"][y0:y0 + h, x0:x0 + w])) <= 1e-13
+    assert np.max(np.abs(out["T"] - full["T"][y0:y0 + h, x0:x0 + w])) <= 1e-13
+    # hit pairs of the window's pixels, counted pixel by pixel
+    rows, cols = np.mgrid[y0:y0 + h, x0:x0 + w]
+    _, _, hits = R.render_pixels(scene, cam, cols.ravel(), rows.ravel())
+    assert out["hit_pairs"] == int(hits.sum()) and out["hit_pairs"] > 0
