@@ -645,14 +645,17 @@ def cpu_baseline(scene, cams, targets, budget_s, workload):
         ids = np.nonzero(project_all(scene, crop)["nonempty"])[0]
         return S.subset_scene(scene, ids), crop, [targets[v][y0:y0 + size, x0:x0 + size]]
 
-    # calibrate the crop count on one crop, then run them all in the pool
+    # calibrate the crop count on one crop, then run them all in the pool;
+    # the calibration runs in a child too: a process that has run an
+    # autograd backward cannot fork workers that run one
+    ctx = mp.get_context("fork")
     probe = make_job()
-    pairs0, sec0 = _oracle_crop(probe)
+    with ctx.Pool(1) as pool:
+        pairs0, sec0 = pool.apply(_oracle_crop, (probe,))
     n_jobs = max(cores, int(round(budget_s / max(sec0, 1e-3))) * cores)
     n_jobs = min(n_jobs, 8 * cores)
     jobs = [make_job() for _ in range(n_jobs)]
     prims = sum(j[0]["P"] for j in jobs)
-    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         res = pool.map(_oracle_crop, jobs, chunksize=1)
