@@ -58,7 +58,8 @@ typedef enum {
   SNP_ERR_CAPACITY = 2,    /* tile instances exceeded the workspace capacity */
   SNP_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
   SNP_ERR_UNSUPPORTED = 4, /* valid but not built (e.g. N outside {4,8,16,32}) */
-  SNP_ERR_RANGE = 5        /* density-MLP phase outside the hardware sine range */
+  SNP_ERR_RANGE = 5,       /* density-MLP phase outside the hardware sine range */
+  SNP_ERR_TOO_LARGE = 6    /* snp_step_static: the step does not fit in its static scratch */
 } snp_status;
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point X
@@ -280,6 +281,26 @@ snp_status snp_render_backward(const snp_config* cfg, const snp_prims* prims, in
 snp_status snp_step(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams, void* ws,
                     const snp_layout* layout, float* images, float* final_T, const float* targets, double n_norm,
                     double* loss_out, float* dL_dimages, const snp_grads* grads, hipStream_t stream);
+
+/* snp_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same step with the same arguments, except that the workspace is not the
+ * caller's but a static device array of 64 MiB inside the library (each GPU
+ * the library runs on holds one until the process ends).  The call allocates
+ * nothing.  The instance capacity is the largest whose workspace layout fits
+ * in the 64 MiB, including the pair cache when cfg->fwd_cache = 1 (set
+ * fwd_cache = 0 for more instances).  Returns SNP_ERR_TOO_LARGE, enqueueing
+ * nothing, when even a capacity of one instance does not fit.  Every call on
+ * one GPU shares its array: calls that overlap on one GPU (other streams,
+ * other threads) race, and the array keeps the last call's contents (the
+ * step initialises everything it reads).  counters_out (DEVICE, 8 int64, or
+ * NULL) receives the workspace counters at the end of the step, as
+ * snp_read_counters lists them: [0] instances, [1] overflow flag (non-zero:
+ * the instances exceeded the capacity and the step's results are
+ * incomplete), [3] phase-range flag. */
+snp_status snp_step_static(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                           float* images, float* final_T, const float* targets, double n_norm, double* loss_out,
+                           float* dL_dimages, const snp_grads* grads, int64_t* counters_out, hipStream_t stream);
 
 /* Captures snp_step with these exact arguments into a HIP graph (the
  * pointers must stay valid while the graph lives) and returns an opaque

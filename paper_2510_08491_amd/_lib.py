@@ -9,7 +9,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsnp.so")
 
-SNP_OK, SNP_ERR_INVALID, SNP_ERR_CAPACITY, SNP_ERR_HIP, SNP_ERR_UNSUPPORTED, SNP_ERR_RANGE = range(6)
+SNP_OK, SNP_ERR_INVALID, SNP_ERR_CAPACITY, SNP_ERR_HIP, SNP_ERR_UNSUPPORTED, SNP_ERR_RANGE, SNP_ERR_TOO_LARGE = range(7)
 
 
 class SnpCamera(C.Structure):
@@ -88,6 +88,7 @@ def lib():
         "snp_loss_l1": [cfg, I32, cams, VP, VP, D, VP, lay, VP, VP, VP],
         "snp_render_backward": [cfg, prims, I32, cams, VP, lay, VP, VP, grads, VP],
         "snp_step": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, D, VP, VP, grads, VP],
+        "snp_step_static": [cfg, prims, I32, cams, VP, VP, VP, D, VP, VP, grads, VP, VP],
         "snp_graph_create": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, D, VP, VP, grads, VP, P(VP)],
         "snp_graph_create_forward": [cfg, prims, I32, cams, VP, lay, VP, VP, VP, P(VP)],
         "snp_graph_launch": [VP, VP],
@@ -117,7 +118,7 @@ def lib():
 
 
 EXPORTED = ["snp_workspace_layout", "snp_preprocess", "snp_bin", "snp_sort", "snp_render_forward", "snp_loss_l1",
-            "snp_render_backward", "snp_step", "snp_graph_create", "snp_graph_create_forward", "snp_graph_launch",
+            "snp_render_backward", "snp_step", "snp_step_static", "snp_graph_create", "snp_graph_create_forward", "snp_graph_launch",
             "snp_graph_destroy",
             "snp_read_status", "snp_supported_tiles", "snp_status_string", "snp_selftest_wave_sum",
             "snp_read_counters", "snp_kernel_timing", "snp_kernel_timing_read", "snp_adam_step",

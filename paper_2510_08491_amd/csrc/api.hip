@@ -3,6 +3,7 @@
 // everything lives in the caller's workspace.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "snp_internal.h"
@@ -532,15 +533,64 @@ static snp_status capture_graph(hipStream_t stream, void** graph_out, F body) {
   return SNP_OK;
 }
 
-}  // namespace snp
-
-using namespace snp;
-
 #define SNP_TRY(x)                  \
   do {                              \
     snp_status s_ = (x);            \
     if (s_ != SNP_OK) return s_;    \
   } while (0)
+
+// ---------------------------------------------------------------------------
+// Static scratch of snp_step_static, for callers that cannot allocate device
+// memory.  The array holds the whole workspace of one step.  On the host its
+// name is only a stand-in symbol, never a device address: host code uses the
+// address hipGetSymbolAddress returns, fetched once per device (every device
+// holds its own copy of the array at its own address).
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];
+
+static snp_status static_scratch(void** out) {
+  int dev = -1;
+  SNP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return SNP_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SNP_ERR_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return SNP_OK;
+}
+
+// The plan with the largest instance capacity whose workspace fits in the
+// static scratch (the layout grows monotonically with the capacity).
+static snp_status static_plan(const snp_config* cfg, int64_t P, int32_t V, const snp_camera* cams, Plan* pl) {
+  SNP_TRY(make_plan(cfg, P, V, cams, 1, pl));
+  if (pl->L.bytes > kStaticScratchBytes) return SNP_ERR_TOO_LARGE;
+  int64_t lo = 1, hi = ((int64_t)1 << 31) - 1;
+  Plan probe;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    SNP_TRY(make_plan(cfg, P, V, cams, mid, &probe));
+    if (probe.L.bytes <= kStaticScratchBytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return make_plan(cfg, P, V, cams, lo, pl);
+}
+
+__global__ void copy_counters_kernel(const unsigned long long* src, int64_t* dst) {
+  if (threadIdx.x < CNT_COUNT) dst[threadIdx.x] = (int64_t)src[threadIdx.x];
+}
+
+}  // namespace snp
+
+using namespace snp;
 
 extern "C" {
 
@@ -669,6 +719,23 @@ snp_status snp_step(const snp_config* cfg, const snp_prims* prims, int32_t V, co
   return do_step(cfg, prims, V, cams, pl, ws, images, final_T, targets, n_norm, loss_out, dL_dimages, grads, stream);
 }
 
+snp_status snp_step_static(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
+                           float* images, float* final_T, const float* targets, double n_norm, double* loss_out,
+                           float* dL_dimages, const snp_grads* grads, int64_t* counters_out, hipStream_t stream) {
+  SNP_TRY(check_step_args(cfg, prims, images, final_T, targets, n_norm, loss_out, dL_dimages, grads));
+  Plan pl;
+  SNP_TRY(static_plan(cfg, prims->P, V, cams, &pl));
+  void* ws = nullptr;
+  SNP_TRY(static_scratch(&ws));
+  SNP_TRY(do_step(cfg, prims, V, cams, pl, ws, images, final_T, targets, n_norm, loss_out, dL_dimages, grads, stream));
+  if (counters_out) {
+    hipLaunchKernelGGL(copy_counters_kernel, dim3(1), dim3(64), 0, stream, wsp<unsigned long long>(ws, pl.L.counters),
+                       counters_out);
+    SNP_HIP(hipGetLastError());
+  }
+  return SNP_OK;
+}
+
 snp_status snp_graph_create(const snp_config* cfg, const snp_prims* prims, int32_t V, const snp_camera* cams,
                             void* ws, const snp_layout* layout, float* images, float* final_T, const float* targets,
                             double n_norm, double* loss_out, float* dL_dimages, const snp_grads* grads,
@@ -748,6 +815,7 @@ const char* snp_status_string(snp_status s) {
     case SNP_ERR_HIP: return "HIP runtime error";
     case SNP_ERR_UNSUPPORTED: return "unsupported configuration";
     case SNP_ERR_RANGE: return "density-MLP phase outside the supported range";
+    case SNP_ERR_TOO_LARGE: return "the step does not fit in the 64 MiB static scratch";
   }
   return "unknown status";
 }

@@ -302,6 +302,29 @@ class Rasterizer:
         return out
 
 
+def step_static(cfg: RenderConfig, params, cams, images, final_T, targets, n_norm, loss_out, dL, grads,
+                counters: Optional[torch.Tensor] = None):
+    """One training step through snp_step_static: the workspace is the
+    library's static device scratch (no allocation).  `counters` (int64
+    device tensor of 8, optional) receives the workspace counters."""
+    ccfg = cfg.to_c()
+    cams = list(cams)
+    pr = L.SnpPrims()
+    pr.P = int(params["centers"].shape[0])
+    for k in PARAM_KEYS:
+        setattr(pr, k, _ptr(params.get(k)))
+    g = L.SnpGrads()
+    for k, _ in L.SnpGrads._fields_:
+        setattr(g, k, _ptr(grads.get(k)))
+    cnt = None
+    if counters is not None:
+        assert counters.is_cuda and counters.dtype == torch.int64 and counters.numel() >= 8
+        cnt = C.c_void_p(counters.data_ptr())
+    L.check(L.lib().snp_step_static(C.byref(ccfg), C.byref(pr), len(cams), camera_array(cams), _ptr(images),
+                                    _ptr(final_T), _ptr(targets), float(n_norm), C.c_void_p(loss_out.data_ptr()),
+                                    _ptr(dL), C.byref(g), cnt, _stream()), "snp_step_static")
+
+
 def kernel_timing(enable: bool):
     L.check(L.lib().snp_kernel_timing(1 if enable else 0), "snp_kernel_timing")
 
