@@ -371,7 +371,23 @@ __global__ void __launch_bounds__(256) preprocess_views_kernel(ViewArgs a) {
       r4[2] = make_float4((float)gy[0], (float)gy[1], (float)gy[2], cr);
       r4[3] = make_float4((float)mc[0], (float)mc[1], (float)mc[2], cg);
       r4[4] = make_float4((float)hx[0], (float)hx[1], (float)hx[2], cb);
-      r4[5] = make_float4((float)hy[0], (float)hy[1], (float)hy[2], 0.f);
+      // Width of the band around the silhouette in which the rasterizer
+      // decides a hit by the float64 coefficients below: 64 times a bound on
+      // the error of the float32 discriminant A - M it evaluates from this
+      // record over the rectangle's pixel centres.  Per component of d' and
+      // m' the error is at most 3 roundings (coefficients, two FMAs) of
+      // S = |c0| + |c1| |dx| + |c2| |dy|; the squares and the difference add
+      // 7 more, so |error| <= 10 u (sum S_d^2 + sum S_m^2), u = 2^-24.
+      const double ex = fmax(fabs((double)rect[0] + 0.5 - rxf), fabs((double)rect[1] + 0.5 - rxf));
+      const double ey = fmax(fabs((double)rect[2] + 0.5 - ryf), fabs((double)rect[3] + 0.5 - ryf));
+      double sum_s2 = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        const double sdr = fabs(dc[r]) + fabs(gx[r]) * ex + fabs(gy[r]) * ey;
+        const double smr = fabs(mc[r]) + fabs(hx[r]) * ex + fabs(hy[r]) * ey;
+        sum_s2 += sdr * sdr + smr * smr;
+      }
+      const float band = (float)(64.0 * 10.0 * 0x1p-24 * sum_s2);
+      r4[5] = make_float4((float)hy[0], (float)hy[1], (float)hy[2], band);
       auto dot = [](const double* u, const double* w) { return u[0] * w[0] + u[1] * w[1] + u[2] * w[2]; };
       double* dq = a.disc_coef + i * 6;
       dq[0] = dot(dc, dc) - dot(mc, mc);

@@ -108,24 +108,20 @@ struct PixelBlock {
   }
 };
 
-// LDS stage of one batch: records, tables and the float64 discriminant
-// coefficients (3 float4 = 6 doubles per instance) that decide the hits
-// near the silhouette.
+// LDS stage of one batch: records and tables.
 template <int N, int B>
 struct Stage {
   static constexpr int NB = B;
   static constexpr int TS = 5 * N + 4;
-  static constexpr int DQ4 = 3;
-  static constexpr int F = 6 + TS / 4 + DQ4;  // float4 per instance
+  static constexpr int F = 6 + TS / 4;  // float4 per instance
   float4 rec[B][6];
   float4 tab[B][TS / 4];
-  float4 dq[B][3];
   int4 rect[B];  // the primitive's inclusive pixel rectangle in this view
   uint32_t id[B];
 };
 
-// Stages one batch: instance ids and rectangles, records, tables (and the
-// discriminant coefficients), gathered by primitive id as float4.  The
+// Stages one batch: instance ids and rectangles, records and tables,
+// gathered by primitive id as float4.  The
 // threads that gather read the id from global memory themselves, so one
 // barrier (at the end) suffices.  The caller's previous barrier (the end of
 // the previous batch, or the work-queue fetch) guarantees nobody still
@@ -140,7 +136,6 @@ __device__ __forceinline__ void stage_batch(Stage<N, B>& S, const RasterArgs& a,
   }
   const float4* rec4 = reinterpret_cast<const float4*>(a.records);
   const float4* tab4 = reinterpret_cast<const float4*>(a.table);
-  const float4* dq4 = reinterpret_cast<const float4*>(a.disc_coef);
   constexpr int F = Stage<N, B>::F;
   constexpr int T4 = Stage<N, B>::TS / 4;
   for (int idx = threadIdx.x; idx < nb * F; idx += NT) {
@@ -148,10 +143,8 @@ __device__ __forceinline__ void stage_batch(Stage<N, B>& S, const RasterArgs& a,
     const uint32_t p = a.values[b0 + j];
     if (c < 6)
       S.rec[j][c] = rec4[(vbase + p) * 6 + c];
-    else if (c < 6 + T4)
-      S.tab[j][c - 6] = tab4[(int64_t)p * T4 + (c - 6)];
     else
-      S.dq[j][c - 6 - T4] = dq4[(vbase + p) * 3 + (c - 6 - T4)];
+      S.tab[j][c - 6] = tab4[(int64_t)p * T4 + (c - 6)];
   }
   __syncthreads();
 }
@@ -164,21 +157,23 @@ struct PairGeom {
   float p0, p1, p2, e0, e1, e2;
 };
 
-// dq: the float64 coefficients of the discriminant as a quadratic in the
-// pixel offset from the record's reference pixel.  The float32 discriminant
-// A - M is off by about 1e-6 |o'| A (o' = the camera centre in the
-// primitive's unit-sphere frame: the rounding of m' = o' x d' grows with it),
-// which stays far below 1% of A up to |o'| ~ 1e4, i.e. a camera 10^4
-// semi-axes away; so its sign decides a hit everywhere outside that band; inside
-// it the float64 form, evaluated at the exact offset (the difference of two
-// floats is exact in float64), decides the hit and gives the value.  The
-// oracle decides with its own float64 discriminant, so the hit pairs of both
-// sides are the same pairs (up to ties within float64 rounding).  The same
-// function serves the forward and both phases of the backward, so they agree
-// on every hit.
+// dqg: the float64 coefficients of the discriminant as a quadratic in the
+// pixel offset from the record's reference pixel (in global memory; the
+// pointer is the same for the whole wave).  The float32 discriminant A - M
+// is within band/64 of the exact one (r5.w, from a bound on its rounding
+// errors over the rectangle), so outside the band its sign decides a hit;
+// inside it the float64 form, evaluated at the exact offset (the difference
+// of two floats is exact in float64), decides the hit and gives the value.
+// The oracle decides with its own float64 discriminant, so the hit pairs of
+// both sides are the same pairs (up to ties within float64 rounding).  The
+// forward and the pixel phase of the backward call this with the same band,
+// so they agree on every hit and every value; the gradient phase widens the
+// band to 1% of A (WIDE), where the float32 value has too few correct digits
+// for the 1/sqrt(disc) factor of the geometry gradient.
+template <bool WIDE = false>
 __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
                                           const float4& r4, const float4& r5, float px, float py, PairGeom& g,
-                                          const double* dq) {
+                                          const double* dqg) {
   g.dx = px - r0.w;
   g.dy = py - r1.w;
   g.d0 = __builtin_fmaf(r2.x, g.dy, __builtin_fmaf(r1.x, g.dx, r0.x));
@@ -191,9 +186,10 @@ __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, co
   const float M = __builtin_fmaf(g.m2, g.m2, __builtin_fmaf(g.m1, g.m1, g.m0 * g.m0));
   float disc = g.A - M;
   bool hit = disc > 0.f;
-  if (fabsf(disc) < 0.01f * g.A) {
+  const float band = WIDE ? fmaxf(r5.w, 0.01f * g.A) : r5.w;
+  if (fabsf(disc) < band) {
     const double x = (double)px - (double)r0.w, y = (double)py - (double)r1.w;
-    const double dd = dq[0] + x * (dq[1] + dq[3] * x + dq[4] * y) + y * (dq[2] + dq[5] * y);
+    const double dd = dqg[0] + x * (dqg[1] + dqg[3] * x + dqg[4] * y) + y * (dqg[2] + dqg[5] * y);
     hit = dd > 0.0;
     disc = (float)dd;
   }
@@ -209,6 +205,14 @@ __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, co
   g.e1 = g.d1 * g.H;
   g.e2 = g.d2 * g.H;
   return hit;
+}
+
+// the float64 discriminant coefficients of staged instance j (the address
+// is the same for the whole wave, so the loads are scalar)
+template <int N, int B>
+__device__ __forceinline__ const double* disc_coef_of(const Stage<N, B>& S, const RasterArgs& a, int v, int j) {
+  const uint32_t p = __builtin_amdgcn_readfirstlane(S.id[j]);
+  return a.disc_coef + ((int64_t)v * a.P + p) * 6;
 }
 
 __device__ __forceinline__ float alpha_of(float ahat, float alpha_max) {
@@ -268,7 +272,7 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
         if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
-        const double* dqj = reinterpret_cast<const double*>(S.dq[j]);
+        const double* dqj = disc_coef_of(S, a, v, j);
         PairGeom g[PPL];
         bool hit[PPL];
         bool any = false;
@@ -640,15 +644,17 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
     const int ty = local / cam.ntx, tx = local - ty * cam.ntx;
     PixelBlock<TW, TH, 1> pb;
     pb.init(cam, tx, ty);
-    float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f;
+    float T = 1.f;
     bool done = pb.pix[0] < 0;
     const int64_t pxi = cam.pix_base + (done ? 0 : pb.pix[0]);
     const float G0 = done ? 0.f : a.dL[3 * pxi + 0];
     const float G1 = done ? 0.f : a.dL[3 * pxi + 1];
     const float G2 = done ? 0.f : a.dL[3 * pxi + 2];
-    const float F0 = done ? 0.f : a.images_in[3 * pxi + 0];
-    const float F1 = done ? 0.f : a.images_in[3 * pxi + 1];
-    const float F2 = done ? 0.f : a.images_in[3 * pxi + 2];
+    // colour of everything behind the instances blended so far: the final
+    // colour minus their contributions
+    float B0 = done ? 0.f : a.images_in[3 * pxi + 0];
+    float B1 = done ? 0.f : a.images_in[3 * pxi + 1];
+    float B2 = done ? 0.f : a.images_in[3 * pxi + 2];
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
@@ -663,8 +669,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
         const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
         const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
         PairGeom g;
-        const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[0], pb.pyc[0], g,
-                                  reinterpret_cast<const double*>(S.dq[j]));
+        const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pb.pxc[0], pb.pyc[0], g, disc_coef_of(S, a, v, j));
         const bool hit = !done && gh;
         if (__ballot(hit) == 0) return;  // wave-uniform
         float ahat, QB = 0.f;  // QB = Q + b2 (recomputed path only)
@@ -695,12 +700,12 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
             gc0 = G0 * wt;
             gc1 = G1 * wt;
             gc2 = G2 * wt;
-            A0 = __builtin_fmaf(r2.w, wt, A0);
-            A1 = __builtin_fmaf(r3.w, wt, A1);
-            A2 = __builtin_fmaf(r4.w, wt, A2);
+            B0 = __builtin_fmaf(-r2.w, wt, B0);
+            B1 = __builtin_fmaf(-r3.w, wt, B1);
+            B2 = __builtin_fmaf(-r4.w, wt, B2);
             if (ahat > 0.f && al < a.alpha_max) {
               const float ta = T * (1.f - al);
-              const float G = G0 * (r2.w * ta - (F0 - A0)) + G1 * (r3.w * ta - (F1 - A1)) + G2 * (r4.w * ta - (F2 - A2));
+              const float G = G0 * (r2.w * ta - B0) + G1 * (r3.w * ta - B1) + G2 * (r4.w * ta - B2);
               wq = G * 2.f * pb.L[0] * g.H;  // d loss / d Q
               // d loss / d H (direct) = G 2 L (Q + b2); from the stored integral
               // alpha-hat = 2 L H (Q + b2) when cached (H > 0 for a hit)
@@ -779,7 +784,8 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           const float4 r0 = S.rec[j][0], r1 = S.rec[j][1], r2 = S.rec[j][2];
           const float4 r3 = S.rec[j][3], r4 = S.rec[j][4], r5 = S.rec[j][5];
           PairGeom G;
-          const bool gh = pair_geom(r0, r1, r2, r3, r4, r5, pxc, pyc, G, reinterpret_cast<const double*>(S.dq[j]));
+          const double* dqj = disc_coef_of(S, a, v, j);
+          const bool gh = pair_geom<true>(r0, r1, r2, r3, r4, r5, pxc, pyc, G, dqj);
           if (!gh) {  // float64 discriminant says the ray misses: no gradient
             wq = 0.f;
             gHd = 0.f;
@@ -873,7 +879,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           {
             const float4 q0 = S.rec[j][0], q1 = S.rec[j][1], q2 = S.rec[j][2];
             const float4 q3 = S.rec[j][3], q4 = S.rec[j][4], q5 = S.rec[j][5];
-            pair_geom(q0, q1, q2, q3, q4, q5, pxc, pyc, G, reinterpret_cast<const double*>(S.dq[j]));
+            pair_geom<true>(q0, q1, q2, q3, q4, q5, pxc, pyc, G, dqj);
           }
           float R[18];
 #pragma unroll

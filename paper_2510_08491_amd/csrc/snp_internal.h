@@ -72,7 +72,7 @@ inline __host__ __device__ int table_stride(int N) { return 5 * N + 4; }
 //
 // Record of a (view, primitive) pair, 6 float4:
 //   q0 (dc.xyz, rx)  q1 (gx.xyz, ry)  q2 (gy.xyz, col.r)
-//   q3 (mc.xyz, col.g)  q4 (hx.xyz, col.b)  q5 (hy.xyz, 0)
+//   q3 (mc.xyz, col.g)  q4 (hx.xyz, col.b)  q5 (hy.xyz, band)
 // For a pixel centre (px, py), with dx = px - rx, dy = py - ry:
 //   d' = dc + gx dx + gy dy   ray direction in the ellipsoid's unit-sphere frame
 //   m' = mc + hx dx + hy dy   its moment o' x d'
@@ -80,9 +80,12 @@ inline __host__ __device__ int table_stride(int N) { return 5 * N + 4; }
 // The discriminant A - M = |d'|^2 - |m'|^2 as a float64 quadratic form in the
 // same offsets is kept beside the record (6 doubles c0..c5):
 //   disc = c0 + dx (c1 + c3 dx + c4 dy) + dy (c2 + c5 dy)
-// The backward evaluates it for pairs close to the silhouette, where the
-// float32 difference A - M has too few correct digits for the 1/sqrt(disc)
-// factor of the geometry gradient.
+// Where the float32 difference A - M lies within `band` of zero (64 times a
+// bound on its rounding error over the rectangle) its sign is not trusted
+// and the float64 form decides the hit and gives the value; the gradient
+// phase of the backward also takes the float64 value within 1% of A of
+// zero, where the float32 difference has too few correct digits for the
+// 1/sqrt(disc) factor of the geometry gradient.
 
 template <typename T>
 __device__ __forceinline__ T* at(void* base, size_t off) {
