@@ -170,10 +170,9 @@ struct PairGeom {
 // so they agree on every hit and every value; the gradient phase widens the
 // band to 1% of A (WIDE), where the float32 value has too few correct digits
 // for the 1/sqrt(disc) factor of the geometry gradient.
-template <bool WIDE = false>
-__device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
-                                          const float4& r4, const float4& r5, float px, float py, PairGeom& g,
-                                          const double* dqg) {
+// d', m' and A = |d'|^2 at a pixel centre from a staged record
+__device__ __forceinline__ void pair_dm(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
+                                        const float4& r4, const float4& r5, float px, float py, PairGeom& g) {
   g.dx = px - r0.w;
   g.dy = py - r1.w;
   g.d0 = __builtin_fmaf(r2.x, g.dy, __builtin_fmaf(r1.x, g.dx, r0.x));
@@ -183,6 +182,13 @@ __device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, co
   g.m1 = __builtin_fmaf(r5.y, g.dy, __builtin_fmaf(r4.y, g.dx, r3.y));
   g.m2 = __builtin_fmaf(r5.z, g.dy, __builtin_fmaf(r4.z, g.dx, r3.z));
   g.A = __builtin_fmaf(g.d2, g.d2, __builtin_fmaf(g.d1, g.d1, g.d0 * g.d0));
+}
+
+template <bool WIDE = false>
+__device__ __forceinline__ bool pair_geom(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
+                                          const float4& r4, const float4& r5, float px, float py, PairGeom& g,
+                                          const double* dqg) {
+  pair_dm(r0, r1, r2, r3, r4, r5, px, py, g);
   const float M = __builtin_fmaf(g.m2, g.m2, __builtin_fmaf(g.m1, g.m1, g.m0 * g.m0));
   float disc = g.A - M;
   bool hit = disc > 0.f;
@@ -582,6 +588,12 @@ __device__ __forceinline__ float cross_rows_pair(float a, float b) {
   return __uint_as_float(q[0]) + __uint_as_float(q[1]);
 }
 
+// d/dh of sin(2 pi h)/h near h = 0 is -(2 pi)^3 h / 3 + (2 pi)^5 h^3 / 30
+// (the next term, (2 pi)^7 h^5 / 840, is below float rounding for
+// |h| < 0.02); these are its coefficients divided by -2 pi
+constexpr float kDsnC1n = (kTwoPi * kTwoPi) / 3.0f;
+constexpr float kDsnC3n = -(kTwoPi * kTwoPi * kTwoPi * kTwoPi) / 30.0f;
+
 // Length of the un-normalised camera ray R^-1 ((x+1/2-cx)/fx, (y+1/2-cy)/fy, 1).
 __device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float pyc) {
   const float cxn = (pxc - cam.cx) / cam.fx;
@@ -621,7 +633,6 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
   __shared__ float s_gh[NB][NT];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   // selector bits and value index of the transposed row reductions
   const bool sel1 = lane & 4, sel2 = lane & 1, sel3 = lane & 2, sel4 = lane & 8;
   const int idx16 = 8 * ((lane >> 3) & 1) + 4 * ((lane >> 1) & 1) + 2 * (lane & 1) + ((lane >> 2) & 1);
@@ -728,7 +739,9 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
         const unsigned long long lm = __ballot(live);
         if (lm) {
           if (live) {
-            const uint32_t pos = wave * 64 + (uint32_t)__popcll(lm & lt_mask);
+            // slot: the number of live lanes below this one (mbcnt)
+            const uint32_t pos =
+                wave * 64 + __builtin_amdgcn_mbcnt_hi((uint32_t)(lm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
             s_pix[j][pos] = (uint16_t)pb.loc[0];
             s_wq[j][pos] = wq;
             s_gh[j][pos] = gH;
@@ -790,6 +803,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
             wq = 0.f;
             gHd = 0.f;
           }
+          const float sq_pair = G.sq;  // kept through the unit loop (the rest is recomputed)
           const float4* tab = S.tab[j];
           const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
           float* acc = s_acc[j];
@@ -819,20 +833,20 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
               const float c = cos_rev(ph), s = sin_rev(ph);
               const float sh = sin_rev(hv), ch = cos_rev(hv);
               const float rh = fast_rcp(hv);
-              const float ahv = fabsf(hv);
               const float sn = fminf(sh * rh, kTwoPi);  // sinc, as in sinc_rev
-              const float hh = kTwoPi * hv, h2 = hh * hh;
-              const float series = kTwoPi * kTwoPi * hh * (-1.f / 3.f + h2 * (1.f / 30.f - h2 * (1.f / 840.f)));
-              const float general = (kTwoPi * ch - sn) * rh;
-              const float dsn = ahv < 0.02f ? series : general;
-              const float ww = wq * w2;
-              const float gph = -kTwoPi * ww * s * sn;  // d loss / d ph
-              const float ghv = ww * c * dsn;           // d loss / d hv
+              // d sn / d hv / (-2 pi): both phase derivatives below carry the
+              // common factor -2 pi, applied once to their sums instead
+              const float series = hv * __builtin_fmaf(kDsnC3n, hv * hv, kDsnC1n);
+              const float general = __builtin_fmaf(sn, kInvTwoPi, -ch) * rh;
+              const float dsn = fabsf(hv) < 0.02f ? series : general;
+              const float wsn = wq * sn;
+              const float gph = wsn * w2 * s;       // d loss / d ph / (-2 pi)
+              const float ghv = wq * w2 * c * dsn;  // d loss / d hv / (-2 pi)
               v8[0 + u] = __builtin_fmaf(gph, G.p0, ghv * G.e0);
               v8[2 + u] = __builtin_fmaf(gph, G.p1, ghv * G.e1);
               v8[4 + u] = __builtin_fmaf(gph, G.p2, ghv * G.e2);
               v8[6 + u] = gph;
-              v2[u] = wq * c * sn;
+              v2[u] = wsn * c;
               gp0 = __builtin_fmaf(gph, w.x, gp0);
               gp1 = __builtin_fmaf(gph, w.y, gp1);
               gp2 = __builtin_fmaf(gph, w.z, gp2);
@@ -872,15 +886,26 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
               if (lane < 8 && !sel3) atomicAdd(acc + 4 * N + g + (idx16 & 3), q4);
             }
           }
-          // chain p', e', H -> d', m' -> record coefficients.  The geometry is
-          // recomputed from LDS here (the barrier keeps the compiler from reusing
-          // the first computation), so only p' and e' stay live through the unit loop.
+          // chain p', e', H -> d', m' -> record coefficients.  d' and m' are
+          // recomputed from LDS here (the barrier keeps the compiler from
+          // reusing the first computation), so only p', e' and sqrt(disc) stay
+          // live through the unit loop.  The unit sums above are d loss / d ph
+          // and d loss / d hv divided by -2 pi.
           asm volatile("" ::: "memory");
           {
             const float4 q0 = S.rec[j][0], q1 = S.rec[j][1], q2 = S.rec[j][2];
             const float4 q3 = S.rec[j][3], q4 = S.rec[j][4], q5 = S.rec[j][5];
-            pair_geom<true>(q0, q1, q2, q3, q4, q5, pxc, pyc, G, dqj);
+            pair_dm(q0, q1, q2, q3, q4, q5, pxc, pyc, G);
+            G.rA = fast_rcp(G.A);
+            G.sq = sq_pair;
+            G.H = G.sq * G.rA;
           }
+          gp0 *= -kTwoPi;
+          gp1 *= -kTwoPi;
+          gp2 *= -kTwoPi;
+          ge0 *= -kTwoPi;
+          ge1 *= -kTwoPi;
+          ge2 *= -kTwoPi;
           float R[18];
 #pragma unroll
           for (int r = 0; r < 18; ++r) R[r] = 0.f;
@@ -942,9 +967,10 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
       for (int idx = threadIdx.x; idx < nb * ACC; idx += NT) {
         const int jj = idx / ACC, cc = idx - jj * ACC;
         float* slot = &s_acc[jj][cc];
-        const float val = *slot;
+        float val = *slot;
         if (val != 0.f) {
           const uint32_t p = S.id[jj];
+          if (cc < 4 * N) val *= -kTwoPi;  // the phase-derivative sums (see the unit loop)
           if (cc < TS)
             atomic_add_f32(a.gtable + (int64_t)p * TS + cc, val);
           else
