@@ -18,6 +18,17 @@ view) (the paper evaluates it per ray; with a point light at l_v):
     input  = [normalize(x_B - o_v) (3), normalize(l_v - x_B) (3), xi_p (8)]
     colour = c_dc + sigmoid(MLP(input))
 
+Per-ray relighting colour (colour mode 4; the relighting application's
+colour per view ray, at the ray's entry point into the bounding ellipsoid):
+for a ray o + t d (d unit) entering the ellipsoid at t_in,
+
+    input  = [(o + t_in d - x_B) / max(s_B) (3), d (3), normalize(l_v - x_B) (3)]
+    colour = c_dc + sigmoid(MLP(input))
+
+The entry point is normalised as the density network's input (Eq. 5), so it
+lies in the unit ball; the light direction is taken relative to the
+primitive's centre, as the paper states.  There is no xi input.
+
 Spherical harmonics: with d = normalize(x_B - o_v) and the 16 real
 orthonormal harmonics Y_k(d) of degrees 0..3 (order (l, m) = (0,0),
 (1,-1), (1,0), (1,1), (2,-2), ..., (3,3); real forms sqrt(2) (-1)^m Re/Im of
@@ -120,3 +131,17 @@ def primitive_colors(scene, cam):
     if scene["color_mode"] == 3:
         c = c + np.asarray(scene["colors"], dtype=np.float64)
     return c
+
+
+def ray_colors(scene, p, cam, o, d, t_in):
+    """Per-ray relighting colour (colour mode 4) of primitive p for rays
+    o + t d (d (..., 3) unit) entering its ellipsoid at t_in (...)."""
+    xb = np.asarray(scene["centers"][p], dtype=np.float64)
+    m = float(np.max(np.asarray(scene["scales"][p], dtype=np.float64)))
+    d = np.asarray(d, dtype=np.float64)
+    x_in = (np.asarray(o, dtype=np.float64) + np.asarray(t_in, dtype=np.float64)[..., None] * d - xb) / m
+    ld = np.asarray(cam.light, dtype=np.float32).astype(np.float64) - xb
+    ld = ld / np.linalg.norm(ld)
+    x = np.concatenate([x_in, d, np.broadcast_to(ld, d.shape)], axis=-1)
+    layers = unpack_cmlp(scene["cmlp"][p], scene["cmlp_width"], scene["cmlp_depth"], 9)
+    return np.asarray(scene["colors"][p], dtype=np.float64) + mlp_forward(x, layers)

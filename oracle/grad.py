@@ -84,6 +84,22 @@ def _colors_t(params, meta, o, cam=None):
     return torch.sigmoid(h)
 
 
+def _mlp_t(vec, width, depth, h):
+    """The packed colour network of one primitive on inputs h (..., n_in):
+    ReLU hidden layers, sigmoid output."""
+    dims = [h.shape[-1]] + [width] * depth + [3]
+    pos = 0
+    for li, (a, b) in enumerate(zip(dims[:-1], dims[1:])):
+        Wm = vec[pos:pos + a * b].reshape(b, a)
+        pos += a * b
+        bb = vec[pos:pos + b]
+        pos += b
+        h = h @ Wm.T + bb
+        if li + 1 < len(dims) - 1:
+            h = torch.relu(h)
+    return torch.sigmoid(h)
+
+
 def render_view_torch(params, meta, cam, opts: RenderOptions = RenderOptions(), proj=None):
     """Differentiable float64 render of one view (route 1)."""
     if proj is None:
@@ -96,7 +112,8 @@ def render_view_torch(params, meta, cam, opts: RenderOptions = RenderOptions(), 
     o = -Rinv @ tc
     fx, fy, cx, cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
     Rp = _rotmat_t(params["quats"])
-    colors = _colors_t(params, meta, o, cam)
+    per_ray = meta["color_mode"] == 4
+    colors = None if per_ray else _colors_t(params, meta, o, cam)
     om = float(meta["omega0"])
     img = torch.zeros(H, W, 3, dtype=torch.float64)
     T = torch.ones(H, W, dtype=torch.float64)
@@ -142,9 +159,18 @@ def render_view_torch(params, meta, cam, opts: RenderOptions = RenderOptions(), 
         if opts.alpha_min > 0:
             use = use & (alpha.detach() >= opts.alpha_min)
         alpha = torch.where(use, alpha, torch.zeros_like(alpha))
+        if per_ray:
+            # relighting colour per ray at the entry point (colour mode 4)
+            x_in = (o + t_in[..., None] * d - xb) / m
+            lv = torch.tensor(np.asarray(cam.light, dtype=np.float32).astype(np.float64)) - xb
+            lv = lv / torch.linalg.norm(lv)
+            inp = torch.cat([x_in, d, lv.expand(d.shape)], -1)
+            col = params["colors"][p] + _mlp_t(params["cmlp"][p], meta["cmlp_width"], meta["cmlp_depth"], inp)
+        else:
+            col = colors[p]
         Tb = T[y0:y1 + 1, x0:x1 + 1]
         img = img.clone()
-        img[y0:y1 + 1, x0:x1 + 1] = img[y0:y1 + 1, x0:x1 + 1] + (alpha * Tb)[..., None] * colors[p]
+        img[y0:y1 + 1, x0:x1 + 1] = img[y0:y1 + 1, x0:x1 + 1] + (alpha * Tb)[..., None] * col
         Tn = Tb * (1.0 - alpha)
         T = T.clone()
         T[y0:y1 + 1, x0:x1 + 1] = Tn

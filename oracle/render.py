@@ -31,7 +31,7 @@ import dataclasses
 
 import numpy as np
 
-from .color import primitive_colors
+from .color import primitive_colors, ray_colors
 from .density import chord_integral
 from .geometry import intersect_ellipsoid, pixel_rays, quat_to_rotmat
 from .keys import project_all
@@ -55,16 +55,30 @@ def primitive(scene, p, R=None):
                 R=quat_to_rotmat(scene["quats"][p]) if R is None else R)
 
 
-def splat_alpha(o, d, prim):
+def splat_alpha(o, d, prim, return_t_in=False):
     """disc and alpha (Eq. 9) of one primitive for rays (o, d); alpha is 0
-    where the ray misses.  Returns (disc, alpha_unclamped_integral, alpha)."""
+    where the ray misses.  Returns (disc, alpha_unclamped_integral, alpha)
+    (and t_in, NaN for misses, with return_t_in)."""
     disc, t_in, t_out = intersect_ellipsoid(o, d, prim["center"], prim["scale"], prim["R"])
     hit = disc > 0
     integral = np.zeros(disc.shape)
     if np.any(hit):
         integral[hit] = chord_integral(o, d[hit], t_in[hit], t_out[hit], prim)
     alpha = np.where(hit, 1.0 - np.exp(-np.maximum(integral, 0.0)), 0.0)
+    if return_t_in:
+        return disc, integral, alpha, t_in
     return disc, integral, alpha
+
+
+def pair_colors(scene, p, cam, colors, o, d, t_in, hit):
+    """Colour of primitive p for each ray: its per-view colour, or (colour
+    mode 4) the per-ray relighting colour at the entry point (0 for misses)."""
+    if scene["color_mode"] != 4:
+        return np.broadcast_to(colors[p], d.shape)
+    out = np.zeros(d.shape)
+    if np.any(hit):
+        out[hit] = ray_colors(scene, p, cam, o, d[hit], t_in[hit])
+    return out
 
 
 def depth_order(proj):
@@ -79,7 +93,7 @@ def render_view(scene, cam, opts: RenderOptions = RenderOptions(), return_trace=
     """Render one view.  Returns dict(image (H,W,3), T (H,W), hit_pairs int)."""
     H, W = cam.height, cam.width
     proj = project_all(scene, cam, 16, 16, opts.z_near)
-    colors = primitive_colors(scene, cam)
+    colors = primitive_colors(scene, cam) if scene["color_mode"] != 4 else None
     Rs = quat_to_rotmat(scene["quats"])
     img = np.zeros((H, W, 3))
     T = np.ones((H, W))
@@ -89,7 +103,7 @@ def render_view(scene, cam, opts: RenderOptions = RenderOptions(), return_trace=
         x0, x1, y0, y1 = proj["rect"][p]
         rows, cols = np.mgrid[y0:y1 + 1, x0:x1 + 1]
         o, d = pixel_rays(cam, cols, rows)
-        disc, _, alpha = splat_alpha(o, d, primitive(scene, p, Rs[p]))
+        disc, _, alpha, t_in = splat_alpha(o, d, primitive(scene, p, Rs[p]), return_t_in=True)
         live = ~done[y0:y1 + 1, x0:x1 + 1]
         hit = (disc > 0) & live
         hit_pairs += int(hit.sum())
@@ -97,7 +111,7 @@ def render_view(scene, cam, opts: RenderOptions = RenderOptions(), return_trace=
         use = hit & (alpha >= opts.alpha_min) if opts.alpha_min > 0 else hit
         a = np.where(use, alpha, 0.0)
         Tb = T[y0:y1 + 1, x0:x1 + 1]
-        img[y0:y1 + 1, x0:x1 + 1] += (a * Tb)[..., None] * colors[p]
+        img[y0:y1 + 1, x0:x1 + 1] += (a * Tb)[..., None] * pair_colors(scene, p, cam, colors, o, d, t_in, disc > 0)
         Tn = Tb * (1.0 - a)
         T[y0:y1 + 1, x0:x1 + 1] = Tn
         if opts.t_eps > 0:
@@ -116,7 +130,7 @@ def render_pixels(scene, cam, cols, rows, opts: RenderOptions = RenderOptions(),
     images too large to render whole).  Returns (colors (n,3), T (n,), hits (n,))."""
     if proj is None:
         proj = project_all(scene, cam, 16, 16, opts.z_near)
-    colors = primitive_colors(scene, cam)
+    colors = primitive_colors(scene, cam) if scene["color_mode"] != 4 else None
     order = depth_order(proj)
     rect = proj["rect"][order]
     out_c = np.zeros((len(cols), 3))
@@ -128,14 +142,14 @@ def render_pixels(scene, cam, cols, rows, opts: RenderOptions = RenderOptions(),
         C = np.zeros(3)
         T = 1.0
         for p in sel:
-            disc, _, alpha = splat_alpha(o, d, primitive(scene, p))
+            disc, _, alpha, t_in = splat_alpha(o, d, primitive(scene, p), return_t_in=True)
             if disc[0] <= 0:
                 continue
             out_h[n] += 1
             a = min(alpha[0], opts.alpha_max)
             if opts.alpha_min > 0 and a < opts.alpha_min:
                 continue
-            C += colors[p] * a * T
+            C += pair_colors(scene, p, cam, colors, o, d, t_in, disc > 0)[0] * a * T
             T *= 1.0 - a
             if opts.t_eps > 0 and T < opts.t_eps:
                 break

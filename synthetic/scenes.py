@@ -71,7 +71,8 @@ class SceneConfig:
     n_hidden: int                   # N, width of the density MLP
     cams: List[tuple]               # list of (width, height)
     color_mode: int                 # 0 constant RGB, 1 colour MLP, 2 spherical harmonics (degree 3),
-                                    # 3 relighting colour (c_dc + colour MLP of view and light direction)
+                                    # 3 relighting colour (c_dc + colour MLP of view and light direction),
+                                    # 4 per-ray relighting colour (c_dc + colour MLP of entry point, ray and light direction)
     cmlp_width: int = 0
     cmlp_depth: int = 0             # number of hidden layers
     omega0: float = 10.0
@@ -181,7 +182,10 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
         sh = np.concatenate([rng.uniform(-1.5, 1.5, (P, 1, 3)), rng.uniform(-0.3, 0.3, (P, 15, 3))], axis=1)
     else:
         layers = []
-        n_in = (6 if cfg.color_mode == 3 else 3) + XI_DIM
+        # network inputs: view direction and xi (mode 1); plus the light
+        # direction (mode 3); entry point, ray direction and light direction
+        # (mode 4, per ray, no xi)
+        n_in = {1: 3 + XI_DIM, 3: 6 + XI_DIM, 4: 9}[cfg.color_mode]
         dims = [n_in] + [cfg.cmlp_width] * cfg.cmlp_depth + [3]
         for a, b in zip(dims[:-1], dims[1:]):
             bound = 1.0 / math.sqrt(a)
@@ -189,8 +193,8 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
             layers.append(rng.uniform(-bound, bound, (P, b)))
         cmlp = np.concatenate(layers, axis=1)
         assert cmlp.shape[1] == cmlp_param_count(cfg.cmlp_width, cfg.cmlp_depth, n_in)
-        xi = rng.standard_normal((P, XI_DIM))
-        if cfg.color_mode == 3:
+        xi = rng.standard_normal((P, XI_DIM)) if cfg.color_mode != 4 else None
+        if cfg.color_mode in (3, 4):
             colors = rng.uniform(0.0, 0.5, (P, 3))  # c_dc
     # opacity (used by Gaussians) is drawn last so the other arrays do not
     # depend on it
