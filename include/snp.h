@@ -32,8 +32,9 @@
  *    be normalised), w1 P x N x 3, b1 P x N, w2 P x N, b2 P, optionally wt
  *    P x N (time-conditioned density), and the colour: colors P x 3
  *    (color_mode 0), cmlp P x K with xi P x 8 (color_mode 1; K from 11
- *    network inputs), sh P x 16 x 3 (color_mode 2), or colors (c_dc), cmlp
- *    (K from 14 inputs) and xi (color_mode 3).
+ *    network inputs), sh P x 16 x 3 (color_mode 2), colors (c_dc), cmlp
+ *    (K from 14 inputs) and xi (color_mode 3), or colors (c_dc) and cmlp
+ *    (K from 9 inputs; color_mode 4).
  *  - A second primitive kind (snp_config.primitive = 1) renders 3D Gaussians
  *    through the same tiling, sorting and blending, as the 3DGS splatting
  *    kernel the paper measures against (App. A, integration-cost table):
@@ -88,7 +89,16 @@ typedef struct {
  *             3 = relighting colour: colors (c_dc) + the colour network of
  *             mode 1 with input [normalize(x_B - o_v), normalize(l_v - x_B),
  *             xi_p] (14 inputs; l_v = the camera's light), per (primitive,
- *             view).
+ *             view);
+ *             4 = per-ray relighting colour (the relighting application's
+ *             colour per view ray): colors (c_dc) + sigmoid(MLP(input)) per
+ *             (pixel, primitive) pair, input [(o + t_in d - x_B)/max(s_B),
+ *             d, normalize(l_v - x_B)] (9 inputs: the ray's entry point into
+ *             the ellipsoid normalised as the density's input, the unit ray
+ *             direction, the light direction relative to the centre), one
+ *             ReLU layer of cmlp_width = 16 units (cmlp_depth = 1), no xi;
+ *             built for N = 8, 16, 16 x 16 tiles with one pixel per thread
+ *             and backward batches of 8 (else SNP_ERR_UNSUPPORTED).
  *  tile_w, tile_h, px_per_lane: rasterizer tile shape and pixels per thread;
  *             supported shapes are listed by snp_supported_tiles().
  *  z_near     a primitive is culled for a view unless its whole ellipsoid
@@ -158,8 +168,8 @@ typedef struct {
 typedef struct {
   int64_t P;
   const float *centers, *scales, *quats, *w1, *b1, *w2, *b2;
-  const float *colors; /* color_mode 0, or c_dc of color_mode 3, else NULL */
-  const float *cmlp;   /* color_mode 1 or 3, else NULL */
+  const float *colors; /* color_mode 0, or c_dc of color_mode 3 or 4, else NULL */
+  const float *cmlp;   /* color_mode 1, 3 or 4, else NULL */
   const float *xi;     /* color_mode 1 or 3, else NULL */
   const float *sh;     /* color_mode 2: P x 16 x 3 (basis (l, m) in order (0,0), (1,-1), (1,0), (1,1), (2,-2) ... (3,3); channel), else NULL */
   const float *opacity; /* primitive 1: P opacities in (0, 1], used as given; else NULL */

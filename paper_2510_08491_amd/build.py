@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsnp.so")
 MICROBENCH = os.path.join(HERE, "snp_microbench")
 
-SOURCES = ["api.hip", "preprocess.hip", "binning.hip", "raster.hip", "loss.hip", "sh.hip", "train.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "binning.hip", "raster.hip", "loss.hip", "sh.hip", "train.hip", "relight.hip"]
 ARCH = "gfx950"
 # packed FP32 instructions are disabled on purpose (the compiler would form
 # them from ordinary float code)

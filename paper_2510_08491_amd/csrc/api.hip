@@ -24,6 +24,9 @@ struct Plan {
   int tile_bits;  // significant bits of the global tile id
   bool depth_first;  // depth sort of the pairs, then the instances by tile bits only
   bool tile_order_on;  // persistent launches take the tiles by instance count, descending
+  // colour mode 4: the colour network's table and biases, their gradients,
+  // and the rotation / scale gradients handed to the preprocess adjoint
+  size_t ctab, cbias, gctab, gcbias, extra_rs;
 };
 
 static bool valid_n(int n) { return n == 4 || n == 8 || n == 16 || n == 32; }
@@ -37,8 +40,12 @@ static snp_status check_cfg(const snp_config* cfg) {
     if (!valid_n(cfg->n_hidden)) return SNP_ERR_UNSUPPORTED;
     if (!(cfg->omega0 > 0.f) || !std::isfinite(cfg->omega0)) return SNP_ERR_INVALID;
   }
-  if (cfg->color_mode < 0 || cfg->color_mode > 3) return SNP_ERR_INVALID;
+  if (cfg->color_mode < 0 || cfg->color_mode > 4) return SNP_ERR_INVALID;
   if ((cfg->color_mode == 1 || cfg->color_mode == 3) && !cmlp_supported(cfg->cmlp_width, cfg->cmlp_depth))
+    return SNP_ERR_UNSUPPORTED;
+  if (cfg->color_mode == 4 &&
+      (gaussian(cfg) || !ray_colour_supported(cfg->cmlp_width, cfg->cmlp_depth) ||
+       !ray_colour_raster_supported(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->bwd_batch)))
     return SNP_ERR_UNSUPPORTED;
   if (!tile_supported(cfg->tile_w, cfg->tile_h, cfg->px_per_lane)) return SNP_ERR_UNSUPPORTED;
   if (!(cfg->z_near > 0.f)) return SNP_ERR_INVALID;
@@ -145,6 +152,16 @@ static snp_status make_plan(const snp_config* cfg, int64_t P, int32_t V, const s
   pl->tile_n = take(sizeof(unsigned long long));
   L.gview = take(gs ? 0 : sizeof(float) * (size_t)VP * kGViewFloats);
   L.gtable = take(sizeof(float) * (size_t)P * TS);
+  {
+    const bool rc = cfg->color_mode == 4 && !gs;
+    const size_t cts = rc ? (size_t)ray_colour_stride(cfg->cmlp_width, cfg->cmlp_depth) : 0;
+    const size_t cw = rc ? (size_t)cfg->cmlp_width : 0;
+    pl->ctab = take(sizeof(float) * (size_t)P * cts);
+    pl->cbias = take(sizeof(float) * (size_t)VP * cw);
+    pl->gctab = take(sizeof(float) * (size_t)P * cts);
+    pl->gcbias = take(sizeof(float) * (size_t)VP * cw);
+    pl->extra_rs = take(rc ? sizeof(float) * 12 * (size_t)P : 0);
+  }
   if (cfg->fwd_cache && !gs) {
     const int64_t n = cfg->fwd_cache_instances > 0 && cfg->fwd_cache_instances < cap ? cfg->fwd_cache_instances : cap;
     L.ahat_cache_bytes = sizeof(float) * (size_t)n * (size_t)(cfg->tile_w * cfg->tile_h);
@@ -171,6 +188,7 @@ static snp_status check_prims(const snp_config* cfg, const snp_prims* pr) {
   if (cfg->color_mode == 1 && (!pr->cmlp || !pr->xi)) return SNP_ERR_INVALID;
   if (cfg->color_mode == 2 && !pr->sh) return SNP_ERR_INVALID;
   if (cfg->color_mode == 3 && (!pr->cmlp || !pr->xi || !pr->colors)) return SNP_ERR_INVALID;
+  if (cfg->color_mode == 4 && (!pr->cmlp || !pr->colors)) return SNP_ERR_INVALID;
   return SNP_OK;
 }
 
@@ -182,6 +200,28 @@ static snp_status check_prims(const snp_config* cfg, const snp_prims* pr) {
 template <typename T>
 static T* wsp(void* ws, size_t off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+static RayColourArgs ray_colour_args(const snp_config* cfg, const snp_prims* pr, int32_t V, const Plan& pl,
+                                     void* ws) {
+  RayColourArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
+  ra.P = pr->P;
+  ra.V = V;
+  ra.W = cfg->cmlp_width;
+  ra.D = cfg->cmlp_depth;
+  ra.centers = pr->centers;
+  ra.scales = pr->scales;
+  ra.quats = pr->quats;
+  ra.cmlp = pr->cmlp;
+  ra.cams = wsp<CamDev>(ws, pl.L.cams);
+  ra.tile_counts = wsp<uint32_t>(ws, pl.L.tile_counts);
+  ra.ctab = wsp<float>(ws, pl.ctab);
+  ra.cbias = wsp<float>(ws, pl.cbias);
+  ra.gctab = wsp<float>(ws, pl.gctab);
+  ra.gcbias = wsp<float>(ws, pl.gcbias);
+  ra.extra_rs = wsp<float>(ws, pl.extra_rs);
+  return ra;
 }
 
 static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int32_t V, const snp_camera* cams,
@@ -252,6 +292,7 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
     sa.records = va.records;
     SNP_HIP(launch_sh_fwd(sa, st));
   }
+  if (cfg->color_mode == 4) SNP_HIP(launch_ray_colour_fwd(ray_colour_args(cfg, pr, V, pl, ws), st));
   return SNP_OK;
 }
 
@@ -358,6 +399,12 @@ static RasterArgs raster_args(const snp_config* cfg, int64_t P, int32_t V, const
   a.cache_instances = cfg->fwd_cache ? (int64_t)(L.ahat_cache_bytes / (sizeof(float) * cfg->tile_w * cfg->tile_h)) : 0;
   a.counters = wsp<unsigned long long>(ws, L.counters);
   a.tile_pairs = wsp<uint32_t>(ws, L.tile_pairs);
+  if (cfg->color_mode == 4) {
+    a.ctab = wsp<float>(ws, pl.ctab);
+    a.cbias = wsp<float>(ws, pl.cbias);
+    a.gctab = wsp<float>(ws, pl.gctab);
+    a.gcbias = wsp<float>(ws, pl.gcbias);
+  }
   a.t_eps = cfg->t_eps;
   a.alpha_min = cfg->alpha_min;
   a.alpha_max = cfg->alpha_max;
@@ -388,6 +435,9 @@ static void timer_mark(int which, hipStream_t st) {
   if (which == 3) g_timer.have_bwd = true;
 }
 
+// depth of the per-ray colour network the rasterizers evaluate (0: none)
+static int ray_depth(const snp_config* cfg) { return cfg->color_mode == 4 ? cfg->cmlp_depth : 0; }
+
 static snp_status do_forward(const snp_config* cfg, int64_t P, int32_t V, const Plan& pl, void* ws, float* images,
                              float* final_T, int count, hipStream_t st) {
   RasterArgs a = raster_args(cfg, P, V, pl, ws);
@@ -401,7 +451,7 @@ static snp_status do_forward(const snp_config* cfg, int64_t P, int32_t V, const 
                                     st));
   else
     SNP_HIP(launch_render_fwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, cfg->px_per_lane, cfg->persistent != 0,
-                              count != 0, a, st));
+                              count != 0, ray_depth(cfg), a, st));
   timer_mark(1, st);
   return SNP_OK;
 }
@@ -416,10 +466,21 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
   SNP_HIP(zero_f32(a.gview, (int64_t)V * P * kGViewFloats, st));
   SNP_HIP(zero_f32(a.gtable, P * (int64_t)L.table_stride, st));
   if (cfg->persistent) SNP_HIP(zero_counter(a.counters + CNT_QUEUE_BWD, st));
+  if (cfg->color_mode == 4) {
+    SNP_HIP(zero_f32(a.gctab, P * (int64_t)ray_colour_stride(cfg->cmlp_width, cfg->cmlp_depth), st));
+    SNP_HIP(zero_f32(a.gcbias, (int64_t)V * P * cfg->cmlp_width, st));
+  }
   timer_mark(2, st);
   const int nb = cfg->bwd_batch ? cfg->bwd_batch : bwd_batch_default(cfg->tile_w, cfg->tile_h);
-  SNP_HIP(launch_render_bwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, nb, cfg->persistent != 0, a, st));
+  SNP_HIP(launch_render_bwd(cfg->n_hidden, cfg->tile_w, cfg->tile_h, nb, cfg->persistent != 0, ray_depth(cfg), a,
+                            st));
   timer_mark(3, st);
+  if (cfg->color_mode == 4) {
+    RayColourArgs ra = ray_colour_args(cfg, pr, V, pl, ws);
+    ra.g_cmlp = g->cmlp;
+    ra.g_centers = g->centers;
+    SNP_HIP(launch_ray_colour_bwd(ra, st));
+  }
   if (cfg->color_mode == 1 || cfg->color_mode == 3) {
     CmlpArgs ca;
     std::memset(&ca, 0, sizeof(ca));
@@ -471,6 +532,7 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
   pa.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
   pa.gview = a.gview;
   pa.gtable = a.gtable;
+  pa.extra_rs = cfg->color_mode == 4 ? wsp<float>(ws, pl.extra_rs) : nullptr;
   pa.g = *g;
   SNP_HIP(launch_preprocess_bwd(pa, st));
   return SNP_OK;
@@ -485,7 +547,9 @@ static snp_status zero_grads(const snp_config* cfg, int64_t P, const snp_grads* 
   SNP_HIP(zero_f32(g->b1, N * P, st));
   SNP_HIP(zero_f32(g->w2, N * P, st));
   SNP_HIP(zero_f32(g->b2, P, st));
-  if (cfg->color_mode == 0 || cfg->color_mode == 3) SNP_HIP(zero_f32(g->colors, 3 * P, st));
+  if (cfg->color_mode == 0 || cfg->color_mode == 3 || cfg->color_mode == 4) SNP_HIP(zero_f32(g->colors, 3 * P, st));
+  if (cfg->color_mode == 4)
+    SNP_HIP(zero_f32(g->cmlp, (int64_t)ray_colour_param_count(cfg->cmlp_width, cfg->cmlp_depth) * P, st));
   if (cfg->color_mode == 1 || cfg->color_mode == 3) {
     SNP_HIP(zero_f32(g->cmlp, (int64_t)cmlp_param_count(cfg->cmlp_width, cfg->cmlp_depth, cfg->color_mode == 3) * P,
                      st));

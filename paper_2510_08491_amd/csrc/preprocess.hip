@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(256) preprocess_views_kernel(ViewArgs a) {
       r4[0] = make_float4((float)dc[0], (float)dc[1], (float)dc[2], rxf);
       r4[1] = make_float4((float)gx[0], (float)gx[1], (float)gx[2], ryf);
       float cr = 0.f, cg = 0.f, cb = 0.f;
-      if (a.color_mode == 0) {
+      if (a.color_mode == 0 || a.color_mode == 4) {  // the constant colour, or c_dc of the per-ray colour
         cr = a.colors[3 * p];
         cg = a.colors[3 * p + 1];
         cb = a.colors[3 * p + 2];
@@ -791,12 +791,12 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(PreBwdArgs a) {
       }
     for (int c = 0; c < 3; ++c) gxb[c] -= U[0][c] * g_op[0] + U[1][c] * g_op[1] + U[2][c] * g_op[2];
     // colour (the constant colour, or the relighting colour's c_dc)
-    if (a.color_mode == 0 || a.color_mode == 3) {
+    if (a.color_mode == 0 || a.color_mode == 3 || a.color_mode == 4) {
       gcol[0] += gv[18];
       gcol[1] += gv[19];
       gcol[2] += gv[20];
     }
-    if (a.color_mode != 0) {
+    if (a.color_mode >= 1 && a.color_mode <= 3) {
       // dir = normalize(x_B - o): d dir / d x_B = (I - dir dir^T) / |x_B - o|
       const double dvec[3] = {-om[0], -om[1], -om[2]};
       const double len = sqrt(dvec[0] * dvec[0] + dvec[1] * dvec[1] + dvec[2] * dvec[2]);
@@ -806,9 +806,16 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(PreBwdArgs a) {
       for (int c = 0; c < 3; ++c) gxb[c] += (gd[c] - dir[c] * dd) / len;
     }
   }
-  // U[r][c] = Rp[c][r] / s[r]
+  // U[r][c] = Rp[c][r] / s[r]; plus the per-ray colour network's own
+  // rotation and scale gradients
   double gR[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   double gs[3] = {0, 0, 0};
+  if (a.extra_rs) {
+    const float* ex = a.extra_rs + p * 12;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) gR[r][c] = ex[3 * r + c];
+    for (int c = 0; c < 3; ++c) gs[c] = ex[9 + c];
+  }
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) {
       gR[c][r] += gU[r][c] / s[r];
@@ -863,7 +870,7 @@ __global__ void __launch_bounds__(256) preprocess_bwd_kernel(PreBwdArgs a) {
     for (int k = 0; k < 3; ++k) a.g.scales[3 * p + k] += (float)gs[k];
   if (a.g.centers)
     for (int k = 0; k < 3; ++k) a.g.centers[3 * p + k] += (float)gxb[k];
-  if ((a.color_mode == 0 || a.color_mode == 3) && a.g.colors)
+  if ((a.color_mode == 0 || a.color_mode == 3 || a.color_mode == 4) && a.g.colors)
     for (int k = 0; k < 3; ++k) a.g.colors[3 * p + k] += (float)gcol[k];
 }
 

@@ -30,9 +30,10 @@
 namespace snp {
 
 // instances per forward batch: 64, or 32 for N = 32 (whose tables would take
-// most of the LDS at 64 and cut the occupancy)
-template <int N>
-constexpr int fwd_batch() { return N >= 32 ? 32 : 64; }
+// most of the LDS at 64 and cut the occupancy), or 8 with the per-ray colour
+// network (its table takes 1.7 KB per instance)
+template <int N, int CD = 0>
+constexpr int fwd_batch() { return CD > 0 ? 8 : (N >= 32 ? 32 : 64); }
 
 
 // sum over the 64 lanes; the total ends in lane 63 (other lanes hold partials)
@@ -120,14 +121,25 @@ struct Stage {
   uint32_t id[B];
 };
 
-// Stages one batch: instance ids and rectangles, records and tables,
-// gathered by primitive id as float4.  The
+// Per-ray colour network of a batch (colour mode 4, width 16, CD hidden
+// layers): each instance's table row and its view's first-layer bias.
+template <int CD, int B>
+struct ColourStage {
+  static constexpr int T4 = RayColourLayout<16, CD>::CTS / 4;
+  float4 t[B][T4];
+  float4 b[B][4];
+};
+
+// Stages one batch: instance ids and rectangles, records and tables (and,
+// with a colour stage, the colour tables and biases), gathered by primitive
+// id as float4.  The
 // threads that gather read the id from global memory themselves, so one
 // barrier (at the end) suffices.  The caller's previous barrier (the end of
 // the previous batch, or the work-queue fetch) guarantees nobody still
 // reads the stage.
-template <int N, int NT, int B>
-__device__ __forceinline__ void stage_batch(Stage<N, B>& S, const RasterArgs& a, int v, uint32_t b0, int nb) {
+template <int N, int NT, int B, int CD = 0>
+__device__ __forceinline__ void stage_batch(Stage<N, B>& S, const RasterArgs& a, int v, uint32_t b0, int nb,
+                                            ColourStage<(CD > 0 ? CD : 1), B>* cs = nullptr) {
   const int64_t vbase = (int64_t)v * a.P;
   for (int t = threadIdx.x; t < nb; t += NT) {
     const uint32_t p = a.values[b0 + t];
@@ -146,7 +158,69 @@ __device__ __forceinline__ void stage_batch(Stage<N, B>& S, const RasterArgs& a,
     else
       S.tab[j][c - 6] = tab4[(int64_t)p * T4 + (c - 6)];
   }
+  if constexpr (CD > 0) {
+    constexpr int C4 = ColourStage<CD, B>::T4;
+    const float4* ct4 = reinterpret_cast<const float4*>(a.ctab);
+    const float4* cb4 = reinterpret_cast<const float4*>(a.cbias);
+    for (int idx = threadIdx.x; idx < nb * (C4 + 4); idx += NT) {
+      const int j = idx / (C4 + 4), c = idx - j * (C4 + 4);
+      const uint32_t p = a.values[b0 + j];
+      if (c < C4)
+        cs->t[j][c] = ct4[(int64_t)p * C4 + c];
+      else
+        cs->b[j][c - C4] = cb4[(vbase + p) * 4 + (c - C4)];
+    }
+  }
   __syncthreads();
+}
+
+// The per-ray colour network on one pair: the entry point u (unit-sphere
+// frame) and the ray direction n = d'/L give the first layer, ReLU hidden
+// layers, sigmoid output (kept with the activations for the adjoint).
+template <int CD>
+struct RayAct {
+  float h1[16];
+  float h2[CD == 2 ? 16 : 1];
+  float sg[3];
+};
+
+template <int CD>
+__device__ __forceinline__ void ray_net(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
+                                        float n1, float n2, RayAct<CD>& r) {
+  using Lt = RayColourLayout<16, CD>;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float h = cb[k];
+    h = __builtin_fmaf(ct[Lt::AU + 3 * k + 0], u0, h);
+    h = __builtin_fmaf(ct[Lt::AU + 3 * k + 1], u1, h);
+    h = __builtin_fmaf(ct[Lt::AU + 3 * k + 2], u2, h);
+    h = __builtin_fmaf(ct[Lt::AD + 3 * k + 0], n0, h);
+    h = __builtin_fmaf(ct[Lt::AD + 3 * k + 1], n1, h);
+    h = __builtin_fmaf(ct[Lt::AD + 3 * k + 2], n2, h);
+    r.h1[k] = fmaxf(h, 0.f);
+    // the weights are broadcast LDS reads: without a compiler barrier the
+    // whole network's reads are hoisted and held in registers
+    asm volatile("" ::: "memory");
+  }
+  if constexpr (CD == 2) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      float h = ct[Lt::BH + k];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) h = __builtin_fmaf(ct[Lt::WH + 16 * k + i], r.h1[i], h);
+      r.h2[k] = fmaxf(h, 0.f);
+      asm volatile("" ::: "memory");  // one row of Wh in registers at a time
+    }
+  }
+  const float* hl = CD == 2 ? r.h2 : r.h1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float o = ct[Lt::BO + c];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) o = __builtin_fmaf(ct[Lt::WO + 16 * c + k], hl[k], o);
+    r.sg[c] = fast_rcp(1.f + exp2_fast(-o * kLog2e));
+    asm volatile("" ::: "memory");
+  }
 }
 
 // geometry of one (pixel, primitive) pair from a staged record
@@ -235,11 +309,14 @@ __device__ __forceinline__ void count_tile_pairs(uint32_t* slot, uint32_t v) {
 // ---------------------------------------------------------------------------
 // forward
 // ---------------------------------------------------------------------------
-template <int N, int TW, int TH, int PPL, bool PERSIST, bool COUNT>
+// CD > 0: the per-ray colour network of colour mode 4 (depth CD, width 16)
+// colours each pair; otherwise the pair takes its record's colour.
+template <int N, int TW, int TH, int PPL, bool PERSIST, bool COUNT, int CD = 0>
 __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH / PPL;
-  constexpr int FB = fwd_batch<N>();
+  constexpr int FB = fwd_batch<N, CD>();
   __shared__ Stage<N, FB> S;
+  __shared__ ColourStage<(CD > 0 ? CD : 1), (CD > 0 ? FB : 1)> CS;
   __shared__ int s_item;
   unsigned long long npairs = 0, nlive = 0;
   int item = blockIdx.x;
@@ -272,7 +349,11 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += FB) {
       const int nb = (int)min((uint32_t)FB, end - b0);
-      stage_batch<N, NT, FB>(S, a, v, b0, nb);
+      if constexpr (CD > 0)
+        stage_batch<N, NT, FB, CD>(S, a, v, b0, nb, &CS);
+      else
+        stage_batch<N, NT, FB>(S, a, v, b0, nb);
+#pragma unroll 1
       for (int j = 0; j < nb; ++j) {
         const int4 rc = S.rect[j];
         if (rc.y < pb.wx0 || rc.x > pb.wx1 || rc.w < pb.wy0 || rc.z > pb.wy1) continue;  // wave-uniform
@@ -319,14 +400,27 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
         }
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
+          // the pair's colour: the record's, or c_dc + the per-ray network at
+          // the entry point u = p' - e' with the direction d' / L
+          float c0 = r2.w, c1 = r3.w, c2 = r4.w;
+          if constexpr (CD > 0) {
+            RayAct<CD> ra;
+            const float iL = fast_rcp(pb.L[q]);
+            ray_net<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
+                        g[q].p0 - g[q].e0, g[q].p1 - g[q].e1, g[q].p2 - g[q].e2, g[q].d0 * iL, g[q].d1 * iL,
+                        g[q].d2 * iL, ra);
+            c0 += ra.sg[0];
+            c1 += ra.sg[1];
+            c2 += ra.sg[2];
+          }
           if (hit[q]) {
             const float al = alpha_of(ahat[q], a.alpha_max);
             if (COUNT) nlive += (ahat[q] > 0.f && al < a.alpha_max) ? 1 : 0;
             if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
               const float w = al * T[q];
-              C0[q] = __builtin_fmaf(r2.w, w, C0[q]);
-              C1[q] = __builtin_fmaf(r3.w, w, C1[q]);
-              C2[q] = __builtin_fmaf(r4.w, w, C2[q]);
+              C0[q] = __builtin_fmaf(c0, w, C0[q]);
+              C1[q] = __builtin_fmaf(c1, w, C1[q]);
+              C2[q] = __builtin_fmaf(c2, w, C2[q]);
               T[q] = T[q] * (1.f - al);
               if (T[q] < a.t_eps) done[q] = true;
             }
@@ -594,6 +688,122 @@ __device__ __forceinline__ float cross_rows_pair(float a, float b) {
 constexpr float kDsnC1n = (kTwoPi * kTwoPi) / 3.0f;
 constexpr float kDsnC3n = -(kTwoPi * kTwoPi * kTwoPi * kTwoPi) / 30.0f;
 
+// Sum over the wave of 16 values: lane l < 16 ends with the sum of value
+// 8 b3 + 4 b1 + 2 b0 + b2 (b = the bits of l).
+__device__ __forceinline__ float wave_sum16(const float* v, bool sel1, bool sel2, bool sel3, bool sel4) {
+  float x4[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    x4[q] = tb_level<kDppXor1>(tb_level<kDppHalfMirror>(v[4 * q], v[4 * q + 1], sel1),
+                               tb_level<kDppHalfMirror>(v[4 * q + 2], v[4 * q + 3], sel1), sel2);
+  return cross_rows_sum(tb_level<kDppRor8>(tb_level<kDppXor2>(x4[0], x4[1], sel3),
+                                           tb_level<kDppXor2>(x4[2], x4[3], sel3), sel4));
+}
+
+// Adjoint of the per-ray colour network on the wave's 64 pairs (every lane
+// takes part; a lane without a pair passes gc = 0).  gc: d loss / d colour
+// of the lane's pair.  The weight gradients summed over the wave go to the
+// primitive's table gradient gt and the (view, primitive) bias gradient gb
+// (global), the offset c_dc's to acc_col (LDS); returns d loss / d u and
+// d loss / d n of the lane's pair.
+template <int CD>
+__device__ __forceinline__ void ray_net_adjoint(const float* ct, const float* cb, float u0, float u1, float u2,
+                                                float n0, float n1, float n2, float gc0, float gc1, float gc2,
+                                                float* gt, float* gb, float* acc_col, int lane, int idx16,
+                                                bool sel1, bool sel2, bool sel3, bool sel4, float* gu, float* gn) {
+  using Lt = RayColourLayout<16, CD>;
+  RayAct<CD> ra;
+  ray_net<CD>(ct, cb, u0, u1, u2, n0, n1, n2, ra);
+  const float go[3] = {gc0 * ra.sg[0] * (1.f - ra.sg[0]), gc1 * ra.sg[1] * (1.f - ra.sg[1]),
+                       gc2 * ra.sg[2] * (1.f - ra.sg[2])};
+  auto flush16 = [&](float* base, const float* v16) {
+    const float z = wave_sum16(v16, sel1, sel2, sel3, sel4);
+    if (lane < 16 && z != 0.f) atomic_add_f32(base + idx16, z);
+    asm volatile("" ::: "memory");  // one block of 16 sums in registers at a time
+  };
+  const float* hl = CD == 2 ? ra.h2 : ra.h1;
+  float v[16];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = go[c] * hl[k];
+    flush16(gt + Lt::WO + 16 * c, v);
+  }
+  {
+    // output bias and the colour offset
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = 0.f;
+    v[0] = go[0];
+    v[1] = go[1];
+    v[2] = go[2];
+    v[3] = gc0;
+    v[4] = gc1;
+    v[5] = gc2;
+    const float z = wave_sum16(v, sel1, sel2, sel3, sel4);
+    if (lane < 16 && z != 0.f) {
+      if (idx16 < 3)
+        atomic_add_f32(gt + Lt::BO + idx16, z);
+      else if (idx16 < 6)
+        atomicAdd(acc_col + idx16 - 3, z);
+    }
+  }
+  // d loss / d pre-activation of the last hidden layer
+  float gh[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float t = go[0] * ct[Lt::WO + k] + go[1] * ct[Lt::WO + 16 + k] + go[2] * ct[Lt::WO + 32 + k];
+    gh[k] = hl[k] > 0.f ? t : 0.f;
+    asm volatile("" ::: "memory");
+  }
+  if constexpr (CD == 2) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = gh[r] * ra.h1[i];
+      flush16(gt + Lt::WH + 16 * r, v);
+    }
+    flush16(gt + Lt::BH, gh);
+    float g1[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      float t = 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) t = __builtin_fmaf(ct[Lt::WH + 16 * r + i], gh[r], t);
+      g1[i] = ra.h1[i] > 0.f ? t : 0.f;
+      asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) gh[i] = g1[i];
+  }
+  // first layer: Au (k * 3 + j), Ad, the bias
+  const float uu[3] = {u0, u1, u2}, nn[3] = {n0, n1, n2};
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = gh[(16 * b + t) / 3] * uu[(16 * b + t) % 3];
+    flush16(gt + Lt::AU + 16 * b, v);
+  }
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = gh[(16 * b + t) / 3] * nn[(16 * b + t) % 3];
+    flush16(gt + Lt::AD + 16 * b, v);
+  }
+  flush16(gb, gh);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    float tu = 0.f, tn = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      tu = __builtin_fmaf(ct[Lt::AU + 3 * k + j], gh[k], tu);
+      tn = __builtin_fmaf(ct[Lt::AD + 3 * k + j], gh[k], tn);
+    }
+    gu[j] = tu;
+    gn[j] = tn;
+    asm volatile("" ::: "memory");
+  }
+}
+
 // Length of the un-normalised camera ray R^-1 ((x+1/2-cx)/fx, (y+1/2-cy)/fy, 1).
 __device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float pyc) {
   const float cxn = (pxc - cam.cx) / cam.fx;
@@ -619,8 +829,17 @@ __device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float 
 // record coefficients over the wave into LDS accumulators, flushed to HBM
 // once per batch.  Every lane of phase 2 carries gradient, and each wave
 // reduction covers 64 live pairs.
-template <int N, int TW, int TH, int NB, bool PERSIST>
-__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5))) render_bwd_kernel(RasterArgs a) {
+//
+// With the per-ray colour network (CD > 0, colour mode 4) phase 1 evaluates
+// each pair's colour, lists every pair that blends (alpha > 0) with its
+// weight alpha T, and phase 2 adds the network's adjoint: the weight
+// gradients summed over the 64 pairs into the per-primitive table gradient
+// (and the per-(view, primitive) bias gradient), the colour offset into the
+// record gradient, and the entry point's and direction's gradients into the
+// geometry chain.
+template <int N, int TW, int TH, int NB, bool PERSIST, int CD = 0>
+__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(CD > 0 ? 2 : 5)))
+render_bwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
   constexpr int TS = 5 * N + 4;
@@ -631,6 +850,9 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
   __shared__ uint16_t s_pix[NB][NT];
   __shared__ float s_wq[NB][NT];
   __shared__ float s_gh[NB][NT];
+  __shared__ ColourStage<(CD > 0 ? CD : 1), (CD > 0 ? NB : 1)> CS;
+  __shared__ float s_wt[CD > 0 ? NB : 1][CD > 0 ? NT : 1];  // alpha T of each listed pair
+  __shared__ float s_G[CD > 0 ? NT : 1][3];                 // d loss / d colour per pixel
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // selector bits and value index of the transposed row reductions
@@ -666,11 +888,19 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
     float B0 = done ? 0.f : a.images_in[3 * pxi + 0];
     float B1 = done ? 0.f : a.images_in[3 * pxi + 1];
     float B2 = done ? 0.f : a.images_in[3 * pxi + 2];
+    if constexpr (CD > 0) {  // read by phase 2 after the first stage's barrier
+      s_G[pb.loc[0]][0] = G0;
+      s_G[pb.loc[0]][1] = G1;
+      s_G[pb.loc[0]][2] = G2;
+    }
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
       if (threadIdx.x < NB * NW) (&s_cnt[0][0])[threadIdx.x] = 0u;
-      stage_batch<N, NT, NB>(S, a, v, b0, nb);
+      if constexpr (CD > 0)
+        stage_batch<N, NT, NB, CD>(S, a, v, b0, nb, &CS);
+      else
+        stage_batch<N, NT, NB>(S, a, v, b0, nb);
       // ---------------- phase 1: pixels ----------------
       // One instance for this thread's pixel.  `cached`: the integral comes
       // from the forward's store (ahc) instead of the density MLP.
@@ -702,33 +932,46 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           QB = Q + tabf[5 * N];
           ahat = 2.f * pb.L[0] * g.H * QB;
         }
-        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, wq = 0.f, gH = 0.f;
+        // the pair's colour (the per-ray network's, as in the forward)
+        float c0 = r2.w, c1 = r3.w, c2 = r4.w;
+        if constexpr (CD > 0) {
+          RayAct<CD> ra;
+          const float iL = fast_rcp(pb.L[0]);
+          ray_net<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
+                      g.p0 - g.e0, g.p1 - g.e1, g.p2 - g.e2, g.d0 * iL, g.d1 * iL, g.d2 * iL, ra);
+          c0 += ra.sg[0];
+          c1 += ra.sg[1];
+          c2 += ra.sg[2];
+        }
+        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, wq = 0.f, gH = 0.f, wt = 0.f;
         bool live = false;
         if (hit) {
           const float al = alpha_of(ahat, a.alpha_max);
           if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
-            const float wt = al * T;
+            wt = al * T;
             gc0 = G0 * wt;
             gc1 = G1 * wt;
             gc2 = G2 * wt;
-            B0 = __builtin_fmaf(-r2.w, wt, B0);
-            B1 = __builtin_fmaf(-r3.w, wt, B1);
-            B2 = __builtin_fmaf(-r4.w, wt, B2);
+            B0 = __builtin_fmaf(-c0, wt, B0);
+            B1 = __builtin_fmaf(-c1, wt, B1);
+            B2 = __builtin_fmaf(-c2, wt, B2);
+            if (CD > 0) live = al > 0.f;  // its colour gradient is G_c alpha T
             if (ahat > 0.f && al < a.alpha_max) {
               const float ta = T * (1.f - al);
-              const float G = G0 * (r2.w * ta - B0) + G1 * (r3.w * ta - B1) + G2 * (r4.w * ta - B2);
+              const float G = G0 * (c0 * ta - B0) + G1 * (c1 * ta - B1) + G2 * (c2 * ta - B2);
               wq = G * 2.f * pb.L[0] * g.H;  // d loss / d Q
               // d loss / d H (direct) = G 2 L (Q + b2); from the stored integral
               // alpha-hat = 2 L H (Q + b2) when cached (H > 0 for a hit)
               gH = cached ? G * ahat * fast_rcp(g.H) : G * 2.f * pb.L[0] * QB;
-              live = wq != 0.f || gH != 0.f;
+              live = live || wq != 0.f || gH != 0.f;
             }
             T = T * (1.f - al);
             if (T < a.t_eps) done = true;
           }
         }
-        // colour gradient: one transposed reduction of the three sums
-        {
+        // colour gradient: one transposed reduction of the three sums (with
+        // the per-ray colour, phase 2 sums it)
+        if constexpr (CD == 0) {
           const float z = nb_level<kDppRor8>(nb_level<kDppXor2>(
               tb_level<kDppXor1>(tb_level<kDppHalfMirror>(gc0, gc1, sel1), tb_level<kDppHalfMirror>(gc2, 0.f, sel1), sel2)));
           const int i4 = idx16 & 3;
@@ -745,6 +988,7 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
             s_pix[j][pos] = (uint16_t)pb.loc[0];
             s_wq[j][pos] = wq;
             s_gh[j][pos] = gH;
+            if constexpr (CD > 0) s_wt[j][pos] = wt;
           }
           if (lane == 0) s_cnt[j][wave] = (uint32_t)__popcll(lm);
         }
@@ -804,6 +1048,8 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
             gHd = 0.f;
           }
           const float sq_pair = G.sq;  // kept through the unit loop (the rest is recomputed)
+          float wtp = 0.f;  // alpha T of the pair (per-ray colour)
+          if constexpr (CD > 0) wtp = (act && gh) ? s_wt[j][slot] : 0.f;
           const float4* tab = S.tab[j];
           const float* tabf = reinterpret_cast<const float*>(S.tab[j]);
           float* acc = s_acc[j];
@@ -906,12 +1152,33 @@ __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(5)
           ge0 *= -kTwoPi;
           ge1 *= -kTwoPi;
           ge2 *= -kTwoPi;
+          float gn[3] = {0.f, 0.f, 0.f}, iLp = 0.f;
+          if constexpr (CD > 0) {
+            // the colour network's adjoint; its entry point u = p' - e' and
+            // direction n = d' / L feed the chain below
+            iLp = 1.f / ray_length(cam, pxc, pyc);
+            const uint32_t pid = __builtin_amdgcn_readfirstlane(S.id[j]);
+            float gu[3];
+            ray_net_adjoint<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
+                                G.p0 - G.e0, G.p1 - G.e1, G.p2 - G.e2, G.d0 * iLp, G.d1 * iLp, G.d2 * iLp,
+                                s_G[pix][0] * wtp, s_G[pix][1] * wtp, s_G[pix][2] * wtp,
+                                a.gctab + (int64_t)pid * RayColourLayout<16, CD>::CTS,
+                                a.gcbias + ((int64_t)v * a.P + pid) * 16, acc + TS + 18, lane, idx16, sel1, sel2,
+                                sel3, sel4, gu, gn);
+            gp0 += gu[0];
+            gp1 += gu[1];
+            gp2 += gu[2];
+            ge0 -= gu[0];
+            ge1 -= gu[1];
+            ge2 -= gu[2];
+          }
           float R[18];
 #pragma unroll
           for (int r = 0; r < 18; ++r) R[r] = 0.f;
-          if (wq != 0.f || gHd != 0.f) {
+          if (wq != 0.f || gHd != 0.f || wtp != 0.f) {
             const float gHt = gHd + ge0 * G.d0 + ge1 * G.d1 + ge2 * G.d2;
-            float gd0 = ge0 * G.H, gd1 = ge1 * G.H, gd2 = ge2 * G.H;
+            float gd0 = __builtin_fmaf(gn[0], iLp, ge0 * G.H), gd1 = __builtin_fmaf(gn[1], iLp, ge1 * G.H),
+                  gd2 = __builtin_fmaf(gn[2], iLp, ge2 * G.H);
             const float gX0 = gp0 * G.rA, gX1 = gp1 * G.rA, gX2 = gp2 * G.rA;
             const float gA_p = -(gp0 * G.p0 + gp1 * G.p1 + gp2 * G.p2) * G.rA;
             const float gdisc = gHt * G.rA * 0.5f * fast_rcp(G.sq);
@@ -1030,23 +1297,25 @@ static int persistent_grid(K kernel, int threads, int total) {
   return g < 1 ? 1 : g;
 }
 
-template <int N, int TW, int TH, int PPL>
+template <int N, int TW, int TH, int PPL, int CD = 0>
 static hipError_t fwd_shape(const RasterArgs& a, bool persist, bool count, hipStream_t st) {
   constexpr int NT = TW * TH / PPL;
   if (a.total_tiles <= 0) return hipSuccess;
   if (persist) {
     if (count) {
-      auto k = render_fwd_kernel<N, TW, TH, PPL, true, true>;
+      auto k = render_fwd_kernel<N, TW, TH, PPL, true, true, CD>;
       hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
     } else {
-      auto k = render_fwd_kernel<N, TW, TH, PPL, true, false>;
+      auto k = render_fwd_kernel<N, TW, TH, PPL, true, false, CD>;
       hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
     }
   } else {
     if (count)
-      hipLaunchKernelGGL((render_fwd_kernel<N, TW, TH, PPL, false, true>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+      hipLaunchKernelGGL((render_fwd_kernel<N, TW, TH, PPL, false, true, CD>), dim3(a.total_tiles), dim3(NT), 0, st,
+                         a);
     else
-      hipLaunchKernelGGL((render_fwd_kernel<N, TW, TH, PPL, false, false>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+      hipLaunchKernelGGL((render_fwd_kernel<N, TW, TH, PPL, false, false, CD>), dim3(a.total_tiles), dim3(NT), 0,
+                         st, a);
   }
   return hipGetLastError();
 }
@@ -1073,17 +1342,37 @@ static hipError_t fwd_gauss_shape(const RasterArgs& a, bool persist, bool count,
   return hipGetLastError();
 }
 
-template <int N, int TW, int TH, int NB>
+template <int N, int TW, int TH, int NB, int CD = 0>
 static hipError_t bwd_shape(const RasterArgs& a, bool persist, hipStream_t st) {
   constexpr int NT = TW * TH;
   if (a.total_tiles <= 0) return hipSuccess;
   if (persist) {
-    auto k = render_bwd_kernel<N, TW, TH, NB, true>;
+    auto k = render_bwd_kernel<N, TW, TH, NB, true, CD>;
     hipLaunchKernelGGL(k, dim3(persistent_grid(k, NT, a.total_tiles)), dim3(NT), 0, st, a);
   } else {
-    hipLaunchKernelGGL((render_bwd_kernel<N, TW, TH, NB, false>), dim3(a.total_tiles), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((render_bwd_kernel<N, TW, TH, NB, false, CD>), dim3(a.total_tiles), dim3(NT), 0, st, a);
   }
   return hipGetLastError();
+}
+
+// The per-ray colour network (colour mode 4) is built for N = 8 and 16,
+// 16 x 16 tiles with one pixel per thread and backward batches of 8.
+bool ray_colour_raster_supported(int N, int tw, int th, int ppl, int nb) {
+  return (N == 8 || N == 16) && tw == 16 && th == 16 && ppl == 1 && (nb == 0 || nb == 8);
+}
+
+// one hidden layer (the kernels are written for two as well, but the
+// adjoint of the 16 x 16 layer does not fit the register file)
+template <int N>
+static hipError_t fwd_ray(const RasterArgs& a, int cd, bool persist, bool count, hipStream_t st) {
+  if (cd == 1) return fwd_shape<N, 16, 16, 1, 1>(a, persist, count, st);
+  return hipErrorInvalidValue;
+}
+
+template <int N>
+static hipError_t bwd_ray(const RasterArgs& a, int cd, bool persist, hipStream_t st) {
+  if (cd == 1) return bwd_shape<N, 16, 16, 8, 1>(a, persist, st);
+  return hipErrorInvalidValue;
 }
 
 template <int N>
@@ -1109,8 +1398,12 @@ static hipError_t bwd_n(const RasterArgs& a, int tw, int th, int nb, bool persis
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
+hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, int cd, const RasterArgs& a,
                              hipStream_t st) {
+  if (cd > 0) {
+    if (!ray_colour_raster_supported(N, tw, th, ppl, 0)) return hipErrorInvalidValue;
+    return N == 8 ? fwd_ray<8>(a, cd, persist, count, st) : fwd_ray<16>(a, cd, persist, count, st);
+  }
   switch (N) {
     case 4: return fwd_n<4>(a, tw, th, ppl, persist, count, st);
     case 8: return fwd_n<8>(a, tw, th, ppl, persist, count, st);
@@ -1131,12 +1424,17 @@ hipError_t launch_render_fwd_gauss(int tw, int th, int ppl, bool persist, bool c
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_render_bwd(int N, int tw, int th, int ppl, bool persist, const RasterArgs& a, hipStream_t st) {
+hipError_t launch_render_bwd(int N, int tw, int th, int nb, bool persist, int cd, const RasterArgs& a,
+                             hipStream_t st) {
+  if (cd > 0) {
+    if (!ray_colour_raster_supported(N, tw, th, 1, nb)) return hipErrorInvalidValue;
+    return N == 8 ? bwd_ray<8>(a, cd, persist, st) : bwd_ray<16>(a, cd, persist, st);
+  }
   switch (N) {
-    case 4: return bwd_n<4>(a, tw, th, ppl, persist, st);
-    case 8: return bwd_n<8>(a, tw, th, ppl, persist, st);
-    case 16: return bwd_n<16>(a, tw, th, ppl, persist, st);
-    case 32: return bwd_n<32>(a, tw, th, ppl, persist, st);
+    case 4: return bwd_n<4>(a, tw, th, nb, persist, st);
+    case 8: return bwd_n<8>(a, tw, th, nb, persist, st);
+    case 16: return bwd_n<16>(a, tw, th, nb, persist, st);
+    case 32: return bwd_n<32>(a, tw, th, nb, persist, st);
   }
   return hipErrorInvalidValue;
 }

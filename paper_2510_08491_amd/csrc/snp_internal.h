@@ -20,6 +20,32 @@ constexpr int kMaxCamsPerChunk = 16;   // cameras passed by value per launch
 constexpr int kXiDim = 8;
 constexpr int kCmlpIn = 3 + kXiDim;
 constexpr int kShCoeffs = 48;     // spherical harmonics of degree 3: 16 basis functions x RGB
+constexpr int kRayIn = 9;         // per-ray relighting colour: entry point, ray direction, light direction
+
+// Per-ray relighting colour (colour mode 4), width W, D hidden layers.  The
+// network's parameters per primitive (cmlp): W1 (W x 9) over [entry point
+// (x - x_B)/m, ray direction d, light direction], b1, [Wh (W x W), bh],
+// Wo (3 x W), bo.  The rasterizer evaluates it from a per-primitive table in
+// the ellipsoid's unit-sphere frame (u = S^-1 R^T (x - x_B), d' the ray
+// direction in that frame, L the length of the un-normalised camera ray):
+//   W1[:, 0:3] (x - x_B)/m = Au u,   Au = W1[:, 0:3] R S / m
+//   W1[:, 3:6] d           = Ad d' / L,   Ad = W1[:, 3:6] R S
+// and a per-(view, primitive) bias cb = b1 + W1[:, 6:9] normalize(l_v - x_B).
+// Table row: Au (k*3 + j), Ad, [Wh, bh], Wo, bo, padded to a multiple of 4.
+template <int W, int D>
+struct RayColourLayout {
+  static constexpr int AU = 0;
+  static constexpr int AD = 3 * W;
+  static constexpr int WH = 6 * W;
+  static constexpr int BH = WH + W * W;
+  static constexpr int WO = D == 2 ? BH + W : 6 * W;
+  static constexpr int BO = WO + 3 * W;
+  static constexpr int CT = BO + 3;
+  static constexpr int CTS = (CT + 3) / 4 * 4;  // row stride
+};
+inline __host__ __device__ int ray_colour_stride(int W, int D) {
+  return ((6 * W + (D == 2 ? W * W + W : 0) + 3 * W + 3) + 3) / 4 * 4;
+}
 
 // Per-view constants on the device.
 struct CamDev {
@@ -179,7 +205,24 @@ struct PreBwdArgs {
   const uint32_t* tile_counts;
   const float* gview;
   const float* gtable;
+  const float* extra_rs;  // per primitive 12 floats: further d loss / d R (9) and d loss / d s (3), or null
   snp_grads g;
+};
+
+// per-ray relighting colour (colour mode 4): the preprocess side
+struct RayColourArgs {
+  int64_t P;
+  int32_t V, W, D;
+  const float *centers, *scales, *quats, *cmlp;
+  const CamDev* cams;
+  const uint32_t* tile_counts;
+  float* ctab;          // P x stride: the network in the unit-sphere frame
+  float* cbias;         // V P x W: first-layer bias with the light term
+  const float* gctab;   // backward: gradient of ctab
+  const float* gcbias;  // backward: gradient of cbias
+  float* g_cmlp;
+  float* g_centers;
+  float* extra_rs;      // backward: per primitive d loss / d R (9), d loss / d s (3) for the preprocess adjoint
 };
 
 struct EmitArgs {
@@ -217,6 +260,10 @@ struct RasterArgs {
   int64_t cache_instances;  // leading instances covered by ahat_cache
   float* ahat_cache;        // per (instance, tile pixel) integral: the forward writes it,
                             // the backward reads it (null: the backward re-evaluates)
+  const float* ctab;        // colour mode 4: per-primitive colour network table
+  const float* cbias;       // colour mode 4: per-(view, primitive) first-layer bias
+  float* gctab;             // colour mode 4 backward: gradients of ctab, cbias
+  float* gcbias;
   unsigned long long* counters;
   uint32_t* tile_pairs;     // forward with pair counting: hit pairs per global tile
   float t_eps, alpha_min, alpha_max;
@@ -236,6 +283,11 @@ hipError_t launch_sh_bwd(const ShArgs& a, hipStream_t st);
 bool cmlp_supported(int width, int depth);
 int cmlp_param_count(int width, int depth, bool relight);
 hipError_t launch_preprocess_bwd(const PreBwdArgs& a, hipStream_t st);
+// relight.hip
+bool ray_colour_supported(int width, int depth);
+int ray_colour_param_count(int width, int depth);
+hipError_t launch_ray_colour_fwd(const RayColourArgs& a, hipStream_t st);
+hipError_t launch_ray_colour_bwd(const RayColourArgs& a, hipStream_t st);
 // binning.hip
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 size_t scan_scratch_bytes(int64_t n);
@@ -258,10 +310,13 @@ hipError_t launch_tile_keys(const uint32_t* ranges, int64_t n_tiles, unsigned lo
 int supported_tiles(int32_t* triples, int32_t max);
 bool tile_supported(int tw, int th, int ppl);
 bool bwd_batch_supported(int tw, int th, int nb);
+bool ray_colour_raster_supported(int N, int tw, int th, int ppl, int nb);
 int bwd_batch_default(int tw, int th);
-hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
+// cd: 0, or the depth of the per-ray colour network (colour mode 4, width 16)
+hipError_t launch_render_fwd(int N, int tw, int th, int ppl, bool persist, bool count, int cd, const RasterArgs& a,
                              hipStream_t st);
-hipError_t launch_render_bwd(int N, int tw, int th, int nb, bool persist, const RasterArgs& a, hipStream_t st);
+hipError_t launch_render_bwd(int N, int tw, int th, int nb, bool persist, int cd, const RasterArgs& a,
+                             hipStream_t st);
 hipError_t launch_render_fwd_gauss(int tw, int th, int ppl, bool persist, bool count, const RasterArgs& a,
                                    hipStream_t st);
 hipError_t launch_wave_sum_selftest(const float* in, float* out, int waves, hipStream_t st);

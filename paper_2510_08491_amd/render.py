@@ -62,12 +62,14 @@ class RenderConfig:
         return c
 
 
-def cmlp_param_count(width: int, depth: int, relight: bool = False) -> int:
+def cmlp_param_count(width: int, depth: int, relight: bool = False, per_ray: bool = False) -> int:
     """Colour-network parameters per primitive: inputs view direction and
-    xi (11), plus the light direction (14) for the relighting colour."""
+    xi (11), plus the light direction (14) for the relighting colour, or the
+    entry point, ray direction and light direction (9) for the per-ray
+    relighting colour."""
     if depth <= 0:
         return 0
-    n_in = 14 if relight else 11
+    n_in = 9 if per_ray else (14 if relight else 11)
     return n_in * width + width + (depth - 1) * (width * width + width) + 3 * width + 3
 
 

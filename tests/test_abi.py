@@ -68,7 +68,7 @@ def test_layout_and_validation():
     assert lib.snp_workspace_layout(C.byref(_cfg(n_hidden=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
     assert lib.snp_workspace_layout(C.byref(_cfg(tile_w=12)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
     assert lib.snp_workspace_layout(C.byref(_cfg(alpha_max=1.0)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
-    assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=4)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
+    assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=5)), 10, 2, cams, 100, C.byref(lay)) == L.SNP_ERR_INVALID
     # the relighting colour needs a supported colour-network shape
     assert lib.snp_workspace_layout(C.byref(_cfg(color_mode=3)), 10, 2, cams, 100,
                                     C.byref(lay)) == L.SNP_ERR_UNSUPPORTED
@@ -212,3 +212,27 @@ def test_tuning_cache_lookup():
     assert tuning.lookup(8, 0, S.make_cameras([(64, 64)], seed=1)) is None
     shapes = tuning.supported_shapes()
     assert (16, 16, 1) in shapes and (8, 8, 1) in shapes and len(shapes) == 6
+
+
+def test_per_ray_colour_configurations():
+    """Colour mode 4 is built for N = 8 and 16, width 16 with one hidden
+    layer, 16 x 16 tiles with one pixel per thread and backward batches of
+    8; other configurations are refused before anything is enqueued, and its
+    layout holds the network table, the biases and their gradients."""
+    L = _lib()
+    lib = L.lib()
+    from paper_2510_08491_amd.render import camera_array
+    cams = camera_array(S.make_cameras([(64, 64)], seed=3, lights=True))
+    ok = dict(n_hidden=16, color_mode=4, cmlp_width=16, cmlp_depth=1)
+    lay, lay0 = L.SnpLayout(), L.SnpLayout()
+    assert lib.snp_workspace_layout(C.byref(_cfg(**ok)), 1000, 1, cams, 5000, C.byref(lay)) == L.SNP_OK
+    assert lib.snp_workspace_layout(C.byref(_cfg(**{**ok, "color_mode": 0})), 1000, 1, cams, 5000,
+                                    C.byref(lay0)) == L.SNP_OK
+    # table (148 floats), bias (16), their gradients and 12 floats per primitive
+    assert lay.bytes - lay0.bytes >= 4 * 1000 * (2 * 148 + 2 * 16 + 12)
+    for bad in (dict(cmlp_depth=2), dict(cmlp_width=32), dict(n_hidden=4), dict(n_hidden=32), dict(tile_w=8, tile_h=8),
+                dict(px_per_lane=2), dict(bwd_batch=4), dict(primitive=1)):
+        c = _cfg(**{**ok, **bad})
+        assert lib.snp_workspace_layout(C.byref(c), 1000, 1, cams, 5000, C.byref(lay)) == L.SNP_ERR_UNSUPPORTED, bad
+    assert lib.snp_workspace_layout(C.byref(_cfg(**{**ok, "bwd_batch": 8})), 1000, 1, cams, 5000,
+                                    C.byref(lay)) == L.SNP_OK
