@@ -33,7 +33,7 @@ PEAK_SLOTS = 256 * 128 * 2.4e9   # FP32 VALU lane-op issue slots/s (= 157.3 TFLO
 TRANS_WEIGHT = 4.0               # issue slots per transcendental (quarter rate)
 
 
-def ops_per_pair(N):
+def ops_per_pair(N, ray_colour_width=0):
     """Algorithmic work of the rasterizer per pair, in VALU lane-ops and
     transcendentals, counted from the formulation (ray frame and
     discriminant, chord, per hidden unit the phase, half-width, cos, sin,
@@ -47,6 +47,21 @@ def ops_per_pair(N):
     # alpha (exp2) and the blending and d loss / d integral (40 ops + 1/H)
     bwd_hit_cached_v, bwd_hit_cached_t = 66, 4
     bwd_live_v, bwd_live_t = 32 * N + 60, 6 * N + 1
+    if ray_colour_width:
+        # the per-ray colour network (one hidden layer of W units) per pair:
+        # entry point and direction (6 ops + 1/L), first layer (6 FMA + ReLU
+        # per unit), output layer (3 W FMA), sigmoid (2 ops + exp2 + rcp per
+        # channel), c_dc (3); in the backward's pixel phase again, and per
+        # listed pair the recomputation plus its adjoint: sigmoid derivative
+        # (4 per channel), output weights (3 W), hidden gradient (3 FMA +
+        # select per unit), first-layer weights (6 W) and the entry point
+        # and direction gradients (6 W FMA), 9 more in the geometry chain
+        W = ray_colour_width
+        col = (10 * W + 15, 7)
+        fwd_v, fwd_t = fwd_v + col[0], fwd_t + col[1]
+        bwd_hit_v, bwd_hit_t = bwd_hit_v + col[0], bwd_hit_t + col[1]
+        bwd_hit_cached_v, bwd_hit_cached_t = bwd_hit_cached_v + col[0], bwd_hit_cached_t + col[1]
+        bwd_live_v, bwd_live_t = bwd_live_v + col[0] + 21 + 19 * W, bwd_live_t + col[1]
     return dict(fwd=(fwd_v, fwd_t), bwd_hit=(bwd_hit_v, bwd_hit_t), bwd_hit_cached=(bwd_hit_cached_v, bwd_hit_cached_t),
                 bwd_live=(bwd_live_v, bwd_live_t))
 
@@ -64,8 +79,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "A"],
-                    help="C3/C4/C5: fwd+bwd step; A: forward-only frames/s of the 100k-primitive throughput workload")
+    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "R", "A"],
+                    help="C3/C4/C5: fwd+bwd step; R: the C4 step with the per-ray relighting colour; "
+                         "A: forward-only frames/s of the 100k-primitive throughput workload")
     ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,bwd_batch] (default: tuned)")
     ap.add_argument("--fwd-cache", type=int, default=None, choices=[0, 1],
                     help="1: the forward keeps every pair's integral for the backward; 0: the backward "
@@ -210,7 +226,7 @@ def main(argv=None):
         log(f"[bench] per-view plain launches: {per_view_ms:.3f} ms/step, images identical: {per_view_equal}")
 
     # ---- roofline of the dominant kernel ----------------------------------------------------
-    ops = ops_per_pair(N)
+    ops = ops_per_pair(N, scene["cmlp_width"] if scene["color_mode"] == 4 else 0)
 
     def bwd_slots_of(cached_fraction):
         hit = hit_pairs * (cached_fraction * slots(ops["bwd_hit_cached"]) + (1 - cached_fraction) * slots(ops["bwd_hit"]))
@@ -592,7 +608,9 @@ def workload_name(w, cams):
     desc = " + ".join(f"{n}x{k}" for k, n in sizes.items())
     return {"C3": "1 camera 1920x1080, 200k primitives, N=16, colour MLP W32 D2, fwd+bwd",
             "C4": f"16 mixed cameras ({desc}), 200k primitives, N=16, colour MLP W32 D2, batched fwd+bwd",
-            "C5": "32 cameras 1600x900, 1M primitives, N=32, colour MLP W32 D3, batched fwd+bwd"}[w]
+            "C5": "32 cameras 1600x900, 1M primitives, N=32, colour MLP W32 D3, batched fwd+bwd",
+            "R": f"16 mixed cameras ({desc}), 200k primitives, N=16, per-ray relighting colour network W16 D1 "
+                 "with a point light per view, batched fwd+bwd"}[w]
 
 
 def _oracle_crop(job):

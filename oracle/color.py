@@ -37,7 +37,16 @@ the complex harmonics, which cancels the Condon-Shortley phase),
     colour_c = max(0, 1/2 + sum_k Y_k(d) sh[k, c])
 
 (the offset of one half and the clamp at zero are the 3DGS convention the
-paper says it follows).  Colour MLP:
+paper says it follows).  In the dynamic-scene application the zero-order
+coefficient is a function of the time xi_t in [0, 1]: S0 plus a polynomial
+and a Fourier series, n = l = 4,
+
+    sh[0, c](xi_t) = S0_c + sum_{i=1..4} a_ic xi_t^i
+                          + sum_{i=1..4} (b_ic cos(i xi_t) + c_ic sin(i xi_t))
+
+(reading: the sums start at i = 1, a constant term would repeat S0;
+frequencies i in radians, as printed), with the coefficients stored per
+primitive as sh_t[12][3]: a_1..a_4, b_1..b_4, c_1..c_4.  Colour MLP:
 
     input  = [normalize(x_B - o_v) (3), xi_p (8)]
     hidden = ReLU(W h + b), `depth` layers of `width` units
@@ -105,6 +114,20 @@ def sh_basis(d):
     ], axis=-1)
 
 
+def time_basis(time):
+    """The 12 functions of xi_t the time-dependent zero-order coefficient
+    combines: xi^1..xi^4, cos(i xi), sin(i xi) for i = 1..4."""
+    t = float(time)
+    return np.array([t ** i for i in range(1, 5)] + [np.cos(i * t) for i in range(1, 5)] +
+                    [np.sin(i * t) for i in range(1, 5)])
+
+
+def time_sh0(sh_t, time):
+    """P_n(xi_t) + F_l(xi_t) per primitive and channel (P, 3) from the
+    coefficients sh_t (P, 12, 3)."""
+    return np.einsum("k,pkc->pc", time_basis(time), np.asarray(sh_t, dtype=np.float64))
+
+
 def view_directions(scene, cam):
     """normalize(x_B - o_v) for every primitive, (P, 3)."""
     o = camera_center(cam)
@@ -119,7 +142,9 @@ def primitive_colors(scene, cam):
     dirv = view_directions(scene, cam)
     if scene["color_mode"] == 2:
         Y = sh_basis(dirv)                                        # (P, 16)
-        sh = np.asarray(scene["sh"], dtype=np.float64)            # (P, 16, 3)
+        sh = np.array(scene["sh"], dtype=np.float64)              # (P, 16, 3)
+        if scene.get("sh_t") is not None:
+            sh[:, 0, :] += time_sh0(scene["sh_t"], scene.get("time", 0.0))
         return np.maximum(0.0, 0.5 + np.einsum("pk,pkc->pc", Y, sh))
     parts = [dirv]
     if scene["color_mode"] == 3:

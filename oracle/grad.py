@@ -25,7 +25,7 @@ import torch
 from .keys import project_all
 from .render import RenderOptions, depth_order, l1_loss, render_views
 
-PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "wt")
+PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "wt", "sh_t")
 
 
 def _rotmat_t(q):
@@ -61,7 +61,15 @@ def _colors_t(params, meta, o, cam=None):
     dirv = params["centers"] - o
     dirv = dirv / torch.linalg.norm(dirv, dim=1, keepdim=True)
     if meta["color_mode"] == 2:
-        return torch.relu(0.5 + torch.einsum("pk,pkc->pc", _sh_basis_t(dirv), params["sh"]))
+        sh = params["sh"]
+        if params.get("sh_t") is not None:
+            # time-dependent zero-order coefficient: polynomial and Fourier terms
+            t = float(meta.get("time", 0.0))
+            basis = torch.tensor([t, t * t, t ** 3, t ** 4] + [float(np.cos(i * t)) for i in (1, 2, 3, 4)] +
+                                 [float(np.sin(i * t)) for i in (1, 2, 3, 4)], dtype=torch.float64)
+            s0 = sh[:, 0, :] + torch.einsum("k,pkc->pc", basis, params["sh_t"])
+            sh = torch.cat([s0[:, None, :], sh[:, 1:, :]], 1)
+        return torch.relu(0.5 + torch.einsum("pk,pkc->pc", _sh_basis_t(dirv), sh))
     parts = [dirv]
     if meta["color_mode"] == 3:
         ld = torch.tensor(np.asarray(cam.light, dtype=np.float32).astype(np.float64)) - params["centers"]

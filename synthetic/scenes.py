@@ -93,6 +93,12 @@ CONFIGS = {
                       1, 32, 2),
     "C5": SceneConfig("C5", 1_000_000, 32, [(1600, 900)] * 32, 1, 32, 3,
                       center_dist="normal06", scale_lo=0.005, scale_hi=0.1),
+    # the 16-view step with the per-ray relighting colour (colour mode 4: one
+    # hidden layer of 16 units, a point light per view) instead of the
+    # per-(primitive, view) colour network
+    "R": SceneConfig("R", 200_000, 16,
+                     [(640, 480)] * 4 + [(1280, 720)] * 8 + [(1920, 1080)] * 4,
+                     4, 16, 1),
     # stand-in for the paper's throughput protocol (App. A): 100k random
     # primitives in a volume, N = 8, omega0 = 30, degree-3 SH colour, square
     # 800x800 views around the volume; forward only
@@ -201,19 +207,23 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
     opacity = rng.uniform(0.2, 0.9, P)
     # temporal weights (time-conditioned density), drawn after everything else
     wt = rng.uniform(-np.pi, np.pi, (P, N)) if cfg.temporal else None
+    # with spherical harmonics, the time-dependent zero-order coefficient's
+    # polynomial and Fourier coefficients a_1..4, b_1..4, c_1..4 per channel
+    sh_t = rng.uniform(-0.3, 0.3, (P, 12, 3)) if cfg.temporal and cfg.color_mode == 2 else None
     f32 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
     return dict(P=P, N=N, omega0=cfg.omega0, color_mode=cfg.color_mode, primitive=cfg.primitive,
                 opacity=f32(opacity), wt=f32(wt), time=0.0,
                 cmlp_width=cfg.cmlp_width, cmlp_depth=cfg.cmlp_depth,
                 centers=f32(centers), scales=f32(scales), quats=f32(quats),
                 w1=f32(w1), b1=f32(b1), w2=f32(w2), b2=f32(b2),
-                colors=f32(colors), cmlp=f32(cmlp), xi=f32(xi), sh=f32(sh))
+                colors=f32(colors), cmlp=f32(cmlp), xi=f32(xi), sh=f32(sh), sh_t=f32(sh_t))
 
 
 def subset_scene(scene: dict, idx) -> dict:
     """Primitives `idx` of a scene (e.g. the first 1000)."""
     out = dict(scene)
-    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity", "wt"):
+    for k in ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity", "wt",
+              "sh_t"):
         if scene.get(k) is not None:
             out[k] = np.ascontiguousarray(scene[k][idx])
     out["P"] = int(out["centers"].shape[0])
@@ -231,7 +241,7 @@ def make_workload(name: str, n_prims: Optional[int] = None, sizes=None):
     fewer primitives or other camera sizes, for tests)."""
     cfg = CONFIGS[name]
     scene = make_scene(cfg, n_prims=n_prims)
-    cams = make_cameras(cfg.cams if sizes is None else sizes)
+    cams = make_cameras(cfg.cams if sizes is None else sizes, lights=cfg.color_mode in (3, 4))
     return cfg, scene, cams, make_targets(cams)
 
 
