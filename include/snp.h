@@ -144,10 +144,13 @@ typedef struct {
  *             the instances, a few more launches); 2 = instances emitted in
  *             primitive order and sorted by the whole key; 0 = 1 when
  *             V * P >= 2^16, else 2.
- *  time       xi_t in [0, 1] of the time-conditioned density (the dynamic-
- *             scene application): with prims.wt the phase of hidden unit k
- *             is omega0 (W1_k x + b1_k) + time * wt_k (the time term added
- *             unscaled, as the paper prints it); ignored without wt. */
+ *  time       xi_t in [0, 1] of the dynamic-scene application: with
+ *             prims.wt the phase of hidden unit k is omega0 (W1_k x + b1_k) +
+ *             time * wt_k (the time term added unscaled, as the paper prints
+ *             it); with prims.sh_t (color_mode 2) the zero-order SH
+ *             coefficient is sh[p][0][c] + sum_{i=1..4} (a_i xi^i +
+ *             b_i cos(i xi) + c_i sin(i xi)) (polynomial and Fourier series
+ *             of degree 4); ignored without either. */
 typedef struct {
   int32_t n_hidden;
   float omega0;
@@ -174,6 +177,9 @@ typedef struct {
   const float *sh;     /* color_mode 2: P x 16 x 3 (basis (l, m) in order (0,0), (1,-1), (1,0), (1,1), (2,-2) ... (3,3); channel), else NULL */
   const float *opacity; /* primitive 1: P opacities in (0, 1], used as given; else NULL */
   const float *wt;      /* P x N temporal weights of the time-conditioned density, or NULL */
+  const float *sh_t;    /* color_mode 2 in the dynamic-scene application: P x 12 x 3 coefficients of the
+                           time-dependent zero-order SH term (a_1..a_4 of xi_t^i, b_1..b_4 of cos(i xi_t),
+                           c_1..c_4 of sin(i xi_t); channel), added to sh[p][0][c]; or NULL */
 } snp_prims;
 
 /* Gradient outputs, same shapes as the parameters.  The backward ADDS into
@@ -181,7 +187,8 @@ typedef struct {
  * are only produced when non-NULL). */
 typedef struct {
   float *centers, *scales, *quats, *w1, *b1, *w2, *b2, *colors, *cmlp, *xi, *sh;
-  float *wt; /* P x N, with prims.wt */
+  float *wt;   /* P x N, with prims.wt */
+  float *sh_t; /* P x 12 x 3, with prims.sh_t */
 } snp_grads;
 
 /* Byte offsets of the internal arrays inside a workspace (for inspection by

@@ -31,12 +31,12 @@ class SnpConfig(C.Structure):
 class SnpPrims(C.Structure):
     _fields_ = [("P", C.c_int64)] + [(k, C.c_void_p) for k in
                                      ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi",
-                                      "sh", "opacity", "wt")]
+                                      "sh", "opacity", "wt", "sh_t")]
 
 
 class SnpGrads(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in
-                ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "wt")]
+                ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "wt", "sh_t")]
 
 
 class SnpLayout(C.Structure):

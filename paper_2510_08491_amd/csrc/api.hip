@@ -202,6 +202,18 @@ static T* wsp(void* ws, size_t off) {
   return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
 }
 
+// the time-dependent zero-order SH term: the coefficient array and the 12
+// functions of xi_t (xi^1..4, cos(i xi), sin(i xi)) it multiplies
+static void sh_time(const snp_config* cfg, const snp_prims* pr, ShArgs* sa) {
+  sa->sh_t = pr->sh_t;
+  const double t = cfg->time;
+  for (int i = 1; i <= 4; ++i) {
+    sa->tb[i - 1] = (float)std::pow(t, i);
+    sa->tb[3 + i] = (float)std::cos(i * t);
+    sa->tb[7 + i] = (float)std::sin(i * t);
+  }
+}
+
 static RayColourArgs ray_colour_args(const snp_config* cfg, const snp_prims* pr, int32_t V, const Plan& pl,
                                      void* ws) {
   RayColourArgs ra;
@@ -287,6 +299,7 @@ static snp_status do_preprocess(const snp_config* cfg, const snp_prims* pr, int3
     sa.V = V;
     sa.centers = pr->centers;
     sa.sh = pr->sh;
+    sh_time(cfg, pr, &sa);
     sa.cams = cd;
     sa.tile_counts = va.tile_counts;
     sa.records = va.records;
@@ -501,7 +514,7 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
     // also without g->cmlp: the view-direction gradient feeds the centres
     if (g->cmlp || g->xi || g->centers) SNP_HIP(launch_cmlp_bwd(cfg->cmlp_width, cfg->cmlp_depth, ca, st));
   }
-  if (cfg->color_mode == 2 && (g->sh || g->centers)) {
+  if (cfg->color_mode == 2 && (g->sh || g->centers || g->sh_t)) {
     // also without g->sh: the view-direction gradient feeds the centres
     ShArgs sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -509,6 +522,8 @@ static snp_status do_backward(const snp_config* cfg, const snp_prims* pr, int32_
     sa.V = V;
     sa.centers = pr->centers;
     sa.sh = pr->sh;
+    sh_time(cfg, pr, &sa);
+    sa.g_sh_t = g->sh_t;
     sa.cams = a.cams;
     sa.tile_counts = wsp<uint32_t>(ws, L.tile_counts);
     sa.records = wsp<float>(ws, L.records);
@@ -556,6 +571,7 @@ static snp_status zero_grads(const snp_config* cfg, int64_t P, const snp_grads* 
     SNP_HIP(zero_f32(g->xi, (int64_t)kXiDim * P, st));
   }
   if (cfg->color_mode == 2) SNP_HIP(zero_f32(g->sh, (int64_t)kShCoeffs * P, st));
+  if (cfg->color_mode == 2) SNP_HIP(zero_f32(g->sh_t, (int64_t)kShTime * 3 * P, st));
   SNP_HIP(zero_f32(g->wt, N * P, st));
   return SNP_OK;
 }

@@ -6,7 +6,11 @@
 //
 //     colour_c = max(0, 1/2 + sum_k Y_k(d) sh[k][c])
 //
-// Coefficients are stored per primitive as sh[16][3] (basis, channel).
+// Coefficients are stored per primitive as sh[16][3] (basis, channel).  In
+// the dynamic-scene application the zero-order coefficient is a function of
+// the time xi_t: sh[0][c] + sum_k tb_k sh_t[k][c] with tb = (xi, xi^2, xi^3,
+// xi^4, cos xi, ..., cos 4 xi, sin xi, ..., sin 4 xi) (a polynomial and a
+// Fourier series of degree 4).
 #include "snp_internal.h"
 
 namespace snp {
@@ -71,6 +75,17 @@ __device__ __forceinline__ void view_dir(const ShArgs& a, int v, int64_t p, floa
   z = dz * il;
 }
 
+// the zero-order coefficient of channel ch (time dependent with sh_t)
+__device__ __forceinline__ float zero_order(const ShArgs& a, int64_t p, const float* c, int ch) {
+  float s0 = c[ch];
+  if (a.sh_t) {
+    const float* t = a.sh_t + p * (kShTime * 3);
+#pragma unroll
+    for (int k = 0; k < kShTime; ++k) s0 = __builtin_fmaf(a.tb[k], t[3 * k + ch], s0);
+  }
+  return s0;
+}
+
 // one thread per (view, primitive): colour into the record
 __global__ void __launch_bounds__(256) sh_fwd_kernel(ShArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -86,7 +101,8 @@ __global__ void __launch_bounds__(256) sh_fwd_kernel(ShArgs a) {
   for (int ch = 0; ch < 3; ++ch) {
     float s = 0.5f;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) s = __builtin_fmaf(Y[k], c[3 * k + ch], s);
+    for (int k = 1; k < 16; ++k) s = __builtin_fmaf(Y[k], c[3 * k + ch], s);
+    s = __builtin_fmaf(Y[0], zero_order(a, p, c, ch), s);
     col[ch] = fmaxf(s, 0.f);
   }
   float* rec = a.records + i * kRecFloats;
@@ -110,6 +126,8 @@ __global__ void __launch_bounds__(128) sh_bwd_kernel(ShArgs a) {
       c[k][ch] = a.sh[p * kShCoeffs + 3 * k + ch];
       g[k][ch] = 0.f;
     }
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) c[0][ch] = zero_order(a, p, a.sh + p * kShCoeffs, ch);
   for (int v = 0; v < a.V; ++v) {
     const int64_t i = (int64_t)v * a.P + p;
     if (a.tile_counts[i] == 0) continue;
@@ -143,6 +161,13 @@ __global__ void __launch_bounds__(128) sh_bwd_kernel(ShArgs a) {
     for (int k = 0; k < 16; ++k)
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) a.g_sh[p * kShCoeffs + 3 * k + ch] += g[k][ch];
+  }
+  // the time coefficients: d S0(xi) / d sh_t[k][c] = tb_k
+  if (a.sh_t && a.g_sh_t) {
+#pragma unroll
+    for (int k = 0; k < kShTime; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) a.g_sh_t[p * (kShTime * 3) + 3 * k + ch] += a.tb[k] * g[0][ch];
   }
 }
 

@@ -184,15 +184,20 @@ struct CmlpArgs {
   float* g_centers;  // relighting: the light direction's chain to the centres
 };
 
+constexpr int kShTime = 12;  // time-dependent zero-order SH: xi^1..4, cos(i xi), sin(i xi), i = 1..4
+
 struct ShArgs {
   int64_t P;
   int32_t V;
   const float *centers, *sh;
+  const float* sh_t;       // P x 12 x 3 time coefficients of the zero-order term, or null
+  float tb[kShTime];       // the 12 functions of xi_t they multiply
   const CamDev* cams;
   const uint32_t* tile_counts;
   float* records;
   float* gview;
   float* g_sh;
+  float* g_sh_t;
 };
 
 struct PreBwdArgs {

@@ -13,7 +13,8 @@ import torch
 
 from . import _lib as L
 
-PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity", "wt")
+PARAM_KEYS = ("centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "cmlp", "xi", "sh", "opacity", "wt",
+              "sh_t")
 XI_DIM = 8
 
 

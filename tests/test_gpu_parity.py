@@ -238,6 +238,22 @@ def test_time_conditioned_density_image_and_gradients(fwd_cache):
     grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "colors", "wt"])
 
 
+@pytest.mark.parametrize("fwd_cache,time", [(1, 0.63), (0, 1.0)])
+def test_dynamic_scene_sh_image_and_gradients(fwd_cache, time):
+    """The dynamic-scene application whole: the time-conditioned density and
+    the degree-3 SH colour whose zero-order coefficient follows the
+    polynomial and Fourier terms of xi_t; image and every gradient, W_t and
+    the time coefficients included, against the oracle."""
+    scene = S.custom_scene(400, 8, color_mode=2, seed=155, temporal=True)
+    scene["time"] = time
+    cams = S.make_cameras([(72, 56), (48, 64)], seed=156)
+    targets = S.make_targets(cams, seed=157)
+    cfg = config_for(scene, tile=(16, 16, 1), persistent=1, fwd_cache=fwd_cache)
+    fw = run_forward(scene, cams, cfg)
+    check_images(fw, scene, cams, cfg)
+    grad_parity(scene, cams, targets, cfg, ["centers", "scales", "quats", "w1", "b1", "w2", "b2", "sh", "wt", "sh_t"])
+
+
 @pytest.mark.parametrize("tile", [(16, 16, 1), (8, 8, 1), (32, 16, 2)])
 def test_both_binning_orders_give_the_oracle_lists(tile):
     """Depth sort of the pairs then a tile-bit sort of the instances, and one
