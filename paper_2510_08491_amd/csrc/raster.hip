@@ -186,6 +186,49 @@ struct RayAct {
 
 template <int CD>
 __device__ __forceinline__ void ray_net(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
+                                        float n1, float n2, RayAct<CD>& r);
+
+// The colour alone (the forward and the backward's pixel phase): with one
+// hidden layer each unit goes straight into the three output sums, so no
+// activation is kept.
+template <int CD>
+__device__ __forceinline__ void ray_colour(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
+                                           float n1, float n2, float* sg) {
+  if constexpr (CD == 1) {
+    using Lt = RayColourLayout<16, 1>;
+    float o0 = ct[Lt::BO + 0], o1 = ct[Lt::BO + 1], o2 = ct[Lt::BO + 2];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      float h = cb[k];
+      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 0], u0, h);
+      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 1], u1, h);
+      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 2], u2, h);
+      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 0], n0, h);
+      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 1], n1, h);
+      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 2], n2, h);
+      h = fmaxf(h, 0.f);
+      o0 = __builtin_fmaf(ct[Lt::WO + k], h, o0);
+      o1 = __builtin_fmaf(ct[Lt::WO + 16 + k], h, o1);
+      o2 = __builtin_fmaf(ct[Lt::WO + 32 + k], h, o2);
+      // keep each unit's weight reads and arithmetic together (the reads are
+      // broadcasts; hoisted, the 160 weights would sit in registers)
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    sg[0] = fast_rcp(1.f + exp2_fast(-o0 * kLog2e));
+    sg[1] = fast_rcp(1.f + exp2_fast(-o1 * kLog2e));
+    sg[2] = fast_rcp(1.f + exp2_fast(-o2 * kLog2e));
+  } else {
+    RayAct<CD> r;
+    ray_net<CD>(ct, cb, u0, u1, u2, n0, n1, n2, r);
+    sg[0] = r.sg[0];
+    sg[1] = r.sg[1];
+    sg[2] = r.sg[2];
+  }
+}
+
+template <int CD>
+__device__ __forceinline__ void ray_net(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
                                         float n1, float n2, RayAct<CD>& r) {
   using Lt = RayColourLayout<16, CD>;
 #pragma unroll
@@ -400,23 +443,25 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
         }
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-          // the pair's colour: the record's, or c_dc + the per-ray network at
-          // the entry point u = p' - e' with the direction d' / L
-          float c0 = r2.w, c1 = r3.w, c2 = r4.w;
-          if constexpr (CD > 0) {
-            RayAct<CD> ra;
-            const float iL = fast_rcp(pb.L[q]);
-            ray_net<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
-                        g[q].p0 - g[q].e0, g[q].p1 - g[q].e1, g[q].p2 - g[q].e2, g[q].d0 * iL, g[q].d1 * iL,
-                        g[q].d2 * iL, ra);
-            c0 += ra.sg[0];
-            c1 += ra.sg[1];
-            c2 += ra.sg[2];
-          }
           if (hit[q]) {
             const float al = alpha_of(ahat[q], a.alpha_max);
             if (COUNT) nlive += (ahat[q] > 0.f && al < a.alpha_max) ? 1 : 0;
             if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
+              // the pair's colour: the record's, or c_dc + the per-ray network
+              // at the entry point u = p' - e' with the direction d' / L
+              // (evaluated here, where it is used, so its weight reads and
+              // arithmetic stay in one block)
+              float c0 = r2.w, c1 = r3.w, c2 = r4.w;
+              if constexpr (CD > 0) {
+                float sg[3];
+                const float iL = fast_rcp(pb.L[q]);
+                ray_colour<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
+                               g[q].p0 - g[q].e0, g[q].p1 - g[q].e1, g[q].p2 - g[q].e2, g[q].d0 * iL,
+                               g[q].d1 * iL, g[q].d2 * iL, sg);
+                c0 += sg[0];
+                c1 += sg[1];
+                c2 += sg[2];
+              }
               const float w = al * T[q];
               C0[q] = __builtin_fmaf(c0, w, C0[q]);
               C1[q] = __builtin_fmaf(c1, w, C1[q]);
@@ -935,13 +980,13 @@ render_bwd_kernel(RasterArgs a) {
         // the pair's colour (the per-ray network's, as in the forward)
         float c0 = r2.w, c1 = r3.w, c2 = r4.w;
         if constexpr (CD > 0) {
-          RayAct<CD> ra;
+          float sg[3];
           const float iL = fast_rcp(pb.L[0]);
-          ray_net<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
-                      g.p0 - g.e0, g.p1 - g.e1, g.p2 - g.e2, g.d0 * iL, g.d1 * iL, g.d2 * iL, ra);
-          c0 += ra.sg[0];
-          c1 += ra.sg[1];
-          c2 += ra.sg[2];
+          ray_colour<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
+                         g.p0 - g.e0, g.p1 - g.e1, g.p2 - g.e2, g.d0 * iL, g.d1 * iL, g.d2 * iL, sg);
+          c0 += sg[0];
+          c1 += sg[1];
+          c2 += sg[2];
         }
         float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, wq = 0.f, gH = 0.f, wt = 0.f;
         bool live = false;
