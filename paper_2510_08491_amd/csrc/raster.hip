@@ -184,66 +184,33 @@ struct RayAct {
   float sg[3];
 };
 
-template <int CD>
-__device__ __forceinline__ void ray_net(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
-                                        float n1, float n2, RayAct<CD>& r);
-
-// The colour alone (the forward and the backward's pixel phase): with one
-// hidden layer each unit goes straight into the three output sums, so no
-// activation is kept.
-template <int CD>
-__device__ __forceinline__ void ray_colour(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
-                                           float n1, float n2, float* sg) {
-  if constexpr (CD == 1) {
-    using Lt = RayColourLayout<16, 1>;
-    float o0 = ct[Lt::BO + 0], o1 = ct[Lt::BO + 1], o2 = ct[Lt::BO + 2];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      float h = cb[k];
-      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 0], u0, h);
-      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 1], u1, h);
-      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 2], u2, h);
-      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 0], n0, h);
-      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 1], n1, h);
-      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 2], n2, h);
-      h = fmaxf(h, 0.f);
-      o0 = __builtin_fmaf(ct[Lt::WO + k], h, o0);
-      o1 = __builtin_fmaf(ct[Lt::WO + 16 + k], h, o1);
-      o2 = __builtin_fmaf(ct[Lt::WO + 32 + k], h, o2);
-      // keep each unit's weight reads and arithmetic together (the reads are
-      // broadcasts; hoisted, the 160 weights would sit in registers)
-      asm volatile("" ::: "memory");
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    sg[0] = fast_rcp(1.f + exp2_fast(-o0 * kLog2e));
-    sg[1] = fast_rcp(1.f + exp2_fast(-o1 * kLog2e));
-    sg[2] = fast_rcp(1.f + exp2_fast(-o2 * kLog2e));
-  } else {
-    RayAct<CD> r;
-    ray_net<CD>(ct, cb, u0, u1, u2, n0, n1, n2, r);
-    sg[0] = r.sg[0];
-    sg[1] = r.sg[1];
-    sg[2] = r.sg[2];
-  }
+// 0, as an opaque value computed after x: weight reads indexed with it
+// cannot be issued before x exists, which keeps the compiler from hoisting a
+// whole network's LDS reads ahead of its arithmetic (and holding them in
+// registers).
+__device__ __forceinline__ int zero_after(float x) {
+  int z = 0;
+  asm volatile("" : "+v"(z) : "v"(x));
+  return z;
 }
 
 template <int CD>
 __device__ __forceinline__ void ray_net(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
                                         float n1, float n2, RayAct<CD>& r) {
   using Lt = RayColourLayout<16, CD>;
+  int z = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    float h = cb[k];
-    h = __builtin_fmaf(ct[Lt::AU + 3 * k + 0], u0, h);
-    h = __builtin_fmaf(ct[Lt::AU + 3 * k + 1], u1, h);
-    h = __builtin_fmaf(ct[Lt::AU + 3 * k + 2], u2, h);
-    h = __builtin_fmaf(ct[Lt::AD + 3 * k + 0], n0, h);
-    h = __builtin_fmaf(ct[Lt::AD + 3 * k + 1], n1, h);
-    h = __builtin_fmaf(ct[Lt::AD + 3 * k + 2], n2, h);
+    const float* w = ct + z;
+    float h = cb[z + k];
+    h = __builtin_fmaf(w[Lt::AU + 3 * k + 0], u0, h);
+    h = __builtin_fmaf(w[Lt::AU + 3 * k + 1], u1, h);
+    h = __builtin_fmaf(w[Lt::AU + 3 * k + 2], u2, h);
+    h = __builtin_fmaf(w[Lt::AD + 3 * k + 0], n0, h);
+    h = __builtin_fmaf(w[Lt::AD + 3 * k + 1], n1, h);
+    h = __builtin_fmaf(w[Lt::AD + 3 * k + 2], n2, h);
     r.h1[k] = fmaxf(h, 0.f);
-    // the weights are broadcast LDS reads: without a compiler barrier the
-    // whole network's reads are hoisted and held in registers
-    asm volatile("" ::: "memory");
+    if (k & 1) z = zero_after(h);  // the next two units' reads wait for these
   }
   if constexpr (CD == 2) {
 #pragma unroll
@@ -258,11 +225,50 @@ __device__ __forceinline__ void ray_net(const float* ct, const float* cb, float 
   const float* hl = CD == 2 ? r.h2 : r.h1;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    float o = ct[Lt::BO + c];
+    const float* w = ct + z;
+    float o = w[Lt::BO + c];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) o = __builtin_fmaf(ct[Lt::WO + 16 * c + k], hl[k], o);
+    for (int k = 0; k < 16; ++k) o = __builtin_fmaf(w[Lt::WO + 16 * c + k], hl[k], o);
     r.sg[c] = fast_rcp(1.f + exp2_fast(-o * kLog2e));
-    asm volatile("" ::: "memory");
+    z = zero_after(o);
+  }
+}
+
+// The colour alone (the forward and the backward's pixel phase): with one
+// hidden layer each unit goes straight into the three output sums, so no
+// activation is kept.  The unit loop is unrolled by two only: fully
+// unrolled, the compiler issues all 160 weight reads (LDS broadcasts) ahead
+// of the arithmetic and holds them in registers, which halves the waves a
+// SIMD can keep.
+template <int CD>
+__device__ __forceinline__ void ray_colour(const float* ct, const float* cb, float u0, float u1, float u2, float n0,
+                                           float n1, float n2, float* sg) {
+  if constexpr (CD == 1) {
+    using Lt = RayColourLayout<16, 1>;
+    float o0 = ct[Lt::BO + 0], o1 = ct[Lt::BO + 1], o2 = ct[Lt::BO + 2];
+#pragma unroll 2
+    for (int k = 0; k < 16; ++k) {
+      float h = cb[k];
+      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 0], u0, h);
+      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 1], u1, h);
+      h = __builtin_fmaf(ct[Lt::AU + 3 * k + 2], u2, h);
+      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 0], n0, h);
+      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 1], n1, h);
+      h = __builtin_fmaf(ct[Lt::AD + 3 * k + 2], n2, h);
+      h = fmaxf(h, 0.f);
+      o0 = __builtin_fmaf(ct[Lt::WO + k], h, o0);
+      o1 = __builtin_fmaf(ct[Lt::WO + 16 + k], h, o1);
+      o2 = __builtin_fmaf(ct[Lt::WO + 32 + k], h, o2);
+    }
+    sg[0] = fast_rcp(1.f + exp2_fast(-o0 * kLog2e));
+    sg[1] = fast_rcp(1.f + exp2_fast(-o1 * kLog2e));
+    sg[2] = fast_rcp(1.f + exp2_fast(-o2 * kLog2e));
+  } else {
+    RayAct<CD> r;
+    ray_net<CD>(ct, cb, u0, u1, u2, n0, n1, n2, r);
+    sg[0] = r.sg[0];
+    sg[1] = r.sg[1];
+    sg[2] = r.sg[2];
   }
 }
 
@@ -443,25 +449,23 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
         }
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
+          // the pair's colour: the record's, or c_dc + the per-ray network at
+          // the entry point u = p' - e' with the direction d' / L
+          float c0 = r2.w, c1 = r3.w, c2 = r4.w;
+          if constexpr (CD > 0) {
+            float sg[3];
+            const float iL = fast_rcp(pb.L[q]);
+            ray_colour<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
+                           g[q].p0 - g[q].e0, g[q].p1 - g[q].e1, g[q].p2 - g[q].e2, g[q].d0 * iL, g[q].d1 * iL,
+                           g[q].d2 * iL, sg);
+            c0 += sg[0];
+            c1 += sg[1];
+            c2 += sg[2];
+          }
           if (hit[q]) {
             const float al = alpha_of(ahat[q], a.alpha_max);
             if (COUNT) nlive += (ahat[q] > 0.f && al < a.alpha_max) ? 1 : 0;
             if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
-              // the pair's colour: the record's, or c_dc + the per-ray network
-              // at the entry point u = p' - e' with the direction d' / L
-              // (evaluated here, where it is used, so its weight reads and
-              // arithmetic stay in one block)
-              float c0 = r2.w, c1 = r3.w, c2 = r4.w;
-              if constexpr (CD > 0) {
-                float sg[3];
-                const float iL = fast_rcp(pb.L[q]);
-                ray_colour<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
-                               g[q].p0 - g[q].e0, g[q].p1 - g[q].e1, g[q].p2 - g[q].e2, g[q].d0 * iL,
-                               g[q].d1 * iL, g[q].d2 * iL, sg);
-                c0 += sg[0];
-                c1 += sg[1];
-                c2 += sg[2];
-              }
               const float w = al * T[q];
               C0[q] = __builtin_fmaf(c0, w, C0[q]);
               C1[q] = __builtin_fmaf(c1, w, C1[q]);
@@ -794,11 +798,13 @@ __device__ __forceinline__ void ray_net_adjoint(const float* ct, const float* cb
   }
   // d loss / d pre-activation of the last hidden layer
   float gh[16];
+  int z = zero_after(go[2]);
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const float t = go[0] * ct[Lt::WO + k] + go[1] * ct[Lt::WO + 16 + k] + go[2] * ct[Lt::WO + 32 + k];
+    const float* w = ct + z;
+    const float t = go[0] * w[Lt::WO + k] + go[1] * w[Lt::WO + 16 + k] + go[2] * w[Lt::WO + 32 + k];
     gh[k] = hl[k] > 0.f ? t : 0.f;
-    asm volatile("" ::: "memory");
+    if ((k & 3) == 3) z = zero_after(t);
   }
   if constexpr (CD == 2) {
 #pragma unroll
@@ -835,17 +841,19 @@ __device__ __forceinline__ void ray_net_adjoint(const float* ct, const float* cb
     flush16(gt + Lt::AD + 16 * b, v);
   }
   flush16(gb, gh);
+  z = zero_after(gh[15]);
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
+    const float* w = ct + z;
     float tu = 0.f, tn = 0.f;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      tu = __builtin_fmaf(ct[Lt::AU + 3 * k + j], gh[k], tu);
-      tn = __builtin_fmaf(ct[Lt::AD + 3 * k + j], gh[k], tn);
+      tu = __builtin_fmaf(w[Lt::AU + 3 * k + j], gh[k], tu);
+      tn = __builtin_fmaf(w[Lt::AD + 3 * k + j], gh[k], tn);
     }
     gu[j] = tu;
     gn[j] = tn;
-    asm volatile("" ::: "memory");
+    z = zero_after(tn);
   }
 }
 
@@ -883,7 +891,7 @@ __device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float 
 // record gradient, and the entry point's and direction's gradients into the
 // geometry chain.
 template <int N, int TW, int TH, int NB, bool PERSIST, int CD = 0>
-__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(CD > 0 ? 2 : 5)))
+__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(CD > 0 ? 3 : 5)))
 render_bwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
