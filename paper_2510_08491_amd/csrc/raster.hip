@@ -462,18 +462,19 @@ __global__ void __launch_bounds__(TW * TH / PPL) render_fwd_kernel(RasterArgs a)
             c1 += sg[1];
             c2 += sg[2];
           }
-          if (hit[q]) {
-            const float al = alpha_of(ahat[q], a.alpha_max);
-            if (COUNT) nlive += (ahat[q] > 0.f && al < a.alpha_max) ? 1 : 0;
-            if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
-              const float w = al * T[q];
-              C0[q] = __builtin_fmaf(c0, w, C0[q]);
-              C1[q] = __builtin_fmaf(c1, w, C1[q]);
-              C2[q] = __builtin_fmaf(c2, w, C2[q]);
-              T[q] = T[q] * (1.f - al);
-              if (T[q] < a.t_eps) done[q] = true;
-            }
-          }
+          // without branches: a lane that does not blend this pair (a miss,
+          // a terminated pixel, an alpha_min skip) takes alpha = 0, which
+          // leaves its colour and T exactly as they were
+          const float al0 = alpha_of(ahat[q], a.alpha_max);
+          if (COUNT) nlive += (hit[q] && ahat[q] > 0.f && al0 < a.alpha_max) ? 1 : 0;
+          const bool blend = hit[q] && !(a.alpha_min > 0.f && al0 < a.alpha_min);
+          const float al = blend ? al0 : 0.f;
+          const float w = al * T[q];
+          C0[q] = __builtin_fmaf(c0, w, C0[q]);
+          C1[q] = __builtin_fmaf(c1, w, C1[q]);
+          C2[q] = __builtin_fmaf(c2, w, C2[q]);
+          T[q] = T[q] * (1.f - al);
+          done[q] = done[q] || T[q] < a.t_eps;
         }
       }
       bool mine = true;
@@ -996,32 +997,31 @@ render_bwd_kernel(RasterArgs a) {
           c1 += sg[1];
           c2 += sg[2];
         }
-        float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, wq = 0.f, gH = 0.f, wt = 0.f;
-        bool live = false;
-        if (hit) {
-          const float al = alpha_of(ahat, a.alpha_max);
-          if (!(a.alpha_min > 0.f && al < a.alpha_min)) {
-            wt = al * T;
-            gc0 = G0 * wt;
-            gc1 = G1 * wt;
-            gc2 = G2 * wt;
-            B0 = __builtin_fmaf(-c0, wt, B0);
-            B1 = __builtin_fmaf(-c1, wt, B1);
-            B2 = __builtin_fmaf(-c2, wt, B2);
-            if (CD > 0) live = al > 0.f;  // its colour gradient is G_c alpha T
-            if (ahat > 0.f && al < a.alpha_max) {
-              const float ta = T * (1.f - al);
-              const float G = G0 * (c0 * ta - B0) + G1 * (c1 * ta - B1) + G2 * (c2 * ta - B2);
-              wq = G * 2.f * pb.L[0] * g.H;  // d loss / d Q
-              // d loss / d H (direct) = G 2 L (Q + b2); from the stored integral
-              // alpha-hat = 2 L H (Q + b2) when cached (H > 0 for a hit)
-              gH = cached ? G * ahat * fast_rcp(g.H) : G * 2.f * pb.L[0] * QB;
-              live = live || wq != 0.f || gH != 0.f;
-            }
-            T = T * (1.f - al);
-            if (T < a.t_eps) done = true;
-          }
-        }
+        // Without branches: a lane whose pixel does not blend this pair (a
+        // miss, a terminated pixel, an alpha_min skip) takes alpha = 0, which
+        // leaves T, the behind colour and every sum exactly as they were
+        // (T < t_eps can only hold after the pair that set done).
+        const float al0 = alpha_of(ahat, a.alpha_max);
+        const bool blend = hit && !(a.alpha_min > 0.f && al0 < a.alpha_min);
+        const float al = blend ? al0 : 0.f;
+        const float wt = al * T;
+        const float gc0 = G0 * wt, gc1 = G1 * wt, gc2 = G2 * wt;
+        B0 = __builtin_fmaf(-c0, wt, B0);
+        B1 = __builtin_fmaf(-c1, wt, B1);
+        B2 = __builtin_fmaf(-c2, wt, B2);
+        const float ta = T * (1.f - al);
+        // live: positive, unclamped integral
+        const bool gl = blend && ahat > 0.f && al < a.alpha_max;
+        const float G = G0 * (c0 * ta - B0) + G1 * (c1 * ta - B1) + G2 * (c2 * ta - B2);
+        const float wq = gl ? G * 2.f * pb.L[0] * g.H : 0.f;  // d loss / d Q
+        // d loss / d H (direct) = G 2 L (Q + b2); from the stored integral
+        // alpha-hat = 2 L H (Q + b2) when cached (H > 0 for a hit)
+        const float gH = gl ? (cached ? G * ahat * fast_rcp(g.H) : G * 2.f * pb.L[0] * QB) : 0.f;
+        // with the per-ray colour every blending pair is listed: its colour
+        // gradient is G_c alpha T
+        const bool live = (CD > 0 && al > 0.f) || wq != 0.f || gH != 0.f;
+        T = ta;
+        done = done || T < a.t_eps;
         // colour gradient: one transposed reduction of the three sums (with
         // the per-ray colour, phase 2 sums it)
         if constexpr (CD == 0) {
