@@ -892,7 +892,7 @@ __device__ __forceinline__ float ray_length(const CamDev& cam, float pxc, float 
 // record gradient, and the entry point's and direction's gradients into the
 // geometry chain.
 template <int N, int TW, int TH, int NB, bool PERSIST, int CD = 0>
-__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(CD > 0 ? 3 : 5)))
+__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(CD > 0 ? 4 : 5)))
 render_bwd_kernel(RasterArgs a) {
   constexpr int NT = TW * TH;
   constexpr int NW = NT / 64;
@@ -901,12 +901,14 @@ render_bwd_kernel(RasterArgs a) {
   __shared__ Stage<N, NB> S;
   __shared__ float s_acc[NB][ACC];
   __shared__ uint32_t s_cnt[NB][NW];  // live pairs per (instance, wave)
-  __shared__ uint16_t s_pix[NB][NT];
+  // the pair's pixel within the tile (one byte where it fits; only the
+  // per-ray colour kernels need the LDS it saves)
+  using PixIndex = std::conditional_t<(CD > 0 && NT <= 256), uint8_t, uint16_t>;
+  __shared__ PixIndex s_pix[NB][NT];
   __shared__ float s_wq[NB][NT];
   __shared__ float s_gh[NB][NT];
   __shared__ ColourStage<(CD > 0 ? CD : 1), (CD > 0 ? NB : 1)> CS;
   __shared__ float s_wt[CD > 0 ? NB : 1][CD > 0 ? NT : 1];  // alpha T of each listed pair
-  __shared__ float s_G[CD > 0 ? NT : 1][3];                 // d loss / d colour per pixel
   __shared__ int s_item;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // selector bits and value index of the transposed row reductions
@@ -942,11 +944,6 @@ render_bwd_kernel(RasterArgs a) {
     float B0 = done ? 0.f : a.images_in[3 * pxi + 0];
     float B1 = done ? 0.f : a.images_in[3 * pxi + 1];
     float B2 = done ? 0.f : a.images_in[3 * pxi + 2];
-    if constexpr (CD > 0) {  // read by phase 2 after the first stage's barrier
-      s_G[pb.loc[0]][0] = G0;
-      s_G[pb.loc[0]][1] = G1;
-      s_G[pb.loc[0]][2] = G2;
-    }
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     for (uint32_t b0 = start; b0 < end; b0 += NB) {
       const int nb = (int)min((uint32_t)NB, end - b0);
@@ -1038,7 +1035,7 @@ render_bwd_kernel(RasterArgs a) {
             // slot: the number of live lanes below this one (mbcnt)
             const uint32_t pos =
                 wave * 64 + __builtin_amdgcn_mbcnt_hi((uint32_t)(lm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)lm, 0u));
-            s_pix[j][pos] = (uint16_t)pb.loc[0];
+            s_pix[j][pos] = (PixIndex)pb.loc[0];
             s_wq[j][pos] = wq;
             s_gh[j][pos] = gH;
             if constexpr (CD > 0) s_wt[j][pos] = wt;
@@ -1185,6 +1182,32 @@ render_bwd_kernel(RasterArgs a) {
               if (lane < 8 && !sel3) atomicAdd(acc + 4 * N + g + (idx16 & 3), q4);
             }
           }
+          // The colour network's adjoint (per-ray colour) comes first, while
+          // only p', e' and sqrt(disc) of the geometry are live, so that the
+          // network's registers and the chain's are not live together: its
+          // entry point is u = p' - e', its direction n = d' / L.
+          float gn[3] = {0.f, 0.f, 0.f}, gu[3] = {0.f, 0.f, 0.f}, iLp = 0.f;
+          int zz = 0;  // orders the re-reads of the record after the adjoint
+          if constexpr (CD > 0) {
+            iLp = 1.f / ray_length(cam, pxc, pyc);
+            const float4 q0 = S.rec[j][0], q1 = S.rec[j][1], q2 = S.rec[j][2];
+            const float ddx = pxc - q0.w, ddy = pyc - q1.w;
+            const float n0 = __builtin_fmaf(q2.x, ddy, __builtin_fmaf(q1.x, ddx, q0.x)) * iLp;
+            const float n1 = __builtin_fmaf(q2.y, ddy, __builtin_fmaf(q1.y, ddx, q0.y)) * iLp;
+            const float n2 = __builtin_fmaf(q2.z, ddy, __builtin_fmaf(q1.z, ddx, q0.z)) * iLp;
+            // the pair's pixel in the view (inactive lanes read the tile's
+            // first pixel, which lies in the image, and carry wtp = 0)
+            const int64_t gpx =
+                cam.pix_base + (int64_t)(ty * TH + pix / TW) * cam.width + (tx * TW + pix % TW);
+            const uint32_t pid = __builtin_amdgcn_readfirstlane(S.id[j]);
+            ray_net_adjoint<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
+                                G.p0 - G.e0, G.p1 - G.e1, G.p2 - G.e2, n0, n1, n2, a.dL[3 * gpx + 0] * wtp,
+                                a.dL[3 * gpx + 1] * wtp, a.dL[3 * gpx + 2] * wtp,
+                                a.gctab + (int64_t)pid * RayColourLayout<16, CD>::CTS,
+                                a.gcbias + ((int64_t)v * a.P + pid) * 16, acc + TS + 18, lane, idx16, sel1, sel2,
+                                sel3, sel4, gu, gn);
+            zz = zero_after(gu[0] + gn[0]);
+          }
           // chain p', e', H -> d', m' -> record coefficients.  d' and m' are
           // recomputed from LDS here (the barrier keeps the compiler from
           // reusing the first computation), so only p', e' and sqrt(disc) stay
@@ -1192,8 +1215,8 @@ render_bwd_kernel(RasterArgs a) {
           // and d loss / d hv divided by -2 pi.
           asm volatile("" ::: "memory");
           {
-            const float4 q0 = S.rec[j][0], q1 = S.rec[j][1], q2 = S.rec[j][2];
-            const float4 q3 = S.rec[j][3], q4 = S.rec[j][4], q5 = S.rec[j][5];
+            const float4 q0 = S.rec[j][0 + zz], q1 = S.rec[j][1 + zz], q2 = S.rec[j][2 + zz];
+            const float4 q3 = S.rec[j][3 + zz], q4 = S.rec[j][4 + zz], q5 = S.rec[j][5 + zz];
             pair_dm(q0, q1, q2, q3, q4, q5, pxc, pyc, G);
             G.rA = fast_rcp(G.A);
             G.sq = sq_pair;
@@ -1205,19 +1228,7 @@ render_bwd_kernel(RasterArgs a) {
           ge0 *= -kTwoPi;
           ge1 *= -kTwoPi;
           ge2 *= -kTwoPi;
-          float gn[3] = {0.f, 0.f, 0.f}, iLp = 0.f;
           if constexpr (CD > 0) {
-            // the colour network's adjoint; its entry point u = p' - e' and
-            // direction n = d' / L feed the chain below
-            iLp = 1.f / ray_length(cam, pxc, pyc);
-            const uint32_t pid = __builtin_amdgcn_readfirstlane(S.id[j]);
-            float gu[3];
-            ray_net_adjoint<CD>(reinterpret_cast<const float*>(CS.t[j]), reinterpret_cast<const float*>(CS.b[j]),
-                                G.p0 - G.e0, G.p1 - G.e1, G.p2 - G.e2, G.d0 * iLp, G.d1 * iLp, G.d2 * iLp,
-                                s_G[pix][0] * wtp, s_G[pix][1] * wtp, s_G[pix][2] * wtp,
-                                a.gctab + (int64_t)pid * RayColourLayout<16, CD>::CTS,
-                                a.gcbias + ((int64_t)v * a.P + pid) * 16, acc + TS + 18, lane, idx16, sel1, sel2,
-                                sel3, sel4, gu, gn);
             gp0 += gu[0];
             gp1 += gu[1];
             gp2 += gu[2];
