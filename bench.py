@@ -79,8 +79,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "R", "A"],
+    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "R", "D", "A"],
                     help="C3/C4/C5: fwd+bwd step; R: the C4 step with the per-ray relighting colour; "
+                         "D: the C4 step with the dynamic-scene density and SH colour; "
                          "A: forward-only frames/s of the 100k-primitive throughput workload")
     ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,bwd_batch] (default: tuned)")
     ap.add_argument("--fwd-cache", type=int, default=None, choices=[0, 1],
@@ -132,7 +133,8 @@ def main(argv=None):
         tile = tile + (0,)
     cfg = snp.RenderConfig(n_hidden=N, omega0=scene["omega0"], color_mode=scene["color_mode"], bin_order=a.bin_order,
                            cmlp_width=scene["cmlp_width"], cmlp_depth=scene["cmlp_depth"], tile_w=tile[0],
-                           tile_h=tile[1], px_per_lane=tile[2], bwd_batch=tile[3], persistent=1, fwd_cache=fwd_cache)
+                           tile_h=tile[1], px_per_lane=tile[2], bwd_batch=tile[3], persistent=1, fwd_cache=fwd_cache,
+                           time=float(scene.get("time", 0.0)))
     log(f"[bench] workload {a.workload}: P={scene['P']} V={len(cams)} N={N} tile={tile} fwd_cache={fwd_cache}")
     params = snp.params_to_device(scene)
     tg = torch.from_numpy(np.concatenate([t.ravel() for t in targets])).cuda()
@@ -610,7 +612,9 @@ def workload_name(w, cams):
             "C4": f"16 mixed cameras ({desc}), 200k primitives, N=16, colour MLP W32 D2, batched fwd+bwd",
             "C5": "32 cameras 1600x900, 1M primitives, N=32, colour MLP W32 D3, batched fwd+bwd",
             "R": f"16 mixed cameras ({desc}), 200k primitives, N=16, per-ray relighting colour network W16 D1 "
-                 "with a point light per view, batched fwd+bwd"}[w]
+                 "with a point light per view, batched fwd+bwd",
+            "D": f"16 mixed cameras ({desc}), 200k primitives, N=16, time-conditioned density and degree-3 SH "
+                 "colour with the time-dependent zero-order coefficient at xi_t=0.5, batched fwd+bwd"}[w]
 
 
 def _oracle_crop(job):

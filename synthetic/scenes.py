@@ -82,6 +82,7 @@ class SceneConfig:
     backward: bool = True
     primitive: int = 0              # 0 neural primitive, 1 Gaussian (scales are standard deviations)
     temporal: bool = False          # time-conditioned density: a temporal weight W_t per hidden unit
+    time: float = 0.0               # the scene's time xi_t (with temporal weights)
 
 
 CONFIGS = {
@@ -99,6 +100,13 @@ CONFIGS = {
     "R": SceneConfig("R", 200_000, 16,
                      [(640, 480)] * 4 + [(1280, 720)] * 8 + [(1920, 1080)] * 4,
                      4, 16, 1),
+    # the dynamic-scene application at the 16-view scale: time-conditioned
+    # density (a temporal weight per hidden unit) and degree-3 SH colour
+    # whose zero-order coefficient follows the polynomial and Fourier terms
+    # of the time, at xi_t = 0.5
+    "D": SceneConfig("D", 200_000, 16,
+                     [(640, 480)] * 4 + [(1280, 720)] * 8 + [(1920, 1080)] * 4,
+                     2, temporal=True, time=0.5),
     # stand-in for the paper's throughput protocol (App. A): 100k random
     # primitives in a volume, N = 8, omega0 = 30, degree-3 SH colour, square
     # 800x800 views around the volume; forward only
@@ -212,7 +220,7 @@ def make_scene(cfg: SceneConfig, seed: int = SCENE_SEED, n_prims: Optional[int] 
     sh_t = rng.uniform(-0.3, 0.3, (P, 12, 3)) if cfg.temporal and cfg.color_mode == 2 else None
     f32 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
     return dict(P=P, N=N, omega0=cfg.omega0, color_mode=cfg.color_mode, primitive=cfg.primitive,
-                opacity=f32(opacity), wt=f32(wt), time=0.0,
+                opacity=f32(opacity), wt=f32(wt), time=float(cfg.time),
                 cmlp_width=cfg.cmlp_width, cmlp_depth=cfg.cmlp_depth,
                 centers=f32(centers), scales=f32(scales), quats=f32(quats),
                 w1=f32(w1), b1=f32(b1), w2=f32(w2), b2=f32(b2),
