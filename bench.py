@@ -79,8 +79,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "R", "D", "A"],
+    ap.add_argument("--workload", default="C4", choices=["C3", "C4", "C5", "R", "L", "D", "A"],
                     help="C3/C4/C5: fwd+bwd step; R: the C4 step with the per-ray relighting colour; "
+                         "L: the C4 step with the relighting colour per (primitive, view); "
                          "D: the C4 step with the dynamic-scene density and SH colour; "
                          "A: forward-only frames/s of the 100k-primitive throughput workload")
     ap.add_argument("--tile", default=None, help="tile_w,tile_h,px_per_lane[,bwd_batch] (default: tuned)")
@@ -219,6 +220,8 @@ def main(argv=None):
     # ---- Adam over every parameter (HBM bound; after the step, not in the metric) --
     optimizer = adam_leg(snp, torch, params)
     log(f"[bench] adam: {optimizer}")
+    extras = training_extras_leg(snp, torch, cfg, scene, cams, params, tg, n_norm)
+    log(f"[bench] training extras: {extras}")
 
     # ---- per-view plain launches ---------------------------------------------------------
     per_view_ms = None
@@ -289,6 +292,7 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "optimizer": optimizer,
+        "training_extras": extras,
         "paper_context": "218.87 FPS forward-only full pipeline, 100k random primitives, RTX 4090 (App. A)",
     }
     print(json.dumps(out))
@@ -336,6 +340,60 @@ def adam_leg(snp, torch, params):
     return {"kernel": "adam (all groups, one launch)", "ms": round(adam_ms, 4), "elements": n_elems,
             "bytes": adam_bytes, "GB_per_s": round(adam_bytes / (adam_ms * 1e-3) / 1e9, 1),
             "frac_of_hbm_peak": round(adam_bytes / (adam_ms * 1e-3) / 8e12, 4)}
+
+
+def training_extras_leg(snp, torch, cfg, scene, cams, params, tg, n_norm):
+    """The other training-step kernels on this scene, timed after one
+    gradient step (not in the metric): the scale regulariser, the
+    population-control statistic and one population-control pass (plan on
+    the device, one synchronisation for the new count, rows carried over
+    with their two Adam moments)."""
+    from paper_2510_08491_amd import train as TR
+    r = snp.Rasterizer(snp.RenderConfig(**{**cfg.__dict__, "fwd_cache": 0}), scene["P"], cams)
+    r._alloc(int(r.prepare(params) * 1.1) + 4096)
+    images, T = r.new_images()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dL = torch.empty_like(images)
+    grads = snp.zeros_like_params(params)
+    r.step(params, images, T, tg, n_norm, loss, dL, grads)
+    P = scene["P"]
+    acc = torch.zeros(P, dtype=torch.float32, device="cuda")
+    vis = torch.zeros(P, dtype=torch.float32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reg_ms = timed(lambda: TR.scale_regularizer(r, params["scales"], 0.01, grad_scales=grads["scales"]))
+    acc_ms = timed(lambda: TR.densify_accumulate(r, grads, acc, vis))
+    N = scene["N"]
+    reg_bytes = 36 * P                                    # scales read, scale gradients read and written
+    acc_bytes = (4 * (5 * N + 1) + 4 * len(cams) + 16) * P  # density-MLP gradients, tile counts, statistic
+    keys = [k for k in params if k in TR.PAPER_LRS or k in ("w1", "b1", "w2", "b2")]
+    pp = {k: params[k].clone() for k in keys}
+    state = {f"{m}_{k}": torch.zeros_like(pp[k]) for k in keys for m in ("m", "v")}
+    noise = torch.randn(P, 2, 3, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    new_p, _, action = TR.densify(pp, state, acc, vis, noise)
+    torch.cuda.synchronize()
+    dens_ms = 1e3 * (time.perf_counter() - t0)
+    n_new = int(new_p["centers"].shape[0])
+    del r, images, T, dL, grads, pp, state, new_p, action, acc, vis, noise
+    torch.cuda.empty_cache()
+    return {"scale_regularizer": {"ms": round(reg_ms, 4), "bytes": reg_bytes,
+                                  "GB_per_s": round(reg_bytes / (reg_ms * 1e-3) / 1e9, 1)},
+            "densify_statistic": {"ms": round(acc_ms, 4), "bytes": acc_bytes,
+                                  "GB_per_s": round(acc_bytes / (acc_ms * 1e-3) / 1e9, 1)},
+            "densify_pass": {"ms_wall": round(dens_ms, 3), "primitives_before": P, "primitives_after": n_new,
+                             "note": "plan, one host synchronisation, allocation of the new arrays, row carry-over"}}
 
 
 def per_view_leg(snp, torch, cfg, scene, cams, params, tg, n_norm, img_batched, a):
@@ -613,6 +671,8 @@ def workload_name(w, cams):
             "C5": "32 cameras 1600x900, 1M primitives, N=32, colour MLP W32 D3, batched fwd+bwd",
             "R": f"16 mixed cameras ({desc}), 200k primitives, N=16, per-ray relighting colour network W16 D1 "
                  "with a point light per view, batched fwd+bwd",
+            "L": f"16 mixed cameras ({desc}), 200k primitives, N=16, relighting colour network W32 D2 per "
+                 "(primitive, view) with a point light per view, batched fwd+bwd",
             "D": f"16 mixed cameras ({desc}), 200k primitives, N=16, time-conditioned density and degree-3 SH "
                  "colour with the time-dependent zero-order coefficient at xi_t=0.5, batched fwd+bwd"}[w]
 

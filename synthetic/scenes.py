@@ -100,6 +100,12 @@ CONFIGS = {
     "R": SceneConfig("R", 200_000, 16,
                      [(640, 480)] * 4 + [(1280, 720)] * 8 + [(1920, 1080)] * 4,
                      4, 16, 1),
+    # the 16-view step with the relighting colour evaluated once per
+    # (primitive, view) (colour mode 3: c_dc + colour network of the view
+    # direction, the light direction and xi, W32 D2, a point light per view)
+    "L": SceneConfig("L", 200_000, 16,
+                     [(640, 480)] * 4 + [(1280, 720)] * 8 + [(1920, 1080)] * 4,
+                     3, 32, 2),
     # the dynamic-scene application at the 16-view scale: time-conditioned
     # density (a temporal weight per hidden unit) and degree-3 SH colour
     # whose zero-order coefficient follows the polynomial and Fourier terms
