@@ -146,34 +146,48 @@ hipError_t launch_scale_reg(int64_t P, const float* scales, float weight, float*
 // population control
 // ---------------------------------------------------------------------------
 // acc += ||d loss / d (W1, b1, W2, b2)||_2, count += 1 if the primitive covers
-// a tile of any view (tile counts of the last preprocess, V x P)
+// a tile of any view (tile counts of the last preprocess, V x P).  Sixteen
+// lanes (one row of the wave) per primitive, so that a row reads each of
+// the primitive's gradient arrays in 64-byte runs; the row then sums its
+// squares and ORs its visibility.
 __global__ void __launch_bounds__(256) densify_acc_kernel(int64_t P, int N, int V, const float* __restrict__ gw1,
                                                           const float* __restrict__ gb1, const float* __restrict__ gw2,
                                                           const float* __restrict__ gb2,
                                                           const uint32_t* __restrict__ tile_counts,
                                                           float* __restrict__ acc, float* __restrict__ cnt) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= P) return;
+  const int64_t p = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int l = threadIdx.x & 15;
   float ss = 0.f;
-  for (int k = 0; k < 3 * N; ++k) {
-    const float x = gw1[p * 3 * N + k];
-    ss += x * x;
-  }
-  for (int k = 0; k < N; ++k) {
-    const float x = gb1[p * N + k], y = gw2[p * N + k];
-    ss += x * x + y * y;
-  }
-  ss += gb2[p] * gb2[p];
   bool vis = false;
-  for (int v = 0; v < V && !vis; ++v) vis = tile_counts[(int64_t)v * P + p] > 0;
-  acc[p] += sqrtf(ss);
-  if (vis) cnt[p] += 1.f;
+  if (p < P) {
+    for (int k = l; k < 3 * N; k += 16) {
+      const float x = gw1[p * 3 * N + k];
+      ss += x * x;
+    }
+    for (int k = l; k < N; k += 16) {
+      const float x = gb1[p * N + k], y = gw2[p * N + k];
+      ss += x * x + y * y;
+    }
+    if (l == 0) ss += gb2[p] * gb2[p];
+    for (int v = l; v < V; v += 16) vis = vis || tile_counts[(int64_t)v * P + p] > 0;
+  }
+  // the row's sum (partners within the row of 16 lanes)
+  ss += __shfl_xor(ss, 1);
+  ss += __shfl_xor(ss, 2);
+  ss += __shfl_xor(ss, 4);
+  ss += __shfl_xor(ss, 8);
+  const unsigned long long vm = __ballot(vis);
+  const int row = (threadIdx.x & 63) >> 4;
+  if (l == 0 && p < P) {
+    acc[p] += sqrtf(ss);
+    if ((vm >> (16 * row)) & 0xFFFFull) cnt[p] += 1.f;
+  }
 }
 
 hipError_t launch_densify_acc(int64_t P, int N, int V, const snp_grads& g, const uint32_t* tile_counts, float* acc,
                               float* cnt, hipStream_t st) {
-  hipLaunchKernelGGL(densify_acc_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, N, V, g.w1, g.b1,
-                     g.w2, g.b2, tile_counts, acc, cnt);
+  hipLaunchKernelGGL(densify_acc_kernel, dim3((unsigned)((P * 16 + 255) / 256)), dim3(256), 0, st, P, N, V, g.w1,
+                     g.b1, g.w2, g.b2, tile_counts, acc, cnt);
   return hipGetLastError();
 }
 
