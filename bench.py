@@ -95,6 +95,8 @@ def main(argv=None):
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--oracle-views", type=int, default=16,
                     help="views whose sampled tile is checked against the oracle (one tile per view)")
+    ap.add_argument("--oracle-tiles-per-view", type=int, default=1,
+                    help="tiles of each checked view compared with the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--eager-only", action="store_true",
                     help="profiling aid: only run --steps eager steps (no graph, no per-view, no CPU leg) and print timings")
@@ -200,7 +202,7 @@ def main(argv=None):
     # ---- the oracle on sampled tiles of the batched images (untimed) -----------------
     check = None
     if not a.no_oracle_check:
-        check = oracle_check(scene, cams, cfg, img_batched, tile_pairs, a.oracle_views)
+        check = oracle_check(scene, cams, cfg, img_batched, tile_pairs, a.oracle_views, a.oracle_tiles_per_view)
         log(f"[bench] oracle check: {check}")
 
     # ---- the same step re-evaluating every pair in the backward (no pair cache) --------
@@ -441,14 +443,14 @@ def per_view_leg(snp, torch, cfg, scene, cams, params, tg, n_norm, img_batched, 
     return ms, bool(equal)
 
 
-def oracle_check(scene, cams, cfg, images, tile_pairs, max_views):
-    """One tile per view (up to max_views views, spread over the list),
-    chosen by a seeded draw among the tiles whose oracle instance count is
-    at least the view's median (the deep lists): the oracle renders the
-    tile's window in float64 (oracle.render.render_window), compared with
-    the batched step's image there and with the GPU's hit-pair count of that
-    tile.  Returns the largest image and transmittance-free colour error and
-    both pair totals."""
+def oracle_check(scene, cams, cfg, images, tile_pairs, max_views, per_view=1):
+    """`per_view` tiles per view (up to max_views views, spread over the
+    list), chosen by a seeded draw without replacement among the tiles whose
+    oracle instance count is at least the view's median (the deep lists):
+    the oracle renders each tile's window in float64
+    (oracle.render.render_window), compared with the batched step's image
+    there and with the GPU's hit-pair count of that tile.  Returns the
+    largest image error and both pair totals."""
     from oracle.keys import project_all
     from oracle.render import RenderOptions, render_window
 
@@ -477,20 +479,22 @@ def oracle_check(scene, cams, cfg, images, tile_pairs, max_views):
         np.add.at(diff, (tr[:, 3] + 1, tr[:, 1] + 1), 1)
         counts = diff.cumsum(0).cumsum(1)[:nty, :ntx].ravel()
         cand = np.nonzero(counts >= max(1, np.median(counts)))[0]
-        t = int(rng.choice(cand))
-        ty, tx = divmod(t, ntx)
-        x0, y0 = tx * tw, ty * th
-        w, h = min(tw, cam.width - x0), min(th, cam.height - y0)
-        ref = render_window(scene, cam, x0, y0, w, h, opts, proj=proj)
         view_img = img[3 * pix_off[v]:3 * pix_off[v + 1]].reshape(cam.height, cam.width, 3)
-        err = float(np.max(np.abs(view_img[y0:y0 + h, x0:x0 + w] - ref["image"])))
-        worst = max(worst, err)
-        gp = int(tile_pairs[tile_off[v] + t])
-        gpu_pairs += gp
-        ora_pairs += int(ref["hit_pairs"])
-        eq = eq and gp == int(ref["hit_pairs"])
-        npix += w * h
-        picked.append([int(v), int(t), int(ref["primitives"])])
+        chosen = rng.choice(cand, size=min(per_view, len(cand)), replace=False) if per_view > 1 else [rng.choice(cand)]
+        for t in chosen:
+            t = int(t)
+            ty, tx = divmod(t, ntx)
+            x0, y0 = tx * tw, ty * th
+            w, h = min(tw, cam.width - x0), min(th, cam.height - y0)
+            ref = render_window(scene, cam, x0, y0, w, h, opts, proj=proj)
+            err = float(np.max(np.abs(view_img[y0:y0 + h, x0:x0 + w] - ref["image"])))
+            worst = max(worst, err)
+            gp = int(tile_pairs[tile_off[v] + t])
+            gpu_pairs += gp
+            ora_pairs += int(ref["hit_pairs"])
+            eq = eq and gp == int(ref["hit_pairs"])
+            npix += w * h
+            picked.append([int(v), int(t), int(ref["primitives"])])
     return {"views": len(views), "tiles": len(picked), "pixels": npix, "max_img_err": worst,
             "hit_pairs_gpu": gpu_pairs, "hit_pairs_oracle": ora_pairs, "hit_pairs_equal": bool(eq),
             "tiles_view_tile_primitives": picked, "seconds": round(time.perf_counter() - t0, 1)}

@@ -68,3 +68,38 @@ def test_workload_names_and_small_scenes(name):
     else:
         assert scene["wt"] is None
     assert np.all(np.isfinite(scene["centers"])) and np.all(scene["scales"] > 0)
+
+
+def test_oracle_check_of_the_bench_on_oracle_images():
+    """The bench's tile check, fed with the oracle's own images and per-tile
+    hit-pair counts, reports no error and equal counts; a perturbed pixel of
+    a checked tile is reported."""
+    import torch
+
+    from oracle.render import RenderOptions, render_view, render_window
+    from paper_2510_08491_amd.render import RenderConfig
+
+    _, scene, cams, _ = S.make_workload("C4", n_prims=300, sizes=[(48, 32), (32, 48)])
+    cfg = RenderConfig(n_hidden=scene["N"], color_mode=scene["color_mode"], cmlp_width=scene["cmlp_width"],
+                       cmlp_depth=scene["cmlp_depth"], tile_w=16, tile_h=16)
+    opts = RenderOptions(z_near=cfg.z_near, t_eps=cfg.t_eps, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
+                         bg=tuple(cfg.bg))
+    imgs, pairs = [], []
+    for cam in cams:
+        imgs.append(render_view(scene, cam, opts)["image"].ravel())
+        for ty in range((cam.height + 15) // 16):
+            for tx in range((cam.width + 15) // 16):
+                w, h = min(16, cam.width - 16 * tx), min(16, cam.height - 16 * ty)
+                pairs.append(render_window(scene, cam, 16 * tx, 16 * ty, w, h, opts)["hit_pairs"])
+    images = torch.from_numpy(np.concatenate(imgs).astype(np.float32))
+    tile_pairs = np.array(pairs)
+    r = bench.oracle_check(scene, cams, cfg, images, tile_pairs, 16, per_view=3)
+    assert r["tiles"] == 6 and r["hit_pairs_equal"] and r["hit_pairs_gpu"] == r["hit_pairs_oracle"] > 0
+    assert r["max_img_err"] < 1e-6
+    # one checked tile's pixel off by 1e-3
+    v, t, _ = r["tiles_view_tile_primitives"][0]
+    ntx = (cams[v].width + 15) // 16
+    ty, tx = divmod(t, ntx)
+    off = sum(c.width * c.height for c in cams[:v])
+    images[3 * (off + (16 * ty) * cams[v].width + 16 * tx)] += 1e-3
+    assert bench.oracle_check(scene, cams, cfg, images, tile_pairs, 16, per_view=3)["max_img_err"] > 9e-4
