@@ -97,6 +97,8 @@ def main(argv=None):
                     help="views whose sampled tile is checked against the oracle (one tile per view)")
     ap.add_argument("--oracle-tiles-per-view", type=int, default=1,
                     help="tiles of each checked view compared with the oracle")
+    ap.add_argument("--oracle-grad-primitives", type=int, default=0,
+                    help="primitives whose gradients from one step are checked against the oracle (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--eager-only", action="store_true",
                     help="profiling aid: only run --steps eager steps (no graph, no per-view, no CPU leg) and print timings")
@@ -219,6 +221,12 @@ def main(argv=None):
         recompute = {"fwd_ms": round(f_rc, 4), "bwd_ms": round(b_rc, 4), "images_identical": same}
         log(f"[bench] without the pair cache: forward {f_rc:.3f} ms, backward {b_rc:.3f} ms, images identical {same}")
 
+    grad_check = None
+    if a.oracle_grad_primitives > 0:
+        grad_check = oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, tg, n_norm,
+                                       a.oracle_grad_primitives)
+        log(f"[bench] oracle gradient check: {grad_check}")
+
     # ---- Adam over every parameter (HBM bound; after the step, not in the metric) --
     optimizer = adam_leg(snp, torch, params)
     log(f"[bench] adam: {optimizer}")
@@ -293,6 +301,7 @@ def main(argv=None):
         "without_pair_cache": recompute,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "oracle_grad_check": grad_check,
         "optimizer": optimizer,
         "training_extras": extras,
         "paper_context": "218.87 FPS forward-only full pipeline, 100k random primitives, RTX 4090 (App. A)",
@@ -498,6 +507,82 @@ def oracle_check(scene, cams, cfg, images, tile_pairs, max_views, per_view=1):
     return {"views": len(views), "tiles": len(picked), "pixels": npix, "max_img_err": worst,
             "hit_pairs_gpu": gpu_pairs, "hit_pairs_oracle": ora_pairs, "hit_pairs_equal": bool(eq),
             "tiles_view_tile_primitives": picked, "seconds": round(time.perf_counter() - t0, 1)}
+
+
+def oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, tg, n_norm, K):
+    """Gradients of K sampled primitives from one step of the bench's own
+    launch against the float64 autograd route.  A primitive changes only the
+    pixels inside its rectangle, so its exact gradient is the sum over the
+    views of the gradient of the L1 loss restricted to its rectangle there:
+    the oracle renders each such window with every primitive that meets it
+    (in index order, so the depth order is kept), scaled by the window's
+    share of the loss's pixel count.  The primitives are drawn (seeded)
+    among the quarter with the smallest footprints, so the windows stay
+    small.  Returns the worst normwise error per parameter array and the
+    number of window pixels where the GPU's and the oracle's images fall on
+    different sides of the target (where the L1 gradients' signs differ)."""
+    from oracle.grad import PARAM_KEYS, autograd_loss_and_grads
+    from oracle.keys import project_all
+    from oracle.render import RenderOptions, window_camera
+
+    r = snp.Rasterizer(cfg, scene["P"], cams)
+    r._alloc(int(r.prepare(params) * 1.1) + 4096)
+    images, T = r.new_images()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dL = torch.empty_like(images)
+    grads = snp.zeros_like_params(params)
+    r.step(params, images, T, tg, n_norm, loss, dL, grads)
+    torch.cuda.synchronize()
+    img = images.cpu().numpy()
+    del r, images, T, dL
+    torch.cuda.empty_cache()
+    opts = RenderOptions(z_near=cfg.z_near, t_eps=cfg.t_eps, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
+                         bg=tuple(cfg.bg))
+    t0 = time.perf_counter()
+    P = scene["P"]
+    projs = [project_all(scene, c, cfg.tile_w, cfg.tile_h, cfg.z_near) for c in cams]
+    area = np.zeros(P)
+    for pr in projs:
+        rr = pr["rect"]
+        area += np.where(pr["nonempty"], (rr[:, 1] - rr[:, 0] + 1) * (rr[:, 3] - rr[:, 2] + 1), 0)
+    cand = np.nonzero((area > 0) & (area <= np.quantile(area[area > 0], 0.25)))[0]
+    picked = np.sort(np.random.default_rng(5).choice(cand, size=min(K, len(cand)), replace=False))
+    pix_off = np.cumsum([0] + [c.width * c.height for c in cams])
+    keys = [k for k in PARAM_KEYS if scene.get(k) is not None and k in grads]
+    worst = {k: 0.0 for k in keys}
+    sign_flips, windows, wpix = 0, 0, 0
+    for p in picked:
+        ref = {k: np.zeros(np.asarray(scene[k][p]).shape) for k in keys}
+        for v, cam in enumerate(cams):
+            pr = projs[v]
+            if not pr["nonempty"][p]:
+                continue
+            x0, x1, y0, y1 = (int(x) for x in pr["rect"][p])
+            w, h = x1 - x0 + 1, y1 - y0 + 1
+            rr = pr["rect"]
+            ids = np.nonzero(pr["nonempty"] & (rr[:, 0] <= x1) & (rr[:, 1] >= x0) & (rr[:, 2] <= y1)
+                             & (rr[:, 3] >= y0))[0]
+            sub = dict(scene)
+            for k, val in scene.items():
+                if isinstance(val, np.ndarray) and val.ndim >= 1 and val.shape[0] == P:
+                    sub[k] = val[ids]
+            sub["P"] = len(ids)
+            tgt = targets[v][y0:y1 + 1, x0:x1 + 1]
+            _, g, wimg = autograd_loss_and_grads(sub, [window_camera(cam, x0, y0, w, h)], [tgt], opts)
+            gimg = img[3 * pix_off[v]:3 * pix_off[v + 1]].reshape(cam.height, cam.width, 3)[y0:y1 + 1, x0:x1 + 1]
+            sign_flips += int(np.sum(np.sign(gimg - tgt) != np.sign(wimg[0] - tgt)))
+            i = int(np.searchsorted(ids, p))
+            for k in keys:
+                ref[k] += g[k][i] * (w * h * 3 / n_norm)
+            windows += 1
+            wpix += w * h
+        for k in keys:
+            gg = grads[k][int(p)].detach().cpu().numpy().astype(np.float64)
+            den = float(np.max(np.abs(ref[k])))
+            worst[k] = max(worst[k], float(np.max(np.abs(gg - ref[k]))) / den if den > 0 else float(np.max(np.abs(gg))))
+    return {"primitives": [int(p) for p in picked], "windows": windows, "window_pixels": wpix,
+            "worst_normwise_err": {k: float(f"{e:.3g}") for k, e in worst.items()}, "sign_flips": sign_flips,
+            "seconds": round(time.perf_counter() - t0, 1)}
 
 
 def _fps(snp, torch, scene, cams, cfg, a, label):

@@ -103,3 +103,67 @@ def test_oracle_check_of_the_bench_on_oracle_images():
     off = sum(c.width * c.height for c in cams[:v])
     images[3 * (off + (16 * ty) * cams[v].width + 16 * tx)] += 1e-3
     assert bench.oracle_check(scene, cams, cfg, images, tile_pairs, 16, per_view=3)["max_img_err"] > 9e-4
+
+
+class _FakeRasterizer:
+    """Stands in for the device rasterizer: its step writes the oracle's
+    full-view images and gradients (so the windowed check must reproduce
+    them from windows alone)."""
+    full = None
+
+    def __init__(self, cfg, P, cams):
+        pass
+
+    def prepare(self, params):
+        return 1
+
+    def _alloc(self, n):
+        pass
+
+    def new_images(self):
+        import torch
+        return torch.zeros(_FakeRasterizer.full["n_img"], dtype=torch.float32), None
+
+    def step(self, params, images, T, tg, n_norm, loss, dL, grads):
+        import torch
+        images.copy_(torch.from_numpy(_FakeRasterizer.full["images"]))
+        for k, g in _FakeRasterizer.full["grads"].items():
+            if k in grads:
+                grads[k].copy_(torch.from_numpy(g))
+
+
+def test_windowed_gradients_sum_to_the_full_view_gradients(monkeypatch):
+    """The bench's gradient check builds each sampled primitive's gradient
+    from the windows of its rectangles alone; on a small scene it must equal
+    the oracle's full-view autograd gradient (the windowing argument: a
+    primitive changes only the pixels inside its rectangle)."""
+    import types
+
+    import torch
+
+    from oracle.grad import PARAM_KEYS, autograd_loss_and_grads
+    from oracle.render import RenderOptions
+    from paper_2510_08491_amd.render import RenderConfig
+
+    _, scene, cams, targets = S.make_workload("C4", n_prims=120, sizes=[(40, 32), (32, 40)])
+    cfg = RenderConfig(n_hidden=scene["N"], color_mode=scene["color_mode"], cmlp_width=scene["cmlp_width"],
+                       cmlp_depth=scene["cmlp_depth"], tile_w=16, tile_h=16)
+    opts = RenderOptions(z_near=cfg.z_near, t_eps=cfg.t_eps, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
+                         bg=tuple(cfg.bg))
+    _, g, imgs = autograd_loss_and_grads(scene, cams, targets, opts)
+    flat = np.concatenate([np.asarray(i).ravel() for i in imgs]).astype(np.float32)
+    _FakeRasterizer.full = {"n_img": flat.size, "images": flat,
+                            "grads": {k: np.asarray(v, np.float32) for k, v in g.items()}}
+    snp = types.SimpleNamespace(
+        Rasterizer=_FakeRasterizer,
+        zeros_like_params=lambda params: {k: torch.zeros_like(v) for k, v in params.items()})
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda: None)
+    monkeypatch.setattr(torch.cuda, "empty_cache", lambda: None)
+    params = {k: torch.from_numpy(np.asarray(scene[k], np.float32)) for k in PARAM_KEYS if scene.get(k) is not None}
+    n_norm = float(sum(t.size for t in targets))
+    real_zeros = torch.zeros
+    monkeypatch.setattr(torch, "zeros", lambda *a, **kw: real_zeros(*a, **{k: v for k, v in kw.items() if k != "device"}))
+    r = bench.oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, None, n_norm, 6)
+    assert r["windows"] > 6 and r["sign_flips"] == 0
+    # float32 copies of the full-view gradients against the float64 windows
+    assert max(r["worst_normwise_err"].values()) < 1e-6, r
