@@ -119,6 +119,11 @@ def main(argv=None):
 
     # ---- the oracle on the host's cores, before the GPU is touched (the
     # worker processes are forked from a process without a GPU context) -----------
+    grad_ref = None
+    if a.oracle_grad_primitives > 0:
+        grad_ref = oracle_grad_reference(scene, cams, targets, a.oracle_grad_primitives)
+        log(f"[bench] oracle gradients of {len(grad_ref['primitives'])} primitives over "
+            f"{len(grad_ref['windows'])} windows in {grad_ref['seconds']} s")
     cpu = None
     if not a.no_cpu_baseline and not a.eager_only:
         cpu = cpu_baseline(scene, cams, targets, a.cpu_seconds, a.workload)
@@ -222,9 +227,8 @@ def main(argv=None):
         log(f"[bench] without the pair cache: forward {f_rc:.3f} ms, backward {b_rc:.3f} ms, images identical {same}")
 
     grad_check = None
-    if a.oracle_grad_primitives > 0:
-        grad_check = oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, tg, n_norm,
-                                       a.oracle_grad_primitives)
+    if grad_ref is not None:
+        grad_check = oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, tg, n_norm, grad_ref)
         log(f"[bench] oracle gradient check: {grad_check}")
 
     # ---- Adam over every parameter (HBM bound; after the step, not in the metric) --
@@ -509,22 +513,94 @@ def oracle_check(scene, cams, cfg, images, tile_pairs, max_views, per_view=1):
             "tiles_view_tile_primitives": picked, "seconds": round(time.perf_counter() - t0, 1)}
 
 
-def oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, tg, n_norm, K):
-    """Gradients of K sampled primitives from one step of the bench's own
-    launch against the float64 autograd route.  A primitive changes only the
-    pixels inside its rectangle, so its exact gradient is the sum over the
-    views of the gradient of the L1 loss restricted to its rectangle there:
-    the oracle renders each such window with every primitive that meets it
-    (in index order, so the depth order is kept), scaled by the window's
-    share of the loss's pixel count.  The primitives are drawn (seeded)
-    among the quarter with the smallest footprints, so the windows stay
-    small.  Returns the worst normwise error per parameter array and the
-    number of window pixels where the GPU's and the oracle's images fall on
-    different sides of the target (where the L1 gradients' signs differ)."""
-    from oracle.grad import PARAM_KEYS, autograd_loss_and_grads
-    from oracle.keys import project_all
-    from oracle.render import RenderOptions, window_camera
+_GRAD_SCENE = None  # the scene the gradient-check workers slice (inherited through fork)
 
+
+def _grad_window(job):
+    """One window of the gradient check: the oracle's autograd gradient of
+    the L1 loss over the window, with respect to primitive `p`, scaled by the
+    window's share of the loss's pixel count; and the signs of the oracle's
+    image minus the target there."""
+    import torch
+    from oracle.grad import autograd_loss_and_grads
+    from oracle.render import window_camera
+    torch.set_num_threads(1)
+    ids, i, cam, x0, y0, w, h, tgt, opts, n_norm = job
+    scene = _GRAD_SCENE
+    sub = dict(scene)
+    for k, val in scene.items():
+        if isinstance(val, np.ndarray) and val.ndim >= 1 and val.shape[0] == scene["P"]:
+            sub[k] = val[ids]
+    sub["P"] = len(ids)
+    _, g, wimg = autograd_loss_and_grads(sub, [window_camera(cam, x0, y0, w, h)], [tgt], opts)
+    return {k: v[i] * (w * h * 3 / n_norm) for k, v in g.items()}, np.sign(wimg[0] - tgt)
+
+
+def oracle_grad_reference(scene, cams, targets, K):
+    """The oracle's side of the gradient check, on the host before the GPU
+    is touched (its workers are forked): K primitives drawn (seeded) among
+    the quarter with the smallest footprints; a primitive changes only the
+    pixels inside its rectangle, so its exact gradient is the sum over the
+    views of the gradient of the L1 loss restricted to its rectangle there,
+    rendered with every primitive that meets the rectangle (in index order,
+    so the depth order is kept).  Returns the primitives, their reference
+    gradients, and per window the oracle's signs of image minus target."""
+    import multiprocessing as mp
+    from oracle.keys import project_all
+    from oracle.render import RenderOptions
+    from paper_2510_08491_amd.render import RenderConfig
+
+    global _GRAD_SCENE
+    cfg = RenderConfig()
+    opts = RenderOptions(z_near=cfg.z_near, t_eps=cfg.t_eps, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
+                         bg=tuple(cfg.bg))
+    t0 = time.perf_counter()
+    P = scene["P"]
+    n_norm = float(sum(np.asarray(t).size for t in targets))
+    projs = [project_all(scene, c, 16, 16, cfg.z_near) for c in cams]
+    area = np.zeros(P)
+    for pr in projs:
+        rr = pr["rect"]
+        area += np.where(pr["nonempty"], (rr[:, 1] - rr[:, 0] + 1) * (rr[:, 3] - rr[:, 2] + 1), 0)
+    cand = np.nonzero((area > 0) & (area <= np.quantile(area[area > 0], 0.25)))[0]
+    picked = np.sort(np.random.default_rng(5).choice(cand, size=min(K, len(cand)), replace=False))
+    jobs, where = [], []
+    for p in picked:
+        for v, cam in enumerate(cams):
+            pr = projs[v]
+            if not pr["nonempty"][p]:
+                continue
+            x0, x1, y0, y1 = (int(x) for x in pr["rect"][p])
+            rr = pr["rect"]
+            ids = np.nonzero(pr["nonempty"] & (rr[:, 0] <= x1) & (rr[:, 1] >= x0) & (rr[:, 2] <= y1)
+                             & (rr[:, 3] >= y0))[0]
+            jobs.append((ids, int(np.searchsorted(ids, p)), cam, x0, y0, x1 - x0 + 1, y1 - y0 + 1,
+                         targets[v][y0:y1 + 1, x0:x1 + 1], opts, n_norm))
+            where.append((int(p), v, x0, y0, x1 - x0 + 1, y1 - y0 + 1))
+    _GRAD_SCENE = scene
+    res = []
+    with mp.get_context("fork").Pool(host_cores()) as pool:
+        for r in pool.imap(_grad_window, jobs, chunksize=1):
+            res.append(r)
+            if len(res) % 16 == 0:
+                log(f"[bench] oracle gradient windows: {len(res)} of {len(jobs)}")
+    ref = {}
+    for (p, *_), (g, _) in zip(where, res):
+        acc = ref.setdefault(p, {})
+        for k, v in g.items():
+            acc[k] = acc.get(k, 0.0) + v
+    windows = [(w, sg) for w, (_, sg) in zip(where, res)]
+    return {"primitives": [int(p) for p in picked], "ref": ref, "windows": windows,
+            "seconds": round(time.perf_counter() - t0, 1)}
+
+
+def oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, tg, n_norm, reference):
+    """The GPU's side: gradients from one step of the bench's own launch
+    (configuration, tile, pair cache) for the reference's primitives, each
+    parameter array compared normwise with the oracle's; and the window
+    pixels where the GPU's image and the oracle's fall on different sides of
+    the target (the L1 gradients' signs differ there, so the comparison
+    would not hold)."""
     r = snp.Rasterizer(cfg, scene["P"], cams)
     r._alloc(int(r.prepare(params) * 1.1) + 4096)
     images, T = r.new_images()
@@ -536,53 +612,25 @@ def oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, tg, n_norm,
     img = images.cpu().numpy()
     del r, images, T, dL
     torch.cuda.empty_cache()
-    opts = RenderOptions(z_near=cfg.z_near, t_eps=cfg.t_eps, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
-                         bg=tuple(cfg.bg))
-    t0 = time.perf_counter()
-    P = scene["P"]
-    projs = [project_all(scene, c, cfg.tile_w, cfg.tile_h, cfg.z_near) for c in cams]
-    area = np.zeros(P)
-    for pr in projs:
-        rr = pr["rect"]
-        area += np.where(pr["nonempty"], (rr[:, 1] - rr[:, 0] + 1) * (rr[:, 3] - rr[:, 2] + 1), 0)
-    cand = np.nonzero((area > 0) & (area <= np.quantile(area[area > 0], 0.25)))[0]
-    picked = np.sort(np.random.default_rng(5).choice(cand, size=min(K, len(cand)), replace=False))
     pix_off = np.cumsum([0] + [c.width * c.height for c in cams])
-    keys = [k for k in PARAM_KEYS if scene.get(k) is not None and k in grads]
-    worst = {k: 0.0 for k in keys}
-    sign_flips, windows, wpix = 0, 0, 0
-    for p in picked:
-        ref = {k: np.zeros(np.asarray(scene[k][p]).shape) for k in keys}
-        for v, cam in enumerate(cams):
-            pr = projs[v]
-            if not pr["nonempty"][p]:
+    flips, wpix = 0, 0
+    for (p, v, x0, y0, w, h), sg in reference["windows"]:
+        cam = cams[v]
+        gimg = img[3 * pix_off[v]:3 * pix_off[v + 1]].reshape(cam.height, cam.width, 3)[y0:y0 + h, x0:x0 + w]
+        flips += int(np.sum(np.sign(gimg - targets[v][y0:y0 + h, x0:x0 + w]) != sg))
+        wpix += w * h
+    worst = {}
+    for p, ref in reference["ref"].items():
+        for k, rk in ref.items():
+            if k not in grads:
                 continue
-            x0, x1, y0, y1 = (int(x) for x in pr["rect"][p])
-            w, h = x1 - x0 + 1, y1 - y0 + 1
-            rr = pr["rect"]
-            ids = np.nonzero(pr["nonempty"] & (rr[:, 0] <= x1) & (rr[:, 1] >= x0) & (rr[:, 2] <= y1)
-                             & (rr[:, 3] >= y0))[0]
-            sub = dict(scene)
-            for k, val in scene.items():
-                if isinstance(val, np.ndarray) and val.ndim >= 1 and val.shape[0] == P:
-                    sub[k] = val[ids]
-            sub["P"] = len(ids)
-            tgt = targets[v][y0:y1 + 1, x0:x1 + 1]
-            _, g, wimg = autograd_loss_and_grads(sub, [window_camera(cam, x0, y0, w, h)], [tgt], opts)
-            gimg = img[3 * pix_off[v]:3 * pix_off[v + 1]].reshape(cam.height, cam.width, 3)[y0:y1 + 1, x0:x1 + 1]
-            sign_flips += int(np.sum(np.sign(gimg - tgt) != np.sign(wimg[0] - tgt)))
-            i = int(np.searchsorted(ids, p))
-            for k in keys:
-                ref[k] += g[k][i] * (w * h * 3 / n_norm)
-            windows += 1
-            wpix += w * h
-        for k in keys:
             gg = grads[k][int(p)].detach().cpu().numpy().astype(np.float64)
-            den = float(np.max(np.abs(ref[k])))
-            worst[k] = max(worst[k], float(np.max(np.abs(gg - ref[k]))) / den if den > 0 else float(np.max(np.abs(gg))))
-    return {"primitives": [int(p) for p in picked], "windows": windows, "window_pixels": wpix,
-            "worst_normwise_err": {k: float(f"{e:.3g}") for k, e in worst.items()}, "sign_flips": sign_flips,
-            "seconds": round(time.perf_counter() - t0, 1)}
+            den = float(np.max(np.abs(rk)))
+            e = float(np.max(np.abs(gg - rk))) / den if den > 0 else float(np.max(np.abs(gg)))
+            worst[k] = max(worst.get(k, 0.0), e)
+    return {"primitives": reference["primitives"], "windows": len(reference["windows"]), "window_pixels": wpix,
+            "worst_normwise_err": {k: float(f"{e:.3g}") for k, e in worst.items()}, "sign_flips": flips,
+            "oracle_seconds": reference["seconds"]}
 
 
 def _fps(snp, torch, scene, cams, cfg, a, label):

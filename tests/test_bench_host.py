@@ -150,6 +150,9 @@ def test_windowed_gradients_sum_to_the_full_view_gradients(monkeypatch):
                        cmlp_depth=scene["cmlp_depth"], tile_w=16, tile_h=16)
     opts = RenderOptions(z_near=cfg.z_near, t_eps=cfg.t_eps, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
                          bg=tuple(cfg.bg))
+    # the oracle's windows first: its workers are forked, which a process
+    # that has already run an autograd backward cannot do safely
+    ref = bench.oracle_grad_reference(scene, cams, targets, 6)
     _, g, imgs = autograd_loss_and_grads(scene, cams, targets, opts)
     flat = np.concatenate([np.asarray(i).ravel() for i in imgs]).astype(np.float32)
     _FakeRasterizer.full = {"n_img": flat.size, "images": flat,
@@ -163,7 +166,7 @@ def test_windowed_gradients_sum_to_the_full_view_gradients(monkeypatch):
     n_norm = float(sum(t.size for t in targets))
     real_zeros = torch.zeros
     monkeypatch.setattr(torch, "zeros", lambda *a, **kw: real_zeros(*a, **{k: v for k, v in kw.items() if k != "device"}))
-    r = bench.oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, None, n_norm, 6)
+    r = bench.oracle_grad_check(snp, torch, cfg, scene, cams, targets, params, None, n_norm, ref)
     assert r["windows"] > 6 and r["sign_flips"] == 0
     # float32 copies of the full-view gradients against the float64 windows
     assert max(r["worst_normwise_err"].values()) < 1e-6, r
