@@ -408,7 +408,9 @@ def training_extras_leg(snp, torch, cfg, scene, cams, params, tg, n_norm):
             "densify_statistic": {"ms": round(acc_ms, 4), "bytes": acc_bytes,
                                   "GB_per_s": round(acc_bytes / (acc_ms * 1e-3) / 1e9, 1)},
             "densify_pass": {"ms_wall": round(dens_ms, 3), "primitives_before": P, "primitives_after": n_new,
-                             "note": "plan, one host synchronisation, allocation of the new arrays, row carry-over"}}
+                             "note": "plan with the default thresholds on the statistic of the six timed accumulations "
+                                     "(most primitives of the random scene fall under the prune threshold), one host "
+                                     "synchronisation, allocation of the new arrays, row carry-over"}}
 
 
 def per_view_leg(snp, torch, cfg, scene, cams, params, tg, n_norm, img_batched, a):
