@@ -408,9 +408,7 @@ __global__ void __launch_bounds__(256) preprocess_views_kernel(ViewArgs a) {
 
 // ---------------------------------------------------------------------------
 // colour MLP: input [normalize(x_B - o_v), xi_p], DEPTH ReLU layers of WIDTH
-// units, sigmoid RGB.  Lanes of one primitive's views are adjacent (group of
-// GS lanes, views v = lane, lane + GS, ...), so the weight loads of a group
-// hit the same addresses.
+// units, sigmoid RGB, with weights of its own for every primitive.
 // ---------------------------------------------------------------------------
 
 // IN = 11: [view direction, xi] (colour mode 1); IN = 14: [view direction,
@@ -455,56 +453,108 @@ __device__ __forceinline__ void cmlp_input(const CmlpArgs& a, int64_t p, int v, 
   for (int k = 0; k < kXiDim; ++k) x[IN - kXiDim + k] = a.xi[p * kXiDim + k];
 }
 
+// Forward of the colour MLP on the matrix cores, one wave per primitive and 16
+// of its views at a time.  Every layer is a product W (units x inputs) times X^T
+// (inputs x views) in 16x16x4 FP32 steps: lane (g, c) = (lane / 16, lane %
+// 16) supplies the weight of unit 16 t + c for input 4 s + g (operand A) and
+// input 4 s + g of view c (operand B), and receives units 16 t + 4 g + r of
+// view c in register r.  rows_to_regs then transposes those four registers
+// with the wave's four rows of 16 lanes, so that lane (g, c) holds unit
+// 16 t + 4 s + g of view c in register s: the next layer's operand B as it
+// stands.  Each weight is loaded once per 16 views by exactly one lane.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f rows_to_regs(v4f d) {
+  // v_permlane32_swap(x, y): the upper two rows of x trade places with the
+  // lower two of y; v_permlane16_swap(x, y): the odd rows of x with the even
+  // rows of y.  Element (row g, register r) ends at (row r, register g).
+  const auto a02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(d[0]), __float_as_uint(d[2]), false, false);
+  const auto a13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(d[1]), __float_as_uint(d[3]), false, false);
+  const auto b01 = __builtin_amdgcn_permlane16_swap(a02[0], a13[0], false, false);
+  const auto b23 = __builtin_amdgcn_permlane16_swap(a02[1], a13[1], false, false);
+  return v4f{__uint_as_float(b01[0]), __uint_as_float(b01[1]), __uint_as_float(b23[0]), __uint_as_float(b23[1])};
+}
+
 template <int WIDTH, int DEPTH, int IN>
-__global__ void __launch_bounds__(256) cmlp_fwd_kernel(CmlpArgs a) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t p = gid / a.GS;
-  const int lane_v = (int)(gid - p * a.GS);
-  if (p >= a.P) return;
+__global__ void __launch_bounds__(256) cmlp_fwd_mfma_kernel(CmlpArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // one wave per primitive
+  if (p >= a.P) return;  // wave-uniform
+  const int lane = (int)(threadIdx.x & 63), g = lane >> 4, c = lane & 15;
   constexpr int K = CmlpShape<WIDTH, DEPTH, IN>::K;
+  constexpr int T = WIDTH / 16;     // tiles of 16 units
+  constexpr int S0 = (IN + 3) / 4;  // steps of four inputs in the first layer
   const float* Wp = a.cmlp + p * K;
-  for (int v = lane_v; v < a.V; v += a.GS) {
-    const int64_t i = (int64_t)v * a.P + p;
-    if (a.tile_counts[i] == 0) continue;
+  for (int v0 = 0; v0 < a.V; v0 += 16) {
+    const int v = v0 + c;
+    const bool vis = v < a.V && a.tile_counts[(int64_t)v * a.P + p] != 0;
+    if (__ballot(vis) == 0) continue;  // wave-uniform
     float x[IN], dir[3], il;
-    cmlp_input<IN>(a, p, v, x, dir, &il);
-    float h[WIDTH], g[WIDTH];
-    int off = 0;
-    // layer 0
+    cmlp_input<IN>(a, p, v < a.V ? v : v0, x, dir, &il);  // lanes past the last view repeat a valid one
+    float bx[S0];
 #pragma unroll
-    for (int o = 0; o < WIDTH; ++o) {
-      float acc = Wp[off + IN * WIDTH + o];
+    for (int s = 0; s < S0; ++s) {
+      float t = 0.f;
 #pragma unroll
-      for (int k = 0; k < IN; ++k) acc = __builtin_fmaf(Wp[off + o * IN + k], x[k], acc);
-      h[o] = fmaxf(acc, 0.f);
+      for (int q = 0; q < 4; ++q)
+        if (4 * s + q < IN) t = g == q ? x[4 * s + q] : t;
+      bx[s] = t;
     }
-    off += IN * WIDTH + WIDTH;
+    v4f h[T];
 #pragma unroll
-    for (int l = 1; l < DEPTH; ++l) {
+    for (int t = 0; t < T; ++t) {
+      v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int o = 0; o < WIDTH; ++o) {
-        float acc = Wp[off + WIDTH * WIDTH + o];
-#pragma unroll
-        for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], h[k], acc);
-        g[o] = fmaxf(acc, 0.f);
+      for (int s = 0; s < S0; ++s) {
+        const int k = 4 * s + g;
+        const float w = k < IN ? Wp[(16 * t + c) * IN + k] : 0.f;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(w, bx[s], d, 0, 0, 0);
       }
 #pragma unroll
-      for (int o = 0; o < WIDTH; ++o) h[o] = g[o];
+      for (int r = 0; r < 4; ++r) d[r] = fmaxf(d[r] + Wp[IN * WIDTH + 16 * t + 4 * g + r], 0.f);
+      h[t] = rows_to_regs(d);
+    }
+    int off = IN * WIDTH + WIDTH;
+#pragma unroll
+    for (int l = 1; l < DEPTH; ++l) {
+      v4f nh[T];
+#pragma unroll
+      for (int to = 0; to < T; ++to) {
+        v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(Wp[off + (16 * to + c) * WIDTH + 16 * t + 4 * s + g], h[t][s], d,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[r] = fmaxf(d[r] + Wp[off + WIDTH * WIDTH + 16 * to + 4 * g + r], 0.f);
+        nh[to] = rows_to_regs(d);
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) h[t] = nh[t];
       off += WIDTH * WIDTH + WIDTH;
     }
-    float out[3];
+    // output layer: rows 0..2 of the tile (units c < 3 carry weights)
+    v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int o = 0; o < 3; ++o) {
-      float acc = Wp[off + 3 * WIDTH + o];
+    for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int k = 0; k < WIDTH; ++k) acc = __builtin_fmaf(Wp[off + o * WIDTH + k], h[k], acc);
-      out[o] = 1.0f / (1.0f + expf(-acc));
-      if (IN == 14) out[o] += a.colors[3 * p + o];  // relighting: c_dc + network
+      for (int s = 0; s < 4; ++s) {
+        const float w = c < 3 ? Wp[off + c * WIDTH + 16 * t + 4 * s + g] : 0.f;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(w, h[t][s], d, 0, 0, 0);
+      }
+    if (g == 0 && vis) {  // row group 0 holds outputs 0..3 of view c
+      float out[3];
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        out[o] = 1.0f / (1.0f + expf(-(d[o] + Wp[off + 3 * WIDTH + o])));
+        if (IN == 14) out[o] += a.colors[3 * p + o];  // relighting: c_dc + network
+      }
+      float* rec = a.records + ((int64_t)v * a.P + p) * kRecFloats;
+      rec[11] = out[0];
+      rec[15] = out[1];
+      rec[19] = out[2];
     }
-    float* rec = a.records + i * kRecFloats;
-    rec[11] = out[0];
-    rec[15] = out[1];
-    rec[19] = out[2];
   }
 }
 
@@ -512,11 +562,11 @@ __global__ void __launch_bounds__(256) cmlp_fwd_kernel(CmlpArgs a) {
 // weights are staged in LDS.  Its views are taken 16 at a time; four lanes
 // serve each view (lane = 16 q + view), each computing a quarter of every
 // layer's units, so the per-view forward pass and deltas run on all 64 lanes
-// with activations exchanged through LDS.  Then every weight gradient
-// sum_v delta_v[o] a_v[i] is owned by one lane (entries lane, lane + 64, ...)
-// and summed over the views from LDS, so no cross-lane reduction or atomic
-// is needed; the sums are added to the gradient in HBM with coalesced
-// read-add-writes.  Views culled for the primitive carry zero deltas.
+// with activations exchanged through LDS.  Then the weight gradients
+// sum_v delta_v[o] a_v[i] are products over the views, taken on the matrix
+// cores with operands read from the LDS copies; each gradient entry has one
+// owning lane, which adds it to HBM (no atomics).  Views culled for the
+// primitive carry zero deltas.
 template <int WIDTH, int DEPTH, int IN>
 __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
   constexpr int K = CmlpShape<WIDTH, DEPTH, IN>::K;
@@ -654,48 +704,81 @@ __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
 #pragma unroll
       for (int w = 0; w < VC; ++w) xi_acc += sGx[w][XI0 + lane];
     }
-    // ---- weight gradients: entries idx = lane, lane + 64, ..., summed over
-    // the chunk's views and added to the gradient in HBM
+    // ---- weight gradients: sum over the chunk's 16 views of delta[o] x a[k]
+    // on the matrix cores (K = views, four per step): lane (g, c) supplies
+    // delta[view 4 s + g][unit 16 t + c] (A) and a[view 4 s + g][input
+    // 16 t2 + c] (B) from LDS and receives the gradient of weight (16 t +
+    // 4 g + r, 16 t2 + c) in register r, added to its entry in HBM (each
+    // entry has one owner).  The biases, sums of the deltas alone, are
+    // summed by one lane per unit.
     float* G = a.g_cmlp ? a.g_cmlp + p * K : nullptr;
+    if (G) {
+      // the lane index through an empty asm, so that the compiler does not
+      // hoist this section's addresses out of the view loop and keep them
+      // live through the passes above
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
+      const int g = ln >> 4, c = ln & 15;
+      // first layer: inputs as columns c < IN of one tile (tile loops not
+      // unrolled: one tile's operands live at a time)
 #pragma unroll 1
-    for (int idx = lane; idx < K && G; idx += 64) {
-      float sum = 0.f;
-      if (idx < IN * WIDTH + WIDTH) {  // first layer
-        if (idx < IN * WIDTH) {
-          const int o = idx / IN, k = idx - o * IN;
+      for (int t = 0; t < WIDTH / 16; ++t) {
+        v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int w = 0; w < VC; ++w) sum = __builtin_fmaf(sD[0][w][o], sX[w][k], sum);
-        } else {
-          const int o = idx - IN * WIDTH;
+        for (int s = 0; s < 4; ++s)
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(sD[0][4 * s + g][16 * t + c], c < IN ? sX[4 * s + g][c] : 0.f, d,
+                                                   0, 0, 0);
+        if (c < IN) {
 #pragma unroll
-          for (int w = 0; w < VC; ++w) sum += sD[0][w][o];
-        }
-      } else if (idx < LAST) {  // hidden layer l >= 1
-        const int r = idx - (IN * WIDTH + WIDTH);
-        const int l = 1 + r / (WIDTH * WIDTH + WIDTH);
-        const int rr = r - (l - 1) * (WIDTH * WIDTH + WIDTH);
-        if (rr < WIDTH * WIDTH) {
-          const int o = rr / WIDTH, k = rr - o * WIDTH;
-#pragma unroll
-          for (int w = 0; w < VC; ++w) sum = __builtin_fmaf(sD[l][w][o], sH[l - 1][w][k], sum);
-        } else {
-          const int o = rr - WIDTH * WIDTH;
-#pragma unroll
-          for (int w = 0; w < VC; ++w) sum += sD[l][w][o];
-        }
-      } else {  // output layer
-        const int rr = idx - LAST;
-        if (rr < 3 * WIDTH) {
-          const int o = rr / WIDTH, k = rr - o * WIDTH;
-#pragma unroll
-          for (int w = 0; w < VC; ++w) sum = __builtin_fmaf(sDo[w][o], sH[DEPTH - 1][w][k], sum);
-        } else {
-          const int o = rr - 3 * WIDTH;
-#pragma unroll
-          for (int w = 0; w < VC; ++w) sum += sDo[w][o];
+          for (int r = 0; r < 4; ++r) G[(16 * t + 4 * g + r) * IN + c] += d[r];
         }
       }
-      G[idx] += sum;
+#pragma unroll
+      for (int l = 1; l < DEPTH; ++l) {
+        const int off = IN * WIDTH + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH);
+#pragma unroll 1
+        for (int t = 0; t < WIDTH / 16; ++t)
+#pragma unroll 1
+          for (int t2 = 0; t2 < WIDTH / 16; ++t2) {
+            v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              d = __builtin_amdgcn_mfma_f32_16x16x4f32(sD[l][4 * s + g][16 * t + c], sH[l - 1][4 * s + g][16 * t2 + c],
+                                                       d, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G[off + (16 * t + 4 * g + r) * WIDTH + 16 * t2 + c] += d[r];
+          }
+      }
+      // output layer: rows 0..2 of one tile
+#pragma unroll 1
+      for (int t2 = 0; t2 < WIDTH / 16; ++t2) {
+        v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(c < 3 ? sDo[4 * s + g][c] : 0.f,
+                                                   sH[DEPTH - 1][4 * s + g][16 * t2 + c], d, 0, 0, 0);
+        if (g == 0) {
+#pragma unroll
+          for (int r = 0; r < 3; ++r) G[LAST + r * WIDTH + 16 * t2 + c] += d[r];
+        }
+      }
+      // biases
+      if (lane < WIDTH) {
+#pragma unroll 1
+        for (int l = 0; l < DEPTH; ++l) {
+          const int boff = l == 0 ? IN * WIDTH : IN * WIDTH + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH) + WIDTH * WIDTH;
+          float sum = 0.f;
+#pragma unroll
+          for (int w = 0; w < VC; ++w) sum += sD[l][w][lane];
+          G[boff + lane] += sum;
+        }
+      } else if (lane < WIDTH + 3) {
+        const int o = lane - WIDTH;
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < VC; ++w) sum += sDo[w][o];
+        G[LAST + 3 * WIDTH + o] += sum;
+      }
     }
     __syncthreads();
   }
@@ -901,12 +984,6 @@ hipError_t launch_preprocess_views(const ViewArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-static int group_size(int V) {
-  int gs = 1;
-  while (gs < V && gs < 64) gs <<= 1;
-  return gs;
-}
-
 #define SNP_CMLP_DISPATCH_IN(KERNEL, IN, width, depth, grid, block, st, a)                                \
   do {                                                                                                     \
     if (width == 16 && depth == 1) hipLaunchKernelGGL((KERNEL<16, 1, IN>), grid, block, 0, st, a);         \
@@ -924,10 +1001,9 @@ static int group_size(int V) {
   } while (0)
 
 hipError_t launch_cmlp_fwd(int width, int depth, CmlpArgs a, hipStream_t st) {
-  a.GS = group_size(a.V);
-  const int64_t n = a.P * a.GS;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-  SNP_CMLP_DISPATCH(cmlp_fwd_kernel, width, depth, grid, block, st, a);
+  if (a.P <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.P + 3) / 4)), block(256);
+  SNP_CMLP_DISPATCH(cmlp_fwd_mfma_kernel, width, depth, grid, block, st, a);
   return hipGetLastError();
 }
 

@@ -172,7 +172,7 @@ struct ViewArgs {
 
 struct CmlpArgs {
   int64_t P;
-  int32_t V, GS;
+  int32_t V;
   int32_t relight;  // 1: relighting colour (light direction input, plus c_dc = colors)
   const float *centers, *xi, *cmlp, *colors;
   const CamDev* cams;
