@@ -558,142 +558,187 @@ __global__ void __launch_bounds__(256) cmlp_fwd_mfma_kernel(CmlpArgs a) {
   }
 }
 
-// Backward of the colour MLP, one wave per primitive.  The primitive's
-// weights are staged in LDS.  Its views are taken 16 at a time; four lanes
-// serve each view (lane = 16 q + view), each computing a quarter of every
-// layer's units, so the per-view forward pass and deltas run on all 64 lanes
-// with activations exchanged through LDS.  Then the weight gradients
-// sum_v delta_v[o] a_v[i] are products over the views, taken on the matrix
-// cores with operands read from the LDS copies; each gradient entry has one
-// owning lane, which adds it to HBM (no atomics).  Views culled for the
+// Backward of the colour MLP, one wave per primitive, 16 of its views at a
+// time, every product on the matrix cores in the tile layout of the forward
+// (lane (g, c) = (lane / 16, lane % 16) holds units 16 t + 4 g + r of view c
+// in register r; rows_to_regs makes that the B operand of the next product).
+// The forward is recomputed; the deltas run back through the transposed
+// weights (operand A = W^T, the lanes along the rows of W: 64-byte runs);
+// the input gradient is one more such product.  The weights are read from
+// global memory (L1 and L2 after the first touch): an LDS copy would cost
+// more workgroups per CU than it saves.  Activations, deltas and inputs also go to LDS as [view][unit],
+// the operands of the weight gradients: products over the views, each entry
+// added to HBM by its one owning lane (no atomics).  Views culled for the
 // primitive carry zero deltas.
 template <int WIDTH, int DEPTH, int IN>
 __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
   constexpr int K = CmlpShape<WIDTH, DEPTH, IN>::K;
   constexpr int XI0 = IN - kXiDim;  // first xi input
   constexpr int VC = 16;            // views per chunk
-  constexpr int QW = WIDTH / 4;     // units per lane and layer
+  constexpr int T = WIDTH / 16;     // tiles of 16 units
+  constexpr int S0 = (IN + 3) / 4;  // steps of four inputs in the first layer
   constexpr int LAST = IN * WIDTH + WIDTH + (DEPTH - 1) * (WIDTH * WIDTH + WIDTH);  // output layer offset
-  __shared__ float sW[K];
   __shared__ float sX[VC][IN + 1];
   __shared__ float sH[DEPTH][VC][WIDTH + 1];  // post-ReLU activations
   __shared__ float sD[DEPTH][VC][WIDTH + 1];  // deltas of the hidden pre-activations
   __shared__ float sDo[VC][4];                // deltas of the output pre-activations
   __shared__ float sGx[VC][IN + 1];           // d loss / d input
   const int64_t p = blockIdx.x;
-  const int lane = threadIdx.x, vi = lane & (VC - 1), q = lane >> 4;
+  const int lane = threadIdx.x, g = lane >> 4, c = lane & 15;
   const float* Wg = a.cmlp + p * K;
-  for (int i = lane; i < K; i += 64) sW[i] = Wg[i];
   float xi_acc = 0.f;  // lanes 0..7: sum over views of d loss / d xi[lane]
   float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;  // relighting: d loss / d x_B through the light direction
-  __syncthreads();
   for (int v0 = 0; v0 < a.V; v0 += VC) {
-    const int v = v0 + vi;
-    const int64_t i = (int64_t)v * a.P + p;
+    const int v = v0 + c;
+    const int64_t i = (int64_t)(v < a.V ? v : v0) * a.P + p;
     const bool act = v < a.V && a.tile_counts[i] != 0;
-    // ---- inputs
-    if (q == 0) {
-      float x[IN], dir[3], il = 0.f;
+    // ---- inputs (every lane of view c computes them; row 0 stores them)
+    float x[IN], dir[3], il = 0.f;
 #pragma unroll
-      for (int k = 0; k < IN; ++k) x[k] = 0.f;
-      if (act) cmlp_input<IN>(a, p, v, x, dir, &il);
+    for (int k = 0; k < IN; ++k) x[k] = 0.f;
+    if (act) cmlp_input<IN>(a, p, v, x, dir, &il);
+    if (g == 0) {
 #pragma unroll
-      for (int k = 0; k < IN; ++k) sX[vi][k] = x[k];
+      for (int k = 0; k < IN; ++k) sX[c][k] = x[k];
     }
-    __syncthreads();
-    // ---- forward, a quarter of each layer per lane (the view's input row in
-    // registers, the weight rows read from LDS)
-    {
-      float xin[IN];
+    float bx[S0];
 #pragma unroll
-      for (int k = 0; k < IN; ++k) xin[k] = sX[vi][k];
-#pragma unroll 1
-      for (int t = 0; t < QW; ++t) {
-        const int o = q * QW + t;
-        float s0 = sW[IN * WIDTH + o];
+    for (int s = 0; s < S0; ++s) {
+      float t = 0.f;
 #pragma unroll
-        for (int k = 0; k < IN; ++k) s0 = __builtin_fmaf(sW[o * IN + k], xin[k], s0);
-        sH[0][vi][o] = fmaxf(s0, 0.f);
+      for (int q = 0; q < 4; ++q)
+        if (4 * s + q < IN) t = g == q ? x[4 * s + q] : t;
+      bx[s] = t;
+    }
+    // ---- forward: activations in the tile layout, their transposes as the
+    // next operands, and a [view][unit] copy in LDS
+    v4f hb[T];  // B operands of the next layer
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < S0; ++s) {
+        const int k = 4 * s + g;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(k < IN ? Wg[(16 * t + c) * IN + k] : 0.f, bx[s], d, 0, 0, 0);
       }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        d[r] = fmaxf(d[r] + Wg[IN * WIDTH + 16 * t + 4 * g + r], 0.f);
+        sH[0][c][16 * t + 4 * g + r] = d[r];
+      }
+      hb[t] = rows_to_regs(d);
     }
-    __syncthreads();
 #pragma unroll
     for (int l = 1; l < DEPTH; ++l) {
       const int off = IN * WIDTH + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH);
-      float hin[WIDTH];
+      v4f nb[T];
 #pragma unroll
-      for (int k = 0; k < WIDTH; ++k) hin[k] = sH[l - 1][vi][k];
-#pragma unroll 1
-      for (int t = 0; t < QW; ++t) {
-        const int o = q * QW + t;
-        float s0 = sW[off + WIDTH * WIDTH + o];
+      for (int to = 0; to < T; ++to) {
+        v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int k = 0; k < WIDTH; ++k) s0 = __builtin_fmaf(sW[off + o * WIDTH + k], hin[k], s0);
-        sH[l][vi][o] = fmaxf(s0, 0.f);
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(Wg[off + (16 * to + c) * WIDTH + 16 * t + 4 * s + g], hb[t][s], d,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          d[r] = fmaxf(d[r] + Wg[off + WIDTH * WIDTH + 16 * to + 4 * g + r], 0.f);
+          sH[l][c][16 * to + 4 * g + r] = d[r];
+        }
+        nb[to] = rows_to_regs(d);
       }
-      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < T; ++t) hb[t] = nb[t];
     }
-    if (q < 3) {  // output unit q: sigmoid, then d loss / d pre-sigmoid
-      float s0 = sW[LAST + 3 * WIDTH + q];
-#pragma unroll 8
-      for (int k = 0; k < WIDTH; ++k) s0 = __builtin_fmaf(sW[LAST + q * WIDTH + k], sH[DEPTH - 1][vi][k], s0);
-      const float sg = 1.0f / (1.0f + expf(-s0));
-      sDo[vi][q] = act ? a.gview[i * kGViewFloats + 18 + q] * sg * (1.0f - sg) : 0.f;
-    }
-    __syncthreads();
-    // ---- deltas, last hidden layer down to the first
+    // ---- output: sigmoid and d loss / d pre-sigmoid (row group 0 holds
+    // outputs 0..3 of view c)
+    v4f dout;
     {
-      const float d0 = sDo[vi][0], d1 = sDo[vi][1], d2 = sDo[vi][2];
-#pragma unroll 1
-      for (int t = 0; t < QW; ++t) {
-        const int k = q * QW + t;
-        float d = sW[LAST + k] * d0;
-        d = __builtin_fmaf(sW[LAST + WIDTH + k], d1, d);
-        d = __builtin_fmaf(sW[LAST + 2 * WIDTH + k], d2, d);
-        sD[DEPTH - 1][vi][k] = sH[DEPTH - 1][vi][k] > 0.f ? d : 0.f;
+      v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(c < 3 ? Wg[LAST + c * WIDTH + 16 * t + 4 * s + g] : 0.f, hb[t][s],
+                                                   d, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float dv = 0.f;
+        if (g == 0 && r < 3 && act) {
+          const float sg = 1.0f / (1.0f + expf(-(d[r] + Wg[LAST + 3 * WIDTH + r])));
+          dv = a.gview[i * kGViewFloats + 18 + r] * sg * (1.0f - sg);
+        }
+        dout[r] = dv;
+        if (g == 0) sDo[c][r] = dv;
       }
     }
-    __syncthreads();
+    // ---- deltas: last hidden layer from the output, then down the layers;
+    // operand B = the layer above's deltas, transposed
+    v4f db[T];  // transposed deltas of the layer above
+    {
+      const v4f ob = rows_to_regs(dout);  // lane (g, c) register 0: output g of view c
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        v4f d = {0.f, 0.f, 0.f, 0.f};
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(g < 3 ? Wg[LAST + g * WIDTH + 16 * t + c] : 0.f, ob[0], d, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int u = 16 * t + 4 * g + r;
+          d[r] = sH[DEPTH - 1][c][u] > 0.f ? d[r] : 0.f;
+          sD[DEPTH - 1][c][u] = d[r];
+        }
+        db[t] = rows_to_regs(d);
+      }
+    }
 #pragma unroll
     for (int l = DEPTH - 1; l >= 1; --l) {
       const int off = IN * WIDTH + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH);
-      float din[WIDTH];
+      v4f nb[T];
 #pragma unroll
-      for (int o = 0; o < WIDTH; ++o) din[o] = sD[l][vi][o];
-#pragma unroll 1
-      for (int t = 0; t < QW; ++t) {
-        const int k = q * QW + t;
-        float d = 0.f;
+      for (int t = 0; t < T; ++t) {  // units of layer l - 1
+        v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int o = 0; o < WIDTH; ++o) d = __builtin_fmaf(sW[off + o * WIDTH + k], din[o], d);
-        sD[l - 1][vi][k] = sH[l - 1][vi][k] > 0.f ? d : 0.f;
+        for (int to = 0; to < T; ++to)  // units of layer l
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(Wg[off + (16 * to + 4 * s + g) * WIDTH + 16 * t + c], db[to][s], d,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int u = 16 * t + 4 * g + r;
+          d[r] = sH[l - 1][c][u] > 0.f ? d[r] : 0.f;
+          sD[l - 1][c][u] = d[r];
+        }
+        nb[t] = rows_to_regs(d);
       }
-      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < T; ++t) db[t] = nb[t];
     }
-    // d loss / d input: inputs q, q + 4, q + 8
+    // ---- d loss / d input: rows = inputs (one tile), K = the first layer's units
     {
-      float din[WIDTH];
+      v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int o = 0; o < WIDTH; ++o) din[o] = sD[0][vi][o];
-#pragma unroll 1
-      for (int k = q; k < IN; k += 4) {
-        float gx = 0.f;
+      for (int to = 0; to < T; ++to)
 #pragma unroll
-        for (int o = 0; o < WIDTH; ++o) gx = __builtin_fmaf(sW[o * IN + k], din[o], gx);
-        sGx[vi][k] = gx;
-      }
+        for (int s = 0; s < 4; ++s)
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(c < IN ? Wg[(16 * to + 4 * s + g) * IN + c] : 0.f, db[to][s], d, 0,
+                                                   0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * g + r < IN) sGx[c][4 * g + r] = d[r];
     }
     __syncthreads();
-    if (q == 0 && act) {  // direction gradient for the chain to the centre
+    if (g == 0 && act) {  // direction gradient for the chain to the centre
       float* gv = a.gview + i * kGViewFloats;
-      gv[21] = sGx[vi][0];
-      gv[22] = sGx[vi][1];
-      gv[23] = sGx[vi][2];
+      gv[21] = sGx[c][0];
+      gv[22] = sGx[c][1];
+      gv[23] = sGx[c][2];
       if constexpr (IN == 14) {
         // ld = normalize(l - x_B): d loss / d x_B = -(g - ld (ld . g)) / |l - x_B|
         float ld[3], il2;
         light_dir(a, p, a.cams[v], ld, &il2);
-        const float g0 = sGx[vi][3], g1 = sGx[vi][4], g2 = sGx[vi][5];
+        const float g0 = sGx[c][3], g1 = sGx[c][4], g2 = sGx[c][5];
         const float dd = ld[0] * g0 + ld[1] * g1 + ld[2] * g2;
         gc0 -= (g0 - ld[0] * dd) * il2;
         gc1 -= (g1 - ld[1] * dd) * il2;
@@ -718,48 +763,70 @@ __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
       // live through the passes above
       int ln = lane;
       asm volatile("" : "+v"(ln));
-      const int g = ln >> 4, c = ln & 15;
-      // first layer: inputs as columns c < IN of one tile (tile loops not
-      // unrolled: one tile's operands live at a time)
-#pragma unroll 1
-      for (int t = 0; t < WIDTH / 16; ++t) {
-        v4f d = {0.f, 0.f, 0.f, 0.f};
+      const int gw = ln >> 4, cw = ln & 15;
+      // Per layer, the gradient entries are loaded first (all tiles at once,
+      // so that their latencies overlap), then the products are added.
+      // First layer: inputs as columns cw < IN of one tile.
+      {
+        float old[WIDTH / 16][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          d = __builtin_amdgcn_mfma_f32_16x16x4f32(sD[0][4 * s + g][16 * t + c], c < IN ? sX[4 * s + g][c] : 0.f, d,
-                                                   0, 0, 0);
-        if (c < IN) {
+        for (int t = 0; t < WIDTH / 16; ++t)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) G[(16 * t + 4 * g + r) * IN + c] += d[r];
+          for (int r = 0; r < 4; ++r) old[t][r] = cw < IN ? G[(16 * t + 4 * gw + r) * IN + cw] : 0.f;
+#pragma unroll
+        for (int t = 0; t < WIDTH / 16; ++t) {
+          v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(sD[0][4 * s + gw][16 * t + cw], cw < IN ? sX[4 * s + gw][cw] : 0.f,
+                                                     d, 0, 0, 0);
+          if (cw < IN) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G[(16 * t + 4 * gw + r) * IN + cw] = old[t][r] + d[r];
+          }
         }
       }
 #pragma unroll
       for (int l = 1; l < DEPTH; ++l) {
         const int off = IN * WIDTH + WIDTH + (l - 1) * (WIDTH * WIDTH + WIDTH);
-#pragma unroll 1
+        float old[WIDTH / 16][WIDTH / 16][4];
+#pragma unroll
         for (int t = 0; t < WIDTH / 16; ++t)
-#pragma unroll 1
+#pragma unroll
+          for (int t2 = 0; t2 < WIDTH / 16; ++t2)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) old[t][t2][r] = G[off + (16 * t + 4 * gw + r) * WIDTH + 16 * t2 + cw];
+#pragma unroll
+        for (int t = 0; t < WIDTH / 16; ++t)
+#pragma unroll
           for (int t2 = 0; t2 < WIDTH / 16; ++t2) {
             v4f d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-              d = __builtin_amdgcn_mfma_f32_16x16x4f32(sD[l][4 * s + g][16 * t + c], sH[l - 1][4 * s + g][16 * t2 + c],
+              d = __builtin_amdgcn_mfma_f32_16x16x4f32(sD[l][4 * s + gw][16 * t + cw], sH[l - 1][4 * s + gw][16 * t2 + cw],
                                                        d, 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) G[off + (16 * t + 4 * g + r) * WIDTH + 16 * t2 + c] += d[r];
+            for (int r = 0; r < 4; ++r) G[off + (16 * t + 4 * gw + r) * WIDTH + 16 * t2 + cw] = old[t][t2][r] + d[r];
           }
       }
       // output layer: rows 0..2 of one tile
-#pragma unroll 1
-      for (int t2 = 0; t2 < WIDTH / 16; ++t2) {
-        v4f d = {0.f, 0.f, 0.f, 0.f};
+      {
+        float old[WIDTH / 16][3];
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          d = __builtin_amdgcn_mfma_f32_16x16x4f32(c < 3 ? sDo[4 * s + g][c] : 0.f,
-                                                   sH[DEPTH - 1][4 * s + g][16 * t2 + c], d, 0, 0, 0);
-        if (g == 0) {
+        for (int t2 = 0; t2 < WIDTH / 16; ++t2)
 #pragma unroll
-          for (int r = 0; r < 3; ++r) G[LAST + r * WIDTH + 16 * t2 + c] += d[r];
+          for (int r = 0; r < 3; ++r) old[t2][r] = gw == 0 ? G[LAST + r * WIDTH + 16 * t2 + cw] : 0.f;
+#pragma unroll
+        for (int t2 = 0; t2 < WIDTH / 16; ++t2) {
+          v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            d = __builtin_amdgcn_mfma_f32_16x16x4f32(cw < 3 ? sDo[4 * s + gw][cw] : 0.f,
+                                                     sH[DEPTH - 1][4 * s + gw][16 * t2 + cw], d, 0, 0, 0);
+          if (gw == 0) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) G[LAST + r * WIDTH + 16 * t2 + cw] = old[t2][r] + d[r];
+          }
         }
       }
       // biases
