@@ -566,10 +566,10 @@ __global__ void __launch_bounds__(256) cmlp_fwd_mfma_kernel(CmlpArgs a) {
 // weights (operand A = W^T, the lanes along the rows of W: 64-byte runs);
 // the input gradient is one more such product.  The weights are read from
 // global memory (L1 and L2 after the first touch): an LDS copy would cost
-// more workgroups per CU than it saves.  Activations, deltas and inputs also go to LDS as [view][unit],
-// the operands of the weight gradients: products over the views, each entry
-// added to HBM by its one owning lane (no atomics).  Views culled for the
-// primitive carry zero deltas.
+// more workgroups per CU than it saves.  Activations, deltas and inputs also
+// go to LDS as [view][unit], the operands of the weight gradients: products
+// over the views, each entry added to HBM by its one owning lane (no
+// atomics).  Views culled for the primitive carry zero deltas.
 template <int WIDTH, int DEPTH, int IN>
 __global__ void __launch_bounds__(64) cmlp_bwd_kernel(CmlpArgs a) {
   constexpr int K = CmlpShape<WIDTH, DEPTH, IN>::K;
